@@ -1,0 +1,423 @@
+"""Pins for the FP64 oracle: each check compares the oracle with something
+other than itself -- hand-derived worked examples (tests/golden), brute
+force over all warping paths, closed forms, textbook special cases and
+invariants that the paper's definitions imply.  CPU only."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def walk(rng, T, D):
+    return np.cumsum(rng.standard_normal((T, D)), axis=0)
+
+
+# ------------------------------------------------------------------ DTW ---
+
+def brute_force_dtw(q, c, W):
+    """Minimum over every monotone path of steps (1,0), (0,1), (1,1) from
+    (0,0) to (m-1,n-1) inside |i-j| <= W of the summed squared point cost
+    (Sec. 2, Eq. 1 and the Sakoe-Chiba band), by explicit enumeration."""
+    m, n = len(q), len(c)
+    best = [np.inf]
+
+    def rec(i, j, acc):
+        if abs(i - j) > W:
+            return
+        acc = acc + float(np.sum((q[i] - c[j]) ** 2))
+        if (i, j) == (m - 1, n - 1):
+            best[0] = min(best[0], acc)
+            return
+        if i + 1 < m:
+            rec(i + 1, j, acc)
+        if j + 1 < n:
+            rec(i, j + 1, acc)
+        if i + 1 < m and j + 1 < n:
+            rec(i + 1, j + 1, acc)
+
+    rec(0, 0, 0.0)
+    return best[0]
+
+
+def test_dtw_brute_force_small():
+    rng = np.random.default_rng(11)
+    cases = 0
+    for m, n in itertools.product(range(1, 7), repeat=2):
+        for D in (1, 2, 3):
+            q, c = walk(rng, m, D), walk(rng, n, D)
+            for W in range(0, 6):
+                weff = O.window_eff(m, n, W)
+                assert weff == max(W, abs(m - n))
+                bf = brute_force_dtw(q, c, weff)
+                got = O.dtw(q, c, weff)
+                assert got == pytest.approx(bf, rel=1e-12, abs=1e-12), (m, n, D, W)
+                cases += 1
+    assert cases == 36 * 3 * 6
+
+
+def test_dtw_golden_hand_example():
+    g = gold("dtw_hand.json")
+    q, c = np.array(g["q"]), np.array(g["c"])
+    for W, v in g["dtw"].items():
+        assert O.dtw(q, c, int(W)) == v
+    val, gq, gc, path = O.path_grad(q, c, 1, 1.0)
+    assert val == g["dtw"]["1"]
+    assert path.tolist() == g["path_w1"]
+    assert gq.tolist() == g["grad_q_w1"]
+    assert gc.tolist() == g["grad_c_w1"]
+
+
+def textbook_dtw(q, c):
+    """Unconstrained O(mn) DTW with an explicit (m+1)x(n+1) table."""
+    m, n = len(q), len(c)
+    T = np.full((m + 1, n + 1), np.inf)
+    T[0, 0] = 0.0
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            cost = float(np.sum((q[i - 1] - c[j - 1]) ** 2))
+            T[i, j] = cost + min(T[i - 1, j], T[i, j - 1], T[i - 1, j - 1])
+    return T[m, n]
+
+
+def test_dtw_closed_forms_and_symmetry():
+    rng = np.random.default_rng(12)
+    for _ in range(40):
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 30))
+        D = int(rng.integers(1, 5))
+        q, c = walk(rng, m, D), walk(rng, n, D)
+        # identity
+        assert O.dtw(q, q, 3) == 0.0
+        # W = 0, equal lengths: the diagonal alone
+        if m == n:
+            assert O.dtw(q, c, 0) == pytest.approx(float(np.sum((q - c) ** 2)), rel=1e-12)
+        # full window = textbook unconstrained DTW
+        assert O.dtw(q, c, max(m, n)) == pytest.approx(textbook_dtw(q, c), rel=1e-12)
+        # symmetry
+        w = O.window_eff(m, n, int(rng.integers(0, 6)))
+        assert O.dtw(q, c, w) == pytest.approx(O.dtw(c, q, w), rel=1e-12)
+        # a wider band never increases the value
+        vals = [O.dtw(q, c, O.window_eff(m, n, W)) for W in range(0, 8)]
+        assert all(a >= b - 1e-9 * abs(a) for a, b in zip(vals, vals[1:]))
+
+
+def test_window_rule():
+    assert O.window_eff(256, 256, 0, 1, 10) == 25
+    assert O.window_eff(256, 256, 0, 1, 20) == 12
+    assert O.window_eff(256, 256, 0, 1, 5) == 51
+    assert O.window_eff(64, 64, 0, 1, 10) == 6
+    assert O.window_eff(1024, 1024, 0, 1, 10) == 102
+    assert O.window_eff(100, 300, 0, 1, 10) == 200   # |m-n| dominates
+    assert O.window_eff(100, 300, 7) == 200
+    assert O.window_eff(100, 100, 7) == 7
+
+
+def test_dtw_early_abandon_equivalence():
+    rng = np.random.default_rng(13)
+    for _ in range(50):
+        n = int(rng.integers(5, 40))
+        q, c = walk(rng, n, 3), walk(rng, n, 3)
+        w = int(rng.integers(0, 6))
+        d = O.dtw(q, c, w)
+        v, ab = O.dtw_ea(q, c, w, d * 1.5)
+        assert not ab and v == d
+        # below the value: either abandoned (+inf) or the full value is returned
+        v, ab = O.dtw_ea(q, c, w, d * 0.5)
+        assert (ab and v == np.inf) or (not ab and v == d)
+        # a threshold below the first row's minimum always abandons
+        v, ab = O.dtw_ea(q, c, w, 1e-300)
+        assert ab and v == np.inf
+        v, ab = O.dtw_ea(q, c, w, np.inf)
+        assert not ab and v == d
+
+
+# --------------------------------------------------------- lower bounds ---
+
+def test_lb_mv_golden():
+    g = gold("lb_mv_hand.json")
+    q, c, W = np.array(g["q"]), np.array(g["c"]), g["W"]
+    U, L = O.envelope(q, len(c), W)
+    assert U.tolist() == g["U"] and L.tolist() == g["L"]
+    assert O.lb_mv(q, c, W) == g["lb_mv"]
+    assert O.lb_ad(q, c, W) == g["lb_ad"]
+    assert O.dtw(q, c, W) == g["dtw"]
+
+
+def lb_keogh(q, c, W):
+    """Univariate LB_Keogh (Sec. 2): envelope max/min over q[i-W .. i+W],
+    squared distance of each candidate point outside it."""
+    n = len(c)
+    s = 0.0
+    for i in range(n):
+        seg = q[max(0, i - W): min(len(q), i + W + 1)]
+        u, l = seg.max(), seg.min()
+        if c[i] > u:
+            s += (c[i] - u) ** 2
+        elif c[i] < l:
+            s += (l - c[i]) ** 2
+    return s
+
+
+def test_lb_mv_univariate_is_lb_keogh():
+    rng = np.random.default_rng(14)
+    for _ in range(50):
+        n = int(rng.integers(2, 60))
+        W = int(rng.integers(0, 10))
+        q, c = walk(rng, n, 1)[:, 0], walk(rng, n, 1)[:, 0]
+        assert O.lb_mv(q[:, None], c[:, None], W) == pytest.approx(lb_keogh(q, c, W), rel=1e-12, abs=1e-12)
+
+
+def test_lb_ti_golden():
+    g = gold("lb_ti_hand.json")
+    for ex, keys in (("A", ("P0_top0", "P0_top1")), ("B", ("P0_top0",))):
+        e = g[ex]
+        q, c, W = np.array(e["q"]), np.array(e["c"]), e["W"]
+        for key in keys:
+            top = 1 if key.endswith("top1") else 0
+            Lo, Hi = O.ti_cells(q, c, W, P=0, top=top)
+            exp_lo = np.array([[np.nan if v is None else v for v in r] for r in e[key]["Lo"]])
+            exp_hi = np.array([[np.nan if v is None else v for v in r] for r in e[key]["Hi"]])
+            np.testing.assert_array_equal(Lo, exp_lo)
+            np.testing.assert_array_equal(Hi, exp_hi)
+            assert O.lb_ti(q, c, W, P=0, top=top) == e[key]["lb"]
+    A = g["A"]
+    q, c = np.array(A["q"]), np.array(A["c"])
+    assert O.lb_ti(q, c, 1, P=2, top=0) == A["P2_top0"]["lb"]
+    assert O.lb_ti(q, c, 1, P=1, top=0) == A["lb_ad"]
+    assert O.lb_ad(q, c, 1) == A["lb_ad"]
+    assert O.dtw(q, c, 1) == A["dtw"]
+
+
+def test_lb_pc_golden():
+    g = gold("lb_pc_hand.json")
+    W, w, Lv = g["W"], g["w"], g["Lv"]
+    for ex, Ks in (("A", (2, 1)), ("B", (2, 3, 1)), ("C", (3, 4))):
+        e = g[ex]
+        q, c = np.array(e["q"], dtype=float), np.array(e["c"], dtype=float)
+        for K in Ks:
+            exp = e["K%d" % K]
+            assert O.lb_pc(q, c, W, Lv=Lv, K=K, w=w) == exp["lb"], (ex, K)
+            if "nbox" in exp:
+                lo, hi, nb = O.pc_boxes(q, len(c), W, Lv=Lv, K=K, w=w)
+                assert nb.tolist() == [exp["nbox"]]
+                assert lo[0, :exp["nbox"]].tolist() == exp["lo"]
+                assert hi[0, :exp["nbox"]].tolist() == exp["hi"]
+    A = g["A"]
+    q, c = np.array(A["q"], dtype=float), np.array(A["c"], dtype=float)
+    assert O.lb_mv(q, c, W) == A["lb_mv"]
+    assert O.lb_ad(q, c, W) == A["lb_ad"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bounds_below_dtw_and_lb_ad(seed):
+    """Every bound <= its LB_AD <= DTW on random pairs, unequal lengths included."""
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(60):
+        D = int(rng.integers(1, 6))
+        m = int(rng.integers(1, 40))
+        n = int(rng.integers(1, 40))
+        q, c = walk(rng, m, D), walk(rng, n, D)
+        if rng.random() < 0.3:
+            c = q[rng.integers(0, m, size=n)] + 0.1 * rng.standard_normal((n, D))
+        weff = O.window_eff(m, n, int(rng.integers(0, 8)))
+        d = O.dtw(q, c, weff)
+        ad = O.lb_ad(q, c, weff)
+        tol = 1e-9 * max(1.0, d)
+        assert ad <= d + tol
+        assert O.lb_mv(q, c, weff) <= ad + tol
+        for P, top in ((5, 1), (0, 0), (0, 1), (3, 0), (1, 0)):
+            assert O.lb_ti(q, c, weff, P, top) <= ad + tol
+        for Lv, K, w in ((2, 6, 6), (3, 6, 6), (2, 1, 1), (3, 4, 3), (2, 16, 6)):
+            assert O.lb_pc(q, c, weff, Lv, K, w) <= ad + tol
+
+
+def test_ti_cells_bracket_true_distance():
+    rng = np.random.default_rng(15)
+    for _ in range(40):
+        D = int(rng.integers(1, 6))
+        m = int(rng.integers(2, 30))
+        n = int(rng.integers(2, 30))
+        q, c = walk(rng, m, D), walk(rng, n, D)
+        weff = O.window_eff(m, n, int(rng.integers(0, 6)))
+        E = np.sqrt(((q[:, None, :] - c[None, :, :]) ** 2).sum(-1))
+        band = np.abs(np.arange(m)[:, None] - np.arange(n)[None, :]) <= weff
+        for P, top in ((5, 1), (0, 0), (0, 1), (2, 0)):
+            Lo, Hi = O.ti_cells(q, c, weff, P, top)
+            assert np.all(np.isnan(Lo[~band])) and not np.any(np.isnan(Lo[band]))
+            assert np.all(Lo[band] <= E[band] + 1e-9)
+            assert np.all(Hi[band] >= E[band] - 1e-9)
+            if P == 1 or (P == 5 and True):
+                rows = np.arange(m) % P == 0 if P > 0 else np.arange(m) == 0
+                exact = band & rows[:, None]
+                np.testing.assert_allclose(Lo[exact], E[exact], rtol=1e-12, atol=1e-12)
+
+
+def test_lb_ti_special_cases():
+    rng = np.random.default_rng(16)
+    for _ in range(40):
+        D = int(rng.integers(1, 5))
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(1, 40))
+        q, c = walk(rng, m, D), walk(rng, n, D)
+        weff = O.window_eff(m, n, int(rng.integers(0, 6)))
+        # every row exact -> LB_TI is LB_AD
+        assert O.lb_ti(q, c, weff, P=1, top=0) == pytest.approx(O.lb_ad(q, c, weff), rel=1e-12)
+        if m == n:
+            c2 = walk(rng, m, D)
+            # W = 0: LB_TI = LB_AD = DTW_0
+            a = O.lb_ti(q, c2, 0, P=0, top=0)
+            assert a == pytest.approx(O.lb_ad(q, c2, 0), rel=1e-12)
+            assert a == pytest.approx(O.dtw(q, c2, 0), rel=1e-12)
+
+
+def test_lb_pc_special_cases():
+    rng = np.random.default_rng(17)
+    for _ in range(60):
+        D = int(rng.integers(1, 4))
+        n = int(rng.integers(1, 30))
+        m = int(rng.integers(1, 30))
+        q, c = rng.standard_normal((m, D)), rng.standard_normal((n, D))
+        weff = O.window_eff(m, n, int(rng.integers(0, 5)))
+        mv = O.lb_mv(q, c, weff)
+        # one box per single-position group: the LB_MV envelope itself
+        assert O.lb_pc(q, c, weff, Lv=2, K=1, w=1) == pytest.approx(mv, rel=1e-12, abs=1e-12)
+        # single-position groups with boxes no bigger than the envelope
+        assert O.lb_pc(q, c, weff, Lv=3, K=6, w=1) >= mv - 1e-12
+        # one point per cell (fine grid, K >= window size): every box is a point -> LB_AD
+        K = 2 * weff + 1
+        assert O.lb_pc(q, c, weff, Lv=100000, K=K, w=1, floor_len=1e-30) == pytest.approx(
+            O.lb_ad(q, c, weff), rel=1e-12, abs=1e-12)
+
+
+def test_pc_boxes_cover_window_points():
+    rng = np.random.default_rng(18)
+    for _ in range(30):
+        D = int(rng.integers(1, 6))
+        n = int(rng.integers(3, 50))
+        q = walk(rng, n, D)
+        W = int(rng.integers(0, 8))
+        K = int(rng.integers(1, 8))
+        w = int(rng.integers(1, 8))
+        lo, hi, nb = O.pc_boxes(q, n, W, Lv=3, K=K, w=w)
+        for g in range(len(nb)):
+            assert 1 <= nb[g] <= K
+            i0 = max(0, g * w - W)
+            i1 = min(n - 1, min(n - 1, g * w + w - 1) + W)
+            pts = q[i0:i1 + 1]
+            inside = np.zeros(len(pts), dtype=bool)
+            for b in range(nb[g]):
+                inside |= np.all((pts >= lo[g, b]) & (pts <= hi[g, b]), axis=1)
+                # each box is tight: its corners are attained by member points
+                assert np.all(lo[g, b] <= hi[g, b])
+            assert inside.all()
+
+
+# ----------------------------------------------------------------- 1-NN ---
+
+def test_knn_exhaustive_matches_brute_force():
+    rng = np.random.default_rng(19)
+    Q = [walk(rng, int(rng.integers(2, 6)), 2) for _ in range(5)]
+    Cs = [walk(rng, int(rng.integers(2, 6)), 2) for _ in range(12)]
+    Cs.append(Cs[3].copy())          # an exact duplicate: ties go to the lower index
+    Q.append(Cs[3] + 0.0)
+    idx, dist = O.knn_exhaustive(Q, Cs, window=1)
+    for a, q in enumerate(Q):
+        vals = [brute_force_dtw(q, c, max(1, abs(len(q) - len(c)))) for c in Cs]
+        assert idx[a] == int(np.argmin(vals))
+        assert dist[a] == pytest.approx(min(vals), rel=1e-12)
+    assert idx[-1] == 3 and dist[-1] == 0.0
+
+
+@pytest.mark.parametrize("bounds", [0, 2, 4, 6])
+def test_cascade_equals_exhaustive(bounds):
+    """The filtering cascade returns exactly the plain 1-NN (Sec. 7.2, soundness)."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn(nq=6, nc=120, T=48, D=4, seed=7)
+    Cs = np.concatenate([Cs, Cs[:5]])      # duplicates force exact ties
+    for (num, den) in ((1, 10), (1, 5)):
+        i0, d0 = O.knn_exhaustive(Q, Cs, num=num, den=den)
+        for e in (0.0, 0.1, 0.5):
+            i1, d1, st = O.knn_cascade(Q, Cs, num=num, den=den, bounds=bounds, e_ti=e, e_pc=e)
+            np.testing.assert_array_equal(i0, i1)
+            np.testing.assert_array_equal(d0, d1)
+            assert np.all(st["pairs"] == len(Cs))
+            assert np.all(st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == len(Cs))
+            if bounds == 0:
+                assert np.all(st["pruned_pc"] + st["pruned_ti"] == 0)
+
+
+def test_cascade_ragged_equals_exhaustive():
+    rng = np.random.default_rng(20)
+    Q = [walk(rng, int(rng.integers(8, 40)), 3) for _ in range(4)]
+    Cs = [walk(rng, int(rng.integers(8, 40)), 3) for _ in range(60)]
+    i0, d0 = O.knn_exhaustive(Q, Cs, num=1, den=10)
+    i1, d1, _ = O.knn_cascade(Q, Cs, num=1, den=10, bounds=6, e_ti=0.05, e_pc=0.1)
+    np.testing.assert_array_equal(i0, i1)
+    np.testing.assert_array_equal(d0, d1)
+
+
+# -------------------------------------------------------------- backward ---
+
+def test_path_gradient_vs_central_differences():
+    """DTW is quadratic in the inputs along a fixed path, so central
+    differences match the path gradient to rounding when the optimal path
+    does not change within +-h (tie-free jittered walks)."""
+    from paper_2101_07731_amd import synth
+    x, y = synth.loss_pairs(npairs=8, T=32, D=12, seed=5)
+    h = 1e-6
+    for k in range(8):
+        q = x[k].astype(np.float64)
+        c = y[k].astype(np.float64)
+        weff = O.window_eff(32, 32, 0, 1, 10)
+        assert weff == 3
+        v, gq, gc, path = O.path_grad(q, c, weff, 1.0)
+        for arr, g in ((q, gq), (c, gc)):
+            fd = np.zeros_like(arr)
+            for idx in np.ndindex(arr.shape):
+                a0 = arr[idx]
+                arr[idx] = a0 + h
+                fp = O.dtw(q, c, weff)
+                arr[idx] = a0 - h
+                fm = O.dtw(q, c, weff)
+                arr[idx] = a0
+                fd[idx] = (fp - fm) / (2 * h)
+            np.testing.assert_allclose(fd, g, rtol=1e-6, atol=1e-5 * max(1.0, np.abs(g).max()) * 1e-1)
+
+
+def test_path_gradient_invariants():
+    rng = np.random.default_rng(21)
+    for _ in range(30):
+        D = int(rng.integers(1, 5))
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 30))
+        q, c = walk(rng, m, D), walk(rng, n, D)
+        weff = O.window_eff(m, n, int(rng.integers(0, 6)))
+        gbar = float(rng.uniform(0.5, 2.0))
+        v, gq, gc, path = O.path_grad(q, c, weff, gbar)
+        assert v == pytest.approx(O.dtw(q, c, weff), rel=1e-12)
+        # path: from the end cell back to (0,0), unit monotone steps inside the band
+        assert tuple(path[0]) == (m - 1, n - 1) and tuple(path[-1]) == (0, 0)
+        steps = path[:-1] - path[1:]
+        assert all(tuple(s) in ((1, 0), (0, 1), (1, 1)) for s in steps)
+        assert np.all(np.abs(path[:, 0] - path[:, 1]) <= weff)
+        # its summed cost is the DTW value
+        pc = sum(float(np.sum((q[i] - c[j]) ** 2)) for i, j in path)
+        assert pc == pytest.approx(v, rel=1e-12)
+        # translation invariance: sum of all gradients is zero per dimension
+        np.testing.assert_allclose(gq.sum(0) + gc.sum(0), 0.0, atol=1e-9 * max(1.0, v))
+        # degree-2 homogeneity (Euler): <q, gq> + <c, gc> = 2 gbar DTW
+        assert float((q * gq).sum() + (c * gc).sum()) == pytest.approx(2 * gbar * v, rel=1e-9, abs=1e-9)
+    q = walk(rng, 20, 3)
+    v, gq, gc, _ = O.path_grad(q, q.copy(), 2, 1.0)
+    assert v == 0.0 and not gq.any() and not gc.any()
