@@ -1,0 +1,73 @@
+"""ctypes view of the C ABI in include/tc_dtw.h (argument marshalling only).
+
+The shared library libtcdtw.so sits next to this file (built by
+csrc/build.py).  Loading fails loudly when it is missing: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtcdtw.so")
+
+OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
+F64 = 1
+
+
+class TcDtwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("tc_dtw status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Batch(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("offset", C.POINTER(C.c_int64)),
+                ("len", C.POINTER(C.c_int32)), ("count", C.c_int32), ("dim", C.c_int32),
+                ("uniform_len", C.c_int32)]
+
+
+class Window(C.Structure):
+    _fields_ = [("window", C.c_int32), ("frac_num", C.c_int32), ("frac_den", C.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "tc_dtw_abi_version": (C.c_int, []),
+    "tc_dtw_last_error": (C.c_char_p, []),
+    "tc_dtw_status_string": (C.c_char_p, [C.c_int]),
+    "tc_dtw_banded_workspace_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_uint32]),
+    "tc_dtw_saved_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
+    "tc_dtw_banded": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_uint32, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tc_dtw_backward_workspace_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
+    "tc_dtw_backward": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+}
+
+
+def lib():
+    """Load libtcdtw.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtcdtw.so is not built (run __graft_entry__.build() or "
+                          "python paper_2101_07731_amd/csrc/build.py): " + LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    if L.tc_dtw_abi_version() != 1:
+        raise ImportError("libtcdtw.so ABI version mismatch")
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != OK:
+        raise TcDtwError(status, lib().tc_dtw_last_error().decode())

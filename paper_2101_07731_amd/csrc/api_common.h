@@ -1,0 +1,53 @@
+// Host-side helpers of the C ABI: error reporting, argument checks, the
+// device check and workspace carving.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tc_dtw.h"
+#include "internal.h"
+
+namespace tcdtw {
+
+tc_dtw_status fail(tc_dtw_status st, const std::string& msg);
+tc_dtw_status ok();
+tc_dtw_status hip_fail(hipError_t e, const char* what);
+// 0 if the current device is a gfx950, else an error status with a message.
+tc_dtw_status check_device();
+
+// Host view of a batch: lengths and float offsets of every series.
+struct HostSet {
+    int count = 0, dim = 0;
+    bool uniform = false;
+    int ulen = 0;
+    int maxlen = 0;
+    const float* data = nullptr;
+    std::vector<int32_t> len;
+    std::vector<int64_t> off;
+    int length(int s) const { return uniform ? ulen : len[s]; }
+    int64_t offset(int s) const { return uniform ? (int64_t)s * ulen * dim : off[s]; }
+};
+
+// Validates a batch and fills `out`; `what` names it in messages.
+tc_dtw_status read_set(const tc_dtw_batch* b, const char* what, HostSet& out);
+tc_dtw_status check_window(tc_dtw_window w);
+int window_eff(int m, int n, tc_dtw_window w);
+
+// Bump allocator over a caller workspace (256-byte aligned pieces).
+struct Carve {
+    char* base;
+    size_t used = 0;
+    size_t cap;
+    explicit Carve(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+    template <typename T> T* take(size_t count) {
+        used = (used + 255) & ~(size_t)255;
+        T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+        used += count * sizeof(T);
+        return p;
+    }
+    size_t need() const { return (used + 255) & ~(size_t)255; }
+};
+
+}  // namespace tcdtw

@@ -1,0 +1,85 @@
+// Device-side helpers shared by the gfx950 kernels of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcdtw {
+
+template <typename T> __device__ __forceinline__ T inf_v();
+template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_inff(); }
+template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_inf(); }
+
+// DPP control codes (GFX9 family): whole-wave shift by one lane.
+constexpr int kWaveShr1 = 0x138;  // lane l receives lane l-1
+constexpr int kWaveShl1 = 0x130;  // lane l receives lane l+1
+
+// Lanes without a source lane keep `old`.
+__device__ __forceinline__ float wave_shr1(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), kWaveShr1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_shl1(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), kWaveShl1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double wave_shr1(double old, double v) {
+    int2 o = __builtin_bit_cast(int2, old), x = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(o.x, x.x, kWaveShr1, 0xF, 0xF, false);
+    r.y = __builtin_amdgcn_update_dpp(o.y, x.y, kWaveShr1, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double wave_shl1(double old, double v) {
+    int2 o = __builtin_bit_cast(int2, old), x = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(o.x, x.x, kWaveShl1, 0xF, 0xF, false);
+    r.y = __builtin_amdgcn_update_dpp(o.y, x.y, kWaveShl1, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+template <typename T> __device__ __forceinline__ T vmin3(T a, T b, T c) { return vmin(vmin(a, b), c); }
+
+// Squared Euclidean point cost over NCH chunks of 4 dimensions.  Padded
+// dimensions hold 0 in both operands (or +-inf in sentinel points) and
+// add nothing.  float: fused multiply-add chain.
+template <int NCH>
+__device__ __forceinline__ float point_cost(const float4 (&q)[NCH], const float4 (&c)[NCH], float) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        float d0 = q[k].x - c[k].x, d1 = q[k].y - c[k].y, d2 = q[k].z - c[k].z, d3 = q[k].w - c[k].w;
+        acc = __builtin_fmaf(d0, d0, acc);
+        acc = __builtin_fmaf(d1, d1, acc);
+        acc = __builtin_fmaf(d2, d2, acc);
+        acc = __builtin_fmaf(d3, d3, acc);
+    }
+    return acc;
+}
+
+// double: every difference, square and sum rounded separately, dimensions
+// in increasing order (reproduces a plain FP64 evaluation exactly; the
+// zero terms of padded dimensions leave the sum unchanged).
+template <int NCH>
+__device__ __forceinline__ double point_cost(const float4 (&q)[NCH], const float4 (&c)[NCH], double) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        double d;
+        d = (double)q[k].x - (double)c[k].x; acc = acc + d * d;
+        d = (double)q[k].y - (double)c[k].y; acc = acc + d * d;
+        d = (double)q[k].z - (double)c[k].z; acc = acc + d * d;
+        d = (double)q[k].w - (double)c[k].w; acc = acc + d * d;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ float add_cost(float cost, float best) { return cost + best; }
+__device__ __forceinline__ double add_cost(double cost, double best) {
+#pragma clang fp contract(off)
+    return cost + best;
+}
+
+}  // namespace tcdtw

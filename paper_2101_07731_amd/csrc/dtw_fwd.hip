@@ -1,0 +1,402 @@
+// Banded DTW forward kernels for gfx950 (Sec. 2, Eq. 1 within the
+// Sakoe-Chiba band |i-j| <= W_eff).
+//
+// Two mappings of the band onto a 64-lane wave; both evaluate the
+// recurrence along anti-diagonals, one cell per lane per step, with
+// neighbour values passed between lanes by DPP whole-wave shifts:
+//
+//  * diagonal pairs (W_eff <= 63): the band's 2 W_eff + 1 diagonals plus one
+//    padding diagonal are split two per lane, W_eff + 1 lanes per pair, and
+//    64 / (W_eff + 1) pairs share a wave.  At anti-diagonal s only the
+//    diagonals with the parity of s are live, so each lane alternates
+//    between its two diagonals (an "E" step for the even slot, an "O" step
+//    for the odd one); the three live anti-diagonals are the lane's two
+//    slot registers plus one neighbour value.  Each lane walks its two
+//    diagonals one round (two cells) at a time and loads one new query
+//    point and one new candidate point per round from LDS.
+//  * row-systolic blocks (any W_eff, used above 63): lane l owns row
+//    i0 + l of a block of 64 rows and sweeps the block's band columns; the
+//    last row of a block is kept in an LDS row buffer for the next block.
+//
+// Series are staged in LDS as [chunk][t][4] floats (conflict-free 16-byte
+// reads) with sentinel points outside the series: +inf on the query side,
+// -inf on the candidate side, so a cell outside the matrix has cost +inf
+// and no edge test is needed.  The single padding diagonal of each pair is
+// forced to +inf.
+//
+// The virtual predecessor of (0,0) is a 0 placed on the slot of diagonal 0
+// one round before the start.
+#include "device_common.h"
+#include "internal.h"
+
+namespace tcdtw {
+
+// ---------------------------------------------------------------------------
+// Diagonal-pair mapping.
+//
+// With off = W + (W & 1) (even) lane l of a group owns the band offsets
+// delta = 2l - off (even slot) and 2l + 1 - off (odd slot), so even slots are
+// live at even anti-diagonals.  In round r the even slot holds cell
+// (r + h - l, r - h + l) and the odd slot (r + h - l, r - h + l + 1),
+// h = off / 2.  The padding diagonal is the top odd slot when W is even
+// (delta = W + 1) and the bottom even slot when W is odd (delta = -W - 1).
+// ---------------------------------------------------------------------------
+
+struct DiagGeom {
+    int m, n, W, G, h, R, LQ, LC;
+    __host__ __device__ void init(int m_, int n_, int W_) {
+        m = m_; n = n_; W = W_;
+        G = W + 1;
+        h = (W + (W & 1)) / 2;
+        R = (m + n) / 2;           // rounds: anti-diagonals 0 .. m+n-2
+        LQ = R + W + 1;            // query positions, index i = pos + h - W
+        LC = R + W + 2;            // candidate positions, index j = pos - h
+    }
+};
+
+size_t diag_lds_bytes(int m, int n, int W, int D, int P) {
+    DiagGeom g;
+    g.init(m, n, W);
+    return (size_t)P * (size_t)(g.LQ + g.LC) * (size_t)nch_pad(D) * 16;
+}
+
+template <typename T, int NCH, bool SAVE, bool WODD>
+__global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
+    extern __shared__ float4 smem[];
+    const int lane = threadIdx.x;
+    const int D = a.D;
+
+    int m, n, W, P;
+    int64_t xoff0 = 0, yoff0 = 0, soff0 = 0;
+    int out0;
+    if (a.uniform) {
+        m = a.m; n = a.n; W = a.W; P = a.P;
+        out0 = blockIdx.x * P;
+    } else {
+        const PairDesc d = a.desc[blockIdx.x];
+        m = d.m; n = d.n; W = d.W; P = 1;
+        xoff0 = d.xoff; yoff0 = d.yoff; soff0 = d.saved_off; out0 = d.out;
+    }
+    DiagGeom g;
+    g.init(m, n, W);
+    const int G = g.G, h = g.h, R = g.R, LQ = g.LQ, LC = g.LC;
+    const int per_pair = (LQ + LC) * NCH;   // float4 per staged pair
+
+    // --- stage the wave's pairs -------------------------------------------
+    int npair_here = P;
+    if (a.uniform) npair_here = min(P, a.npairs - out0);
+    for (int gg = 0; gg < npair_here; ++gg) {
+        const float* xs;
+        const float* ys;
+        if (a.uniform) {
+            xs = a.x + (int64_t)(out0 + gg) * m * D;
+            ys = a.y + (int64_t)(out0 + gg) * n * D;
+        } else {
+            xs = a.x + xoff0;
+            ys = a.y + yoff0;
+        }
+        float4* sq = smem + gg * per_pair;
+        float4* sc = sq + LQ * NCH;
+        for (int pos = lane; pos < LQ; pos += kWave) {
+            const int i = pos + h - W;
+            const bool in = (i >= 0 && i < m);
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int p = 4 * k + e;
+                    v[e] = in ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
+                }
+                sq[k * LQ + pos] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+        for (int pos = lane; pos < LC; pos += kWave) {
+            const int j = pos - h;
+            const bool in = (j >= 0 && j < n);
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int p = 4 * k + e;
+                    v[e] = in ? (p < D ? ys[(int64_t)j * D + p] : 0.0f) : -__builtin_inff();
+                }
+                sc[k * LC + pos] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // --- lane roles ----------------------------------------------------------
+    const int grp = lane / G;
+    const int lg = lane - grp * G;
+    const bool spare = grp >= npair_here;          // lanes without a pair
+    const int gsrc = spare ? 0 : grp;              // spare lanes read group 0's data
+    // the padding diagonal (and spare lanes) are forced to +inf
+    const bool kill_e = WODD && (lg == 0 || spare);
+    const bool kill_o = !WODD && (lg == G - 1);
+
+    const float4* qb = smem + gsrc * per_pair + (W - lg);       // + k*LQ + r
+    const float4* cb = smem + gsrc * per_pair + LQ * NCH + lg;  // + k*LC + r (E), r+1 (O)
+
+    const T INF = inf_v<T>();
+    T vE = INF, vO = INF;
+    if (!spare && lg == h) vE = T(0);              // virtual D(-1,-1)
+
+    float4 qv[NCH], cE[NCH], cO[NCH];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) cE[k] = cb[k * LC + 0];
+
+    uint32_t cw = 0;
+    uint32_t* codes = nullptr;
+    if (SAVE) {
+        const int64_t base = a.uniform ? (int64_t)(out0 + (spare ? 0 : grp)) * a.codes_stride : soff0;
+        codes = a.codes + base;
+    }
+
+
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            qv[k] = qb[k * LQ + r];
+            cO[k] = cb[k * LC + r + 1];
+        }
+        // E step: anti-diagonal 2r, even slot.  up = own odd slot, left = lane-1's odd slot.
+        {
+            const T cost = point_cost<NCH>(qv, cE, T(0));
+            const T up = vO;
+            const T left = wave_shr1(INF, vO);
+            const T diag = vE;
+            T best;
+            if (SAVE) {
+                uint32_t code = 0;
+                best = diag;
+                if (up < best) { best = up; code = 1; }
+                if (left < best) { best = left; code = 2; }
+                cw |= code << ((r & 7) * 4);
+            } else {
+                best = vmin3(diag, up, left);
+            }
+            T v = add_cost(cost, best);
+            if (kill_e) v = INF;
+            vE = v;
+        }
+        // O step: anti-diagonal 2r+1, odd slot.  up = lane+1's even slot, left = own even slot.
+        {
+            const T cost = point_cost<NCH>(qv, cO, T(0));
+            const T up = wave_shl1(INF, vE);
+            const T left = vE;
+            const T diag = vO;
+            T best;
+            if (SAVE) {
+                uint32_t code = 0;
+                best = diag;
+                if (up < best) { best = up; code = 1; }
+                if (left < best) { best = left; code = 2; }
+                cw |= code << ((r & 7) * 4 + 2);
+            } else {
+                best = vmin3(diag, up, left);
+            }
+            T v = add_cost(cost, best);
+            if (kill_o) v = INF;
+            vO = v;
+        }
+        if (SAVE && ((r & 7) == 7 || r == R - 1)) {
+            if (!spare) codes[(int64_t)(r >> 3) * G + lg] = cw;
+            cw = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) cE[k] = cO[k];
+    }
+
+    // --- result: cell (m-1, n-1) on diagonal n-m ------------------------------
+    const int sigma = (n - m) + 2 * h;
+    if (!spare && lg == (sigma >> 1)) {
+        const T v = (sigma & 1) ? vO : vE;
+        const int out = a.uniform ? out0 + grp : out0;
+        a.dist[out] = (float)v;
+        if (a.dist64) a.dist64[out] = (double)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row-systolic mapping: one pair per wave.  Block b holds rows
+// i0 = 64 b .. i0 + 63; lane l owns row i0 + l and at step t evaluates
+// column j = jlo + t - l.  up = lane l-1's previous value (lane 0: the
+// row buffer), diag = the up value of the previous step, left = own
+// previous value.  Lane 63 writes its row into the row buffer 63 columns
+// behind lane 0's reads, so one buffer serves both.
+// ---------------------------------------------------------------------------
+
+constexpr int kRowPad = 65;   // candidate / row-buffer positions left of column 0
+
+size_t rows_lds_bytes(int n, int W, int D, bool f64) {
+    (void)W;
+    const size_t LC = (size_t)n + 2 * kRowPad;
+    return LC * (size_t)nch_pad(D) * 16 + LC * (f64 ? 8 : 4);
+}
+
+template <typename T, int NCH, bool SAVE>
+__global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
+    extern __shared__ float4 smem[];
+    const int lane = threadIdx.x;
+    const int D = a.D;
+    int m, n, W, out;
+    int64_t xoff, yoff, soff;
+    if (a.uniform) {
+        m = a.m; n = a.n; W = a.W;
+        out = blockIdx.x;
+        xoff = (int64_t)out * m * D; yoff = (int64_t)out * n * D;
+        soff = (int64_t)out * a.codes_stride;
+    } else {
+        const PairDesc d = a.desc[blockIdx.x];
+        m = d.m; n = d.n; W = d.W; out = d.out;
+        xoff = d.xoff; yoff = d.yoff; soff = d.saved_off;
+    }
+    const float* xs = a.x + xoff;
+    const float* ys = a.y + yoff;
+    const int LC = n + 2 * kRowPad;
+    float4* sc = smem;                                   // [k][LC], position = j + kRowPad
+    T* rowbuf = reinterpret_cast<T*>(smem + (size_t)LC * NCH);  // [LC], position = j + kRowPad
+    const T INF = inf_v<T>();
+
+    for (int pos = lane; pos < LC; pos += kWave) {
+        const int j = pos - kRowPad;
+        const bool in = (j >= 0 && j < n);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = 4 * k + e;
+                v[e] = in ? (p < D ? ys[(int64_t)j * D + p] : 0.0f) : -__builtin_inff();
+            }
+            sc[k * LC + pos] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        rowbuf[pos] = (j == -1) ? T(0) : INF;            // row -1: only the virtual D(-1,-1)
+    }
+    __syncthreads();
+
+    const int nb = (m + kRowBlock - 1) / kRowBlock;
+    const int tmax = min(n, 2 * W + kRowBlock) + kRowBlock - 1;
+    const int nwb = (tmax + 15) / 16;
+    T result = INF;
+
+    for (int b = 0; b < nb; ++b) {
+        const int i0 = b * kRowBlock;
+        const int i = i0 + lane;
+        float4 qv[NCH];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = 4 * k + e;
+                v[e] = (i < m) ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
+            }
+            qv[k] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        const int jlo = max(0, i0 - W);
+        const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
+        const int T_b = jhi - jlo + kRowBlock;
+        const int k0 = jlo - i0 + W - 2 * lane;          // band offset k = t + k0 must lie in [0, 2W]
+        const float4* cl = sc + (jlo - lane + kRowPad);  // + k*LC + t
+        const T* rb = rowbuf + (jlo + kRowPad);          // + t
+        T* wb = rowbuf + (jlo - (kRowBlock - 1) + kRowPad);  // lane 63 writes + t
+        T cur = INF;
+        T prevup = (lane == 0) ? rowbuf[jlo - 1 + kRowPad] : INF;
+        const bool last = (b == nb - 1);
+        const int tend = (n - 1) - jlo + (m - 1 - i0);    // step at which lane m-1-i0 reaches column n-1
+        uint32_t cw = 0;
+        uint32_t* codes = SAVE ? a.codes + soff + (int64_t)b * nwb * kWave + lane : nullptr;
+
+
+        for (int t = 0; t < T_b; ++t) {
+            float4 cv[NCH];
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) cv[k] = cl[k * LC + t];
+            const T up = wave_shr1(rb[t], cur);
+            const T diag = prevup;
+            prevup = up;
+            const T left = cur;
+            const T cost = point_cost<NCH>(qv, cv, T(0));
+            T best;
+            if (SAVE) {
+                uint32_t code = 0;
+                best = diag;
+                if (up < best) { best = up; code = 1; }
+                if (left < best) { best = left; code = 2; }
+                cw |= code << ((t & 15) * 2);
+                if ((t & 15) == 15 || t == T_b - 1) {
+                    codes[(int64_t)(t >> 4) * kWave] = cw;
+                    cw = 0;
+                }
+            } else {
+                best = vmin3(diag, up, left);
+            }
+            T v = add_cost(cost, best);
+            const unsigned kb = (unsigned)(t + k0);
+            v = (kb <= (unsigned)(2 * W)) ? v : INF;
+            cur = v;
+            if (lane == kRowBlock - 1) wb[t] = v;
+            if (last && t == tend && lane == m - 1 - i0) result = v;
+        }
+        __syncthreads();
+    }
+    if (lane == (m - 1) % kRowBlock) {
+        a.dist[out] = (float)result;
+        if (a.dist64) a.dist64[out] = (double)result;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch: the mapping is chosen by the largest W_eff of the launch.
+// ---------------------------------------------------------------------------
+
+template <typename T, int NCH, bool SAVE>
+static hipError_t launch_nch(const DtwFwdArgs& a, int maxW, int nitems, size_t lds, hipStream_t s) {
+    if (maxW <= kDiagMaxW) {
+        // every item of a launch shares the parity of W (a ragged caller splits by parity)
+        if (a.wodd) {
+            hipLaunchKernelGGL((dtw_diag_kernel<T, NCH, SAVE, true>), dim3(nitems), dim3(64), lds, s, a);
+        } else {
+            hipLaunchKernelGGL((dtw_diag_kernel<T, NCH, SAVE, false>), dim3(nitems), dim3(64), lds, s, a);
+        }
+    } else {
+        hipLaunchKernelGGL((dtw_rows_kernel<T, NCH, SAVE>), dim3(nitems), dim3(64), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool SAVE>
+static hipError_t launch_t(const DtwFwdArgs& a, int maxW, int nitems, size_t lds, hipStream_t s) {
+    switch (nch_pad(a.D)) {
+        case 1: return launch_nch<T, 1, SAVE>(a, maxW, nitems, lds, s);
+        case 2: return launch_nch<T, 2, SAVE>(a, maxW, nitems, lds, s);
+        case 3: return launch_nch<T, 3, SAVE>(a, maxW, nitems, lds, s);
+        case 4: return launch_nch<T, 4, SAVE>(a, maxW, nitems, lds, s);
+        case 6: return launch_nch<T, 6, SAVE>(a, maxW, nitems, lds, s);
+        case 8: return launch_nch<T, 8, SAVE>(a, maxW, nitems, lds, s);
+        case 12: return launch_nch<T, 12, SAVE>(a, maxW, nitems, lds, s);
+        case 16: return launch_nch<T, 16, SAVE>(a, maxW, nitems, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, int maxW, int nitems,
+                          hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    size_t lds;
+    if (maxW <= kDiagMaxW) {
+        lds = diag_lds_bytes(a.m, a.n, a.W, a.D, a.P);
+    } else {
+        lds = rows_lds_bytes(a.n, a.W, a.D, f64);
+    }
+    if (f64) return save ? launch_t<double, true>(a, maxW, nitems, lds, s)
+                         : launch_t<double, false>(a, maxW, nitems, lds, s);
+    return save ? launch_t<float, true>(a, maxW, nitems, lds, s)
+                : launch_t<float, false>(a, maxW, nitems, lds, s);
+}
+
+}  // namespace tcdtw

@@ -1,0 +1,88 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/*.h declares, and rejects invalid arguments on the host before any
+HIP call (no compute call is made here)."""
+import ctypes as C
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2101_07731_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w\s\*]*?\b(tc_dtw_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("tc_dtw_banded", "tc_dtw_backward", "tc_dtw_abi_version", "tc_dtw_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_function():
+    lib = L.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert lib.tc_dtw_abi_version() == 1
+
+
+def _batch(count=2, dim=3, ulen=8, data=0x1000):
+    return L.Batch(data, None, None, count, dim, ulen)
+
+
+def test_invalid_arguments_rejected_before_any_device_call():
+    lib = L.lib()
+    w = L.Window(2, 0, 0)
+    x, y = _batch(), _batch()
+    d = C.c_void_p(0x2000)
+    cases = [
+        (L.Batch(0, None, None, 2, 3, 8), y, w, d, L.ERR_INVALID),      # null data
+        (_batch(count=0), y, w, d, L.ERR_INVALID),                       # empty set
+        (_batch(count=3), y, w, d, L.ERR_INVALID),                       # count mismatch
+        (_batch(dim=4), y, w, d, L.ERR_INVALID),                         # dim mismatch
+        (_batch(ulen=0), y, w, d, L.ERR_INVALID),                        # zero length
+        (_batch(dim=65), _batch(dim=65), w, d, L.ERR_UNSUPPORTED),       # dim > 64
+        (x, y, L.Window(-1, 0, 0), d, L.ERR_INVALID),                    # negative window
+        (x, y, L.Window(0, 1, -10), d, L.ERR_INVALID),                   # negative fraction
+        (x, y, w, None, L.ERR_INVALID),                                  # null output
+    ]
+    for xb, yb, wb, out, expect in cases:
+        st = lib.tc_dtw_banded(C.byref(xb), C.byref(yb), wb, 0, out, None, None, 0, None)
+        assert st == expect, (st, lib.tc_dtw_last_error())
+        assert lib.tc_dtw_last_error()
+    st = lib.tc_dtw_banded(C.byref(x), C.byref(y), w, 0x80, d, None, None, 0, None)
+    assert st == L.ERR_INVALID
+    st = lib.tc_dtw_backward(C.byref(x), C.byref(y), w, None, d, d, d, None, 0, None)
+    assert st == L.ERR_INVALID
+
+
+def test_ragged_batches_need_a_workspace():
+    lib = L.lib()
+    lens = (C.c_int32 * 3)(5, 9, 7)
+    x = L.Batch(0x1000, None, lens, 3, 2, 0)
+    y = L.Batch(0x1000, None, lens, 3, 2, 0)
+    w = L.Window(0, 1, 10)
+    need = lib.tc_dtw_banded_workspace_bytes(C.byref(x), C.byref(y), w, 0)
+    assert need > 0
+    st = lib.tc_dtw_banded(C.byref(x), C.byref(y), w, 0, C.c_void_p(0x2000), None, None, 0, None)
+    assert st == L.ERR_WORKSPACE
+    assert lib.tc_dtw_saved_bytes(C.byref(x), C.byref(y), w) > 0
+    # uniform pairs need none
+    xu = _batch()
+    assert lib.tc_dtw_banded_workspace_bytes(C.byref(xu), C.byref(xu), w, 0) == 0
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in range(5):
+        assert lib.tc_dtw_status_string(s)

@@ -1,0 +1,174 @@
+"""Banded DTW forward and backward on the GPU against the FP64 oracle.
+
+Tolerances: float32 mode within 1e-5 relative (the recurrence sums at most
+m+n-1 point costs; observed rounding is far below the rigorous bound
+(m+n+D+2) 2^-24); the float64 mode reproduces the oracle bit for bit (same
+operation order, no contraction), checked after rounding both to float32.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2101_07731_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def walks(rng, B, T, D):
+    return np.cumsum(rng.standard_normal((B, T, D)), axis=1).astype(np.float32)
+
+
+def oracle_pairs(x, y, window=0, num=0, den=0):
+    return O.dtw_pairs(list(x), list(y), window=window, num=num, den=den)
+
+
+UNIFORM_CASES = [
+    # (B, m, n, D, window, frac)  -- diagonal mapping (W_eff <= 63), both parities, partial last wave
+    (37, 64, 64, 3, None, (1, 10)),     # W=6, 9 pairs per wave
+    (23, 100, 100, 8, 25, None),        # W=25 (odd)
+    (19, 96, 96, 8, 12, None),          # W=12 (even)
+    (9, 128, 128, 12, 51, None),        # W=51
+    (5, 70, 70, 2, 63, None),           # W=63, one pair per wave
+    (11, 40, 52, 5, 3, None),           # unequal lengths: W_eff = 12
+    (7, 1, 9, 3, 0, None),              # one point against many
+    (6, 33, 33, 1, 0, None),            # W=0: the diagonal
+    (5, 20, 20, 64, 4, None),           # D=64
+    (4, 30, 30, 13, 200, None),         # window wider than the series (capped at 29)
+    # row-systolic mapping (W_eff >= 64)
+    (6, 300, 300, 16, 64, None),
+    (5, 200, 130, 3, 70, None),
+    (3, 129, 257, 8, 0, None),          # W_eff = |m-n| = 128
+    (3, 260, 260, 12, None, (1, 3)),    # W = 86, partial last row block
+]
+
+
+@pytest.mark.parametrize("case", UNIFORM_CASES, ids=[str(c) for c in UNIFORM_CASES])
+def test_uniform_pairs_f32_and_f64(dev, case):
+    from paper_2101_07731_amd import pairs
+    B, m, n, D, window, frac = case
+    say("banded uniform", case)
+    rng = np.random.default_rng(hash(case) % 2**32)
+    x, y = walks(rng, B, m, D), walks(rng, B, n, D)
+    num, den = frac if frac else (0, 0)
+    ref = oracle_pairs(x, y, window or 0, num, den)
+    X, Y = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    d32 = pairs.banded(X, Y, window=window, frac=frac).cpu().numpy()
+    np.testing.assert_allclose(d32, ref, rtol=1e-5, atol=0)
+    d64 = pairs.banded(X, Y, window=window, frac=frac, f64=True).cpu().numpy()
+    np.testing.assert_array_equal(d64, ref.astype(np.float32))
+
+
+def test_ragged_pairs(dev):
+    from paper_2101_07731_amd import pairs
+    rng = np.random.default_rng(5)
+    xs, ys = [], []
+    for k in range(40):
+        D = 4
+        m = int(rng.integers(1, 300))
+        n = int(rng.integers(1, 300)) if k % 3 else max(1, m + int(rng.integers(-20, 20)))
+        xs.append(walks(rng, 1, m, D)[0])
+        ys.append(walks(rng, 1, n, D)[0])
+    say("banded ragged", len(xs))
+    ref = oracle_pairs(xs, ys, 0, 1, 10)
+    X = [torch.from_numpy(a).to(dev) for a in xs]
+    Y = [torch.from_numpy(a).to(dev) for a in ys]
+    d32 = pairs.banded(X, Y, frac=(1, 10)).cpu().numpy()
+    np.testing.assert_allclose(d32, ref, rtol=1e-5, atol=0)
+    d64 = pairs.banded(X, Y, frac=(1, 10), f64=True).cpu().numpy()
+    np.testing.assert_array_equal(d64, ref.astype(np.float32))
+
+
+def test_repeatable(dev):
+    from paper_2101_07731_amd import pairs
+    rng = np.random.default_rng(6)
+    x, y = walks(rng, 50, 120, 8), walks(rng, 50, 120, 8)
+    X, Y = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    a = pairs.banded(X, Y, frac=(1, 10)).cpu().numpy()
+    b = pairs.banded(X, Y, frac=(1, 10)).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+
+
+GRAD_CASES = [
+    (8, 32, 32, 12, None, (1, 10)),     # the finite-difference set shape (W=3)
+    (12, 100, 100, 8, 25, None),        # diagonal mapping, odd W
+    (6, 64, 80, 3, 16, None),           # unequal lengths
+    (4, 200, 200, 4, 70, None),         # row-systolic mapping
+]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[str(c) for c in GRAD_CASES])
+def test_backward_matches_oracle_path_gradient(dev, case):
+    """In float64 mode the forward takes the oracle's path, so the gradient
+    must equal the oracle's path gradient to float32 rounding."""
+    from paper_2101_07731_amd import pairs
+    B, m, n, D, window, frac = case
+    say("backward", case)
+    rng = np.random.default_rng(7 + B)
+    x = walks(rng, B, m, D) + 1e-3 * rng.standard_normal((B, m, D)).astype(np.float32)
+    y = walks(rng, B, n, D) + 1e-3 * rng.standard_normal((B, n, D)).astype(np.float32)
+    g = rng.uniform(0.5, 2.0, size=B).astype(np.float32)
+    X, Y = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    dist, saved = pairs.banded(X, Y, window=window, frac=frac, f64=True, save=True)
+    gx, gy = pairs.backward(X, Y, saved, torch.from_numpy(g).to(dev), window=window, frac=frac)
+    gx, gy = gx.cpu().numpy(), gy.cpu().numpy()
+    num, den = frac if frac else (0, 0)
+    for b in range(B):
+        weff = O.window_eff(m, n, window or 0, num, den)
+        v, rq, rc, _ = O.path_grad(x[b], y[b], weff, float(g[b]))
+        assert np.float32(v) == dist[b].item()
+        scale = max(1.0, np.abs(rq).max(), np.abs(rc).max())
+        np.testing.assert_allclose(gx[b], rq, rtol=1e-6, atol=1e-6 * scale)
+        np.testing.assert_allclose(gy[b], rc, rtol=1e-6, atol=1e-6 * scale)
+
+
+def test_backward_f32_forward_invariants(dev):
+    """With a float32 forward the path may differ from the FP64 one at
+    near-ties; any monotone path's gradient still satisfies translation
+    invariance and Euler's identity sum(x gx) + sum(y gy) = 2 g cost(path),
+    with cost(path) equal to the float32 DTW up to rounding."""
+    from paper_2101_07731_amd import pairs
+    rng = np.random.default_rng(8)
+    B, T, D = 16, 128, 12
+    x = walks(rng, B, T, D)
+    y = walks(rng, B, T, D)
+    X, Y = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    dist, saved = pairs.banded(X, Y, frac=(1, 10), save=True)
+    g = torch.ones(B, device=dev)
+    gx, gy = pairs.backward(X, Y, saved, g, frac=(1, 10))
+    gx, gy, dist = gx.cpu().numpy().astype(np.float64), gy.cpu().numpy().astype(np.float64), dist.cpu().numpy()
+    ref = oracle_pairs(x, y, 0, 1, 10)
+    for b in range(B):
+        tr = gx[b].sum(0) + gy[b].sum(0)
+        np.testing.assert_allclose(tr, 0.0, atol=1e-3 * max(1.0, np.abs(gx[b]).max()))
+        euler = (x[b] * gx[b]).sum() + (y[b] * gy[b]).sum()
+        assert euler == pytest.approx(2 * ref[b], rel=1e-4)
+
+
+def test_dtw_loss_autograd(dev):
+    from paper_2101_07731_amd.pairs import DTWLoss
+    rng = np.random.default_rng(9)
+    x = walks(rng, 4, 48, 6)
+    y = walks(rng, 4, 48, 6)
+    X = torch.from_numpy(x).to(dev).requires_grad_(True)
+    Y = torch.from_numpy(y).to(dev).requires_grad_(True)
+    loss = DTWLoss.apply(X, Y, None, (1, 10), True).sum()
+    loss.backward()
+    for b in range(4):
+        v, rq, rc, _ = O.path_grad(x[b], y[b], 4, 1.0)
+        np.testing.assert_allclose(X.grad[b].cpu().numpy(), rq, rtol=1e-6, atol=1e-5)
+        np.testing.assert_allclose(Y.grad[b].cpu().numpy(), rc, rtol=1e-6, atol=1e-5)
