@@ -131,6 +131,122 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
                               float* grad_x, float* grad_y,
                               void* ws, size_t ws_bytes, tc_dtw_stream stream);
 
+/* -------------------------------------------------------------- index ---
+ * tc_dtw_build_index: prepares a candidate (reference) set for repeated
+ * searches: a copy of the series, an element-major copy in tiles of 64
+ * references (uniform lengths only) for the envelope bound, the candidate
+ * neighbour distances d(c_{j-1}, c_j) of the basic triangle bound (Sec. 4.1,
+ * Eqs. 9-10, computed ahead of time and reused by every query), and the
+ * value range (min, max over all values) that sets LB_PC's smallest cell
+ * (Sec. 5).
+ *   refs   the candidate set; its device data may be freed once the call
+ *          has completed on `stream`.
+ *   buf    DEVICE buffer of tc_dtw_index_bytes(refs) bytes, owned by the
+ *          caller and read by every later call that takes the index; it
+ *          must stay alive and unmodified while the index is used.
+ *   out    HOST: receives the index description (plain data; copy freely).
+ * The index is immutable after the build, so searches on different streams
+ * may share it.  Errors: INVALID, UNSUPPORTED, WORKSPACE (buf too small),
+ * DEVICE. */
+typedef struct {
+    void* buf;
+    size_t bytes;
+    int32_t count;        /* number of candidate series */
+    int32_t dim;
+    int32_t uniform_len;  /* > 0 when every candidate has this length, else 0 */
+    int32_t max_len;
+    int32_t ntiles;       /* 64-candidate tiles of the element-major copy (uniform only) */
+    int32_t reserved0;
+    int64_t off_series;   /* byte offsets of the sections inside buf */
+    int64_t off_tiles;
+    int64_t off_gamma;
+    int64_t off_meta;     /* int64 offsets[count], then int32 lengths[count] */
+    int64_t off_range;    /* float[2]: smallest and largest value */
+    int64_t total_len;    /* sum of the candidate lengths */
+    int64_t reserved[3];
+} tc_dtw_index;
+
+size_t tc_dtw_index_bytes(const tc_dtw_batch* refs);
+tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t bytes,
+                                 tc_dtw_index* out, tc_dtw_stream stream);
+
+/* ---------------------------------------------------- search parameters ---
+ * Lower-bound cascade of the 1-NN search (Sec. 6, selective deployment):
+ * LB_MV (Sec. 3) for every pair; LB_PC (Sec. 5) and then LB_TI (Sec. 4,
+ * LB_TIP_TOP by default) only for pairs whose LB_MV exceeds e^2 times the
+ * best-so-far (the squared-cost form of e < LB_MV / d_best; the paper's e
+ * applies to distances, Sec. 6); DTW with early abandoning (Sec. 7.1) for
+ * the survivors.  Defaults are the paper's settings (Sec. 7.1): P = 5 with
+ * TOP, K = w = 6, Lv = 2, e in its grids. */
+#define TC_DTW_LB_MV 1u
+#define TC_DTW_LB_PC 2u
+#define TC_DTW_LB_TI 4u
+
+typedef struct {
+    tc_dtw_window window;
+    uint32_t bounds;        /* OR of TC_DTW_LB_*; 0 = plain exhaustive DTW (no bounds, no abandoning) */
+    int32_t early_abandon;  /* 1: abandon a DTW once it provably exceeds the best so far */
+    int32_t ti_period;      /* P of LB_TIP; <= 0: only row 0 is exact (basic LB_TI) */
+    int32_t ti_top;         /* 1: exact distance at the top cell of every row's window */
+    int32_t pc_levels;      /* quantisation levels per dimension, Lv */
+    int32_t pc_clusters;    /* boxes per expanded window, K */
+    int32_t pc_group;       /* window expansion factor, w */
+    float pc_min_cell;      /* smallest cell length; <= 0: 1e-5 * (max - min) of the index */
+    float trigger_ti;       /* triggering threshold e of LB_TI */
+    float trigger_pc;       /* triggering threshold e of LB_PC */
+    float prune_margin;     /* extra relative margin of every prune test (>= 0) */
+    int32_t seed_r;         /* smallest-LB_MV candidates per query whose DTW seeds the best-so-far; 0: 4 */
+    int32_t k;              /* neighbours per query; must be 1 */
+} tc_dtw_knn_params;
+
+void tc_dtw_knn_params_default(tc_dtw_knn_params* p);
+
+/* ------------------------------------------------------- lower bounds ---
+ * tc_dtw_lower_bounds: the dense bound matrix lb[q][c] (squared cost) of one
+ * kind: TC_DTW_LB_MV (Sec. 3), TC_DTW_LB_PC (Sec. 5) or TC_DTW_LB_TI
+ * (Sec. 4) with the parameters of `p`.  Every value is rounded so that it
+ * never exceeds the exact bound of the float32 inputs, so it is safe to
+ * prune with.  Uniform query and candidate lengths.
+ *   lb   DEVICE float[queries->count * ix->count], row-major by query. */
+size_t tc_dtw_lower_bounds_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                                           const tc_dtw_knn_params* p, uint32_t kind);
+tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                                  const tc_dtw_knn_params* p, uint32_t kind, float* lb,
+                                  void* ws, size_t ws_bytes, tc_dtw_stream stream);
+
+/* ---------------------------------------------------------------- 1-NN ---
+ * tc_dtw_knn: for every query, the index of the candidate with the smallest
+ * banded DTW (ties go to the lowest index) and that distance (Sec. 2
+ * DTW-NN; Sec. 3 Definition 1).  The result equals an exhaustive float64
+ * search: pruning and abandoning use rigorous float32 error bounds, and
+ * every candidate whose float32 DTW lies within those bounds of the best is
+ * re-scored in float64.
+ *   nn_idx   DEVICE int32[queries->count]
+ *   nn_dist  DEVICE float[queries->count] (the float64 DTW rounded to float32)
+ *   stats    HOST or NULL.  When given, the call waits for the stream and
+ *            fills the counters and per-stage times.
+ * Errors: INVALID (dims differ, bad parameters), UNSUPPORTED (k != 1),
+ * WORKSPACE, DEVICE. */
+typedef struct {
+    uint64_t pairs;          /* query-candidate pairs */
+    uint64_t pruned_mv;      /* pairs skipped by LB_MV */
+    uint64_t pruned_pc;      /* pairs skipped by LB_PC */
+    uint64_t pruned_ti;      /* pairs skipped by LB_TI */
+    uint64_t dtw_started;    /* pairs whose DTW was started (seeds included) */
+    uint64_t dtw_abandoned;  /* of those, abandoned early */
+    uint64_t dtw_completed;
+    uint64_t cells;          /* DTW cells evaluated (abandoned pairs counted up to the abandoning step) */
+    uint64_t rescored;       /* float64 re-scorings */
+    float stage_ms[8];       /* prep, lb_mv, seed, compact, lb_pc+lb_ti, dtw, finalize, total */
+} tc_dtw_knn_stats;
+
+size_t tc_dtw_knn_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                                  const tc_dtw_knn_params* p);
+tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                         const tc_dtw_knn_params* p, int32_t* nn_idx, float* nn_dist,
+                         tc_dtw_knn_stats* stats, void* ws, size_t ws_bytes,
+                         tc_dtw_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,31 @@ class Window(C.Structure):
     _fields_ = [("window", C.c_int32), ("frac_num", C.c_int32), ("frac_den", C.c_int32)]
 
 
+class Index(C.Structure):
+    _fields_ = [("buf", C.c_void_p), ("bytes", C.c_size_t), ("count", C.c_int32), ("dim", C.c_int32),
+                ("uniform_len", C.c_int32), ("max_len", C.c_int32), ("ntiles", C.c_int32),
+                ("reserved0", C.c_int32), ("off_series", C.c_int64), ("off_tiles", C.c_int64),
+                ("off_gamma", C.c_int64), ("off_meta", C.c_int64), ("off_range", C.c_int64),
+                ("total_len", C.c_int64), ("reserved", C.c_int64 * 3)]
+
+
+class KnnParams(C.Structure):
+    _fields_ = [("window", Window), ("bounds", C.c_uint32), ("early_abandon", C.c_int32),
+                ("ti_period", C.c_int32), ("ti_top", C.c_int32), ("pc_levels", C.c_int32),
+                ("pc_clusters", C.c_int32), ("pc_group", C.c_int32), ("pc_min_cell", C.c_float),
+                ("trigger_ti", C.c_float), ("trigger_pc", C.c_float), ("prune_margin", C.c_float),
+                ("seed_r", C.c_int32), ("k", C.c_int32)]
+
+
+class KnnStats(C.Structure):
+    _fields_ = [("pairs", C.c_uint64), ("pruned_mv", C.c_uint64), ("pruned_pc", C.c_uint64),
+                ("pruned_ti", C.c_uint64), ("dtw_started", C.c_uint64), ("dtw_abandoned", C.c_uint64),
+                ("dtw_completed", C.c_uint64), ("cells", C.c_uint64), ("rescored", C.c_uint64),
+                ("stage_ms", C.c_float * 8)]
+
+
+LB_MV, LB_PC, LB_TI = 1, 2, 4
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -46,6 +71,16 @@ _SIGS = {
     "tc_dtw_backward_workspace_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
     "tc_dtw_backward": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tc_dtw_index_bytes": (C.c_size_t, [C.POINTER(Batch)]),
+    "tc_dtw_build_index": (C.c_int, [C.POINTER(Batch), C.c_void_p, C.c_size_t, C.POINTER(Index), C.c_void_p]),
+    "tc_dtw_knn_params_default": (None, [C.POINTER(KnnParams)]),
+    "tc_dtw_lower_bounds_workspace_bytes": (C.c_size_t, [C.POINTER(Index), C.POINTER(Batch),
+                                                         C.POINTER(KnnParams), C.c_uint32]),
+    "tc_dtw_lower_bounds": (C.c_int, [C.POINTER(Index), C.POINTER(Batch), C.POINTER(KnnParams), C.c_uint32,
+                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tc_dtw_knn_workspace_bytes": (C.c_size_t, [C.POINTER(Index), C.POINTER(Batch), C.POINTER(KnnParams)]),
+    "tc_dtw_knn": (C.c_int, [C.POINTER(Index), C.POINTER(Batch), C.POINTER(KnnParams), C.c_void_p, C.c_void_p,
+                             C.POINTER(KnnStats), C.c_void_p, C.c_size_t, C.c_void_p]),
 }
 
 

@@ -1,0 +1,415 @@
+// C ABI: candidate index, dense lower bounds and the 1-NN search.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "api_common.h"
+
+namespace tcdtw {
+
+static const double kUnit = 1.0 / 16777216.0;   // float32 unit roundoff 2^-24
+
+// Section layout of an index buffer.
+struct IndexLayout {
+    bool uniform;
+    int count, dim, ulen, maxlen, ntiles;
+    int64_t total_len;
+    size_t off_series, off_tiles, off_gamma, off_meta, off_range, bytes;
+};
+
+static IndexLayout index_layout(const HostSet& R) {
+    IndexLayout L;
+    L.uniform = R.uniform;
+    L.count = R.count;
+    L.dim = R.dim;
+    L.ulen = R.uniform ? R.ulen : 0;
+    L.maxlen = R.maxlen;
+    L.total_len = 0;
+    for (int s = 0; s < R.count; ++s) L.total_len += R.length(s);
+    L.ntiles = R.uniform ? (R.count + 63) / 64 : 0;
+    Carve c(nullptr, 0);
+    auto at = [&](size_t bytes) { c.used = (c.used + 255) & ~(size_t)255; size_t o = c.used; c.used += bytes; return o; };
+    L.off_series = at((size_t)L.total_len * R.dim * 4);
+    L.off_tiles = at(R.uniform ? (size_t)L.ntiles * R.ulen * R.dim * 64 * 4 : 0);
+    L.off_gamma = at((size_t)L.total_len * 4);
+    L.off_meta = at((size_t)R.count * (8 + 8 + 4 + 8) + 8);
+    L.off_range = at(8);
+    L.bytes = c.need();
+    return L;
+}
+
+static tc_dtw_status check_index(const tc_dtw_index* ix) {
+    if (!ix || !ix->buf) return fail(TC_DTW_ERR_INVALID, "null index");
+    if (ix->count < 1 || ix->dim < 1 || ix->dim > 64) return fail(TC_DTW_ERR_INVALID, "index not built");
+    return TC_DTW_OK;
+}
+
+static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
+    if (!p) return fail(TC_DTW_ERR_INVALID, "null params");
+    tc_dtw_status st = check_window(p->window);
+    if (st != TC_DTW_OK) return st;
+    if (p->k != 1) return fail(TC_DTW_ERR_UNSUPPORTED, "only k = 1 is supported");
+    if (p->bounds & ~(TC_DTW_LB_MV | TC_DTW_LB_PC | TC_DTW_LB_TI))
+        return fail(TC_DTW_ERR_INVALID, "unknown bound bits");
+    if ((p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)) && !(p->bounds & TC_DTW_LB_MV))
+        return fail(TC_DTW_ERR_INVALID, "LB_PC and LB_TI are deployed behind LB_MV (set TC_DTW_LB_MV)");
+    if (p->pc_levels < 2 || p->pc_clusters < 1 || p->pc_group < 1)
+        return fail(TC_DTW_ERR_INVALID, "LB_PC needs levels >= 2, clusters >= 1, group >= 1");
+    if (!(p->prune_margin >= 0.0f) || !(p->trigger_ti >= 0.0f) || !(p->trigger_pc >= 0.0f))
+        return fail(TC_DTW_ERR_INVALID, "margins and triggers must be >= 0");
+    if (p->seed_r < 0) return fail(TC_DTW_ERR_INVALID, "seed_r must be >= 0");
+    return TC_DTW_OK;
+}
+
+// Everything a uniform search needs, with workspace offsets.
+struct KnnPlan {
+    int nq, nc, m, n, D, W, R, P, cap, ntiles;
+    bool plain, abandon, gate;
+    size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
+        o_counters, o_key, o_stats, bytes;
+};
+
+static int list_pairs_per_wave(int W) { return W <= kDiagMaxW ? kWave / (W + 1) : 1; }
+
+static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* qb, const tc_dtw_knn_params* p,
+                                   KnnPlan& K, HostSet& Qs) {
+    tc_dtw_status st;
+    if ((st = check_index(ix)) != TC_DTW_OK) return st;
+    if ((st = read_set(qb, "queries", Qs)) != TC_DTW_OK) return st;
+    if ((st = check_params(p)) != TC_DTW_OK) return st;
+    if (Qs.dim != ix->dim) return fail(TC_DTW_ERR_INVALID, "queries and index have different dims");
+    if (!Qs.uniform || ix->uniform_len <= 0)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "this search needs uniform query and candidate lengths");
+    K.nq = Qs.count;
+    K.nc = ix->count;
+    K.m = Qs.ulen;
+    K.n = ix->uniform_len;
+    K.D = ix->dim;
+    K.W = window_eff(K.m, K.n, p->window);
+    K.plain = (p->bounds == 0);
+    K.abandon = !K.plain && p->early_abandon != 0;
+    K.gate = (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)) != 0;
+    K.R = K.plain ? 0 : std::min(std::min(p->seed_r > 0 ? p->seed_r : 4, kMaxSeeds), K.nc);
+    K.P = list_pairs_per_wave(K.W);
+    K.cap = K.nc;
+    K.ntiles = ix->ntiles;
+    Carve c(nullptr, 0);
+    auto at = [&](size_t bytes) { c.used = (c.used + 255) & ~(size_t)255; size_t o = c.used; c.used += bytes; return o; };
+    const size_t nqt = (size_t)(K.nq + kQT - 1) / kQT;
+    K.o_env = at(K.plain ? 0 : nqt * kQT * (size_t)K.n * K.D * 2 * 4);
+    K.o_lb = at(K.plain ? 0 : (size_t)K.nq * K.nc * 4);
+    K.o_seeds = at((size_t)K.nq * std::max(K.R, 1) * 4);
+    K.o_seed_dist = at((size_t)K.nq * std::max(K.R, 1) * 4);
+    K.o_list = at((size_t)K.nq * K.cap * 4);
+    K.o_list_dist = at((size_t)K.nq * K.cap * 4);
+    K.o_cnt = at((size_t)K.nq * 4);
+    K.o_glist = at(K.gate ? (size_t)K.nq * K.cap * 4 : 0);
+    K.o_gcnt = at((size_t)K.nq * 4);
+    K.o_prefix = at((size_t)(K.nq + 1) * 4);
+    K.o_counters = at(kNumCounters * 4);
+    K.o_key = at((size_t)K.nq * 8);
+    K.o_stats = at(kNumStats * 8);
+    K.bytes = c.need();
+    const size_t lim = 163840;
+    if (knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, 1) > lim || knn_final_lds_bytes(K.m, K.n, K.W, K.D) > lim)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
+    while (K.P > 1 && knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, K.P) > lim) --K.P;
+    return TC_DTW_OK;
+}
+
+static KnnPlanDev dev_plan(const KnnPlan& K, const tc_dtw_index* ix, const HostSet& Qs, char* ws) {
+    KnnPlanDev d;
+    std::memset(&d, 0, sizeof d);
+    char* base = static_cast<char*>(ix->buf);
+    d.Q = Qs.data;
+    d.C = reinterpret_cast<const float*>(base + ix->off_series);
+    d.tiles = reinterpret_cast<const float*>(base + ix->off_tiles);
+    d.nq = K.nq; d.nc = K.nc; d.m = K.m; d.n = K.n; d.D = K.D; d.W = K.W;
+    d.ntiles = K.ntiles; d.R = K.R; d.cap = K.cap;
+    d.env = K.plain ? nullptr : reinterpret_cast<float*>(ws + K.o_env);
+    d.lb = K.plain ? nullptr : reinterpret_cast<float*>(ws + K.o_lb);
+    d.seeds = reinterpret_cast<int32_t*>(ws + K.o_seeds);
+    d.seed_dist = reinterpret_cast<float*>(ws + K.o_seed_dist);
+    d.list = reinterpret_cast<uint32_t*>(ws + K.o_list);
+    d.list_dist = reinterpret_cast<float*>(ws + K.o_list_dist);
+    d.cnt = reinterpret_cast<int32_t*>(ws + K.o_cnt);
+    d.glist = K.gate ? reinterpret_cast<uint32_t*>(ws + K.o_glist) : nullptr;
+    d.gcnt = reinterpret_cast<int32_t*>(ws + K.o_gcnt);
+    d.prefix = reinterpret_cast<int32_t*>(ws + K.o_prefix);
+    d.counters = reinterpret_cast<int32_t*>(ws + K.o_counters);
+    d.key = reinterpret_cast<unsigned long long*>(ws + K.o_key);
+    d.stats = reinterpret_cast<unsigned long long*>(ws + K.o_stats);
+    return d;
+}
+
+static float dp_gamma(int m, int n, int D) {
+    return (float)(1.01 * (double)(m + n + 4 * nch_pad(D) + 2) * kUnit);
+}
+
+static int persistent_blocks(size_t lds, int64_t max_items) {
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 163840 / std::max<size_t>(lds, 1)));
+    int64_t nb = (int64_t)256 * per_cu;
+    if (max_items < nb) nb = std::max<int64_t>(max_items, 1);
+    return (int)nb;
+}
+
+static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, bool abandon) {
+    KnnDtwArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Q = d.Q; a.C = d.C;
+    a.nq = K.nq; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W; a.P = K.P;
+    if (seeds) {
+        a.list = reinterpret_cast<const uint32_t*>(d.seeds);
+        a.list_dist = d.seed_dist;
+        a.cnt = d.cnt;      // unused with cnt_uniform
+        a.cnt_uniform = K.R;
+        a.cap = K.R;
+    } else {
+        a.list = d.list;
+        a.list_dist = d.list_dist;
+        a.cnt = d.cnt;
+        a.cnt_uniform = 0;
+        a.cap = K.cap;
+    }
+    a.prefix = d.prefix;
+    a.counter = d.counters + (seeds ? 0 : 1);
+    a.key = d.key;
+    a.stats = d.stats;
+    a.gamma = dp_gamma(K.m, K.n, K.D);
+    a.abandon = abandon ? 1 : 0;
+    return a;
+}
+
+}  // namespace tcdtw
+
+using namespace tcdtw;
+
+extern "C" {
+
+void tc_dtw_knn_params_default(tc_dtw_knn_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->window.frac_num = 1;
+    p->window.frac_den = 10;
+    p->bounds = TC_DTW_LB_MV;
+    p->early_abandon = 1;
+    p->ti_period = 5;
+    p->ti_top = 1;
+    p->pc_levels = 2;
+    p->pc_clusters = 6;
+    p->pc_group = 6;
+    p->pc_min_cell = 0.0f;
+    p->trigger_ti = 0.1f;
+    p->trigger_pc = 0.1f;
+    p->prune_margin = 1e-6f;
+    p->seed_r = 4;
+    p->k = 1;
+}
+
+size_t tc_dtw_index_bytes(const tc_dtw_batch* refs) {
+    HostSet R;
+    if (read_set(refs, "refs", R) != TC_DTW_OK) return 0;
+    return index_layout(R).bytes;
+}
+
+tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t bytes, tc_dtw_index* out,
+                                 tc_dtw_stream stream) {
+    HostSet R;
+    tc_dtw_status st = read_set(refs, "refs", R);
+    if (st != TC_DTW_OK) return st;
+    if (!buf || !out) return fail(TC_DTW_ERR_INVALID, "null index buffer or output");
+    const IndexLayout L = index_layout(R);
+    if (bytes < L.bytes) return fail(TC_DTW_ERR_WORKSPACE, "index buffer smaller than tc_dtw_index_bytes()");
+    if ((st = check_device()) != TC_DTW_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(buf);
+    IndexBuildArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.src = R.data;
+    a.count = R.count;
+    a.ulen = L.ulen;
+    a.D = R.dim;
+    a.maxlen = R.maxlen;
+    a.ntiles = L.ntiles;
+    a.total_len = L.total_len;
+    a.series = reinterpret_cast<float*>(base + L.off_series);
+    a.tiles = L.uniform ? reinterpret_cast<float*>(base + L.off_tiles) : nullptr;
+    a.gamma = reinterpret_cast<float*>(base + L.off_gamma);
+    a.range_keys = reinterpret_cast<uint32_t*>(base + L.off_range);
+    // meta: dst offsets, gamma offsets, lengths, source offsets
+    int64_t* dst_off = reinterpret_cast<int64_t*>(base + L.off_meta);
+    int64_t* gam_off = dst_off + R.count;
+    int32_t* lens = reinterpret_cast<int32_t*>(gam_off + R.count);
+    int64_t* src_off = reinterpret_cast<int64_t*>(lens + R.count + (R.count & 1));
+    std::vector<int64_t> h_dst(R.count), h_gam(R.count), h_src(R.count);
+    std::vector<int32_t> h_len(R.count);
+    int64_t next = 0, gnext = 0;
+    for (int k = 0; k < R.count; ++k) {
+        h_len[k] = R.length(k);
+        h_src[k] = R.offset(k);
+        h_dst[k] = next;
+        h_gam[k] = gnext;
+        next += (int64_t)h_len[k] * R.dim;
+        gnext += h_len[k];
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dst_off, h_dst.data(), R.count * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(gam_off, h_gam.data(), R.count * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(lens, h_len.data(), R.count * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(src_off, h_src.data(), R.count * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "index metadata upload");
+    a.dst_off = dst_off;
+    a.gamma_off = gam_off;
+    a.lens = lens;
+    a.src_off = src_off;
+    if ((e = launch_index_build(a, s)) != hipSuccess) return hip_fail(e, "index build launch");
+    std::memset(out, 0, sizeof *out);
+    out->buf = buf;
+    out->bytes = L.bytes;
+    out->count = R.count;
+    out->dim = R.dim;
+    out->uniform_len = L.ulen;
+    out->max_len = R.maxlen;
+    out->ntiles = L.ntiles;
+    out->off_series = (int64_t)L.off_series;
+    out->off_tiles = (int64_t)L.off_tiles;
+    out->off_gamma = (int64_t)L.off_gamma;
+    out->off_meta = (int64_t)L.off_meta;
+    out->off_range = (int64_t)L.off_range;
+    out->total_len = L.total_len;
+    return ok();
+}
+
+size_t tc_dtw_knn_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                                  const tc_dtw_knn_params* p) {
+    KnnPlan K;
+    HostSet Q;
+    if (make_knn_plan(ix, queries, p, K, Q) != TC_DTW_OK) return 0;
+    return K.bytes;
+}
+
+tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, const tc_dtw_knn_params* p,
+                         int32_t* nn_idx, float* nn_dist, tc_dtw_knn_stats* stats, void* ws,
+                         size_t ws_bytes, tc_dtw_stream stream) {
+    KnnPlan K;
+    HostSet Qs;
+    tc_dtw_status st = make_knn_plan(ix, queries, p, K, Qs);
+    if (st != TC_DTW_OK) return st;
+    if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
+    if (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI))
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC / LB_TI are not available in this build");
+    if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
+    if ((st = check_device()) != TC_DTW_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    const KnnPlanDev d = dev_plan(K, ix, Qs, w);
+
+    hipEvent_t ev[8];
+    const bool timed = stats != nullptr;
+    if (timed)
+        for (auto& x : ev) (void)hipEventCreate(&x);
+    auto mark = [&](int i) { if (timed) (void)hipEventRecord(ev[i], s); };
+
+    hipError_t e;
+    mark(0);
+    if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
+    mark(1);
+    if (!K.plain) {
+        if ((e = launch_lb_mv(d, d.lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+    }
+    mark(2);
+    const size_t lds = knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, K.P);
+    if (!K.plain && K.R > 0) {
+        if ((e = launch_topr(d, s)) != hipSuccess) return hip_fail(e, "seed selection");
+        const KnnDtwArgs a = list_args(K, d, true, false);
+        const int64_t items = (int64_t)K.nq * ((K.R + K.P - 1) / K.P);
+        if ((e = launch_dtw_lists(a, persistent_blocks(lds, items), s)) != hipSuccess) return hip_fail(e, "seed dtw");
+    }
+    mark(3);
+    const double keep = 1.0 - (double)p->prune_margin;
+    const double e_pc = p->trigger_pc, e_ti = p->trigger_ti;
+    const double gate_e2 = std::min(e_pc * e_pc, e_ti * e_ti);
+    if ((e = launch_compact(d, K.plain ? 0.0 : keep, gate_e2, K.gate ? 1 : 0, s)) != hipSuccess)
+        return hip_fail(e, "compaction");
+    mark(4);
+    mark(5);
+    {
+        const KnnDtwArgs a = list_args(K, d, false, K.abandon);
+        const int64_t items = (int64_t)K.nq * ((K.nc + K.P - 1) / K.P);
+        if ((e = launch_dtw_lists(a, persistent_blocks(lds, items), s)) != hipSuccess) return hip_fail(e, "dtw");
+    }
+    mark(6);
+    {
+        KnnFinalArgs f;
+        std::memset(&f, 0, sizeof f);
+        f.Q = d.Q; f.C = d.C;
+        f.nq = K.nq; f.m = K.m; f.n = K.n; f.D = K.D; f.W = K.W; f.R = K.R; f.cap = K.cap;
+        f.seeds = d.seeds; f.seed_dist = d.seed_dist;
+        f.list = d.list; f.list_dist = d.list_dist; f.cnt = d.cnt;
+        const double g = dp_gamma(K.m, K.n, K.D);
+        f.ratio = (1.0 + g) / (1.0 - g) * (1.0 + 1e-9);
+        f.nn_idx = nn_idx; f.nn_dist = nn_dist;
+        f.stats = d.stats;
+        if ((e = launch_knn_finalize(f, s)) != hipSuccess) return hip_fail(e, "finalize");
+    }
+    mark(7);
+    if (timed) {
+        unsigned long long h[kNumStats];
+        e = hipMemcpyAsync(h, d.stats, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "stats readback");
+        std::memset(stats, 0, sizeof *stats);
+        stats->pairs = (uint64_t)K.nq * K.nc;
+        stats->pruned_mv = h[kStPrunedMv];
+        stats->pruned_pc = h[kStPrunedPc];
+        stats->pruned_ti = h[kStPrunedTi];
+        stats->dtw_started = h[kStDtwStarted];
+        stats->dtw_abandoned = h[kStDtwAbandoned];
+        stats->dtw_completed = h[kStDtwStarted] - h[kStDtwAbandoned];
+        stats->cells = h[kStCells];
+        stats->rescored = h[kStRescored];
+        for (int i = 0; i < 7; ++i) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            stats->stage_ms[i] = ms;
+        }
+        float tot = 0.0f;
+        (void)hipEventElapsedTime(&tot, ev[0], ev[7]);
+        stats->stage_ms[7] = tot;
+        for (auto& x : ev) (void)hipEventDestroy(x);
+    }
+    return ok();
+}
+
+size_t tc_dtw_lower_bounds_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                                           const tc_dtw_knn_params* p, uint32_t kind) {
+    KnnPlan K;
+    HostSet Q;
+    if (make_knn_plan(ix, queries, p, K, Q) != TC_DTW_OK) return 0;
+    (void)kind;
+    return K.bytes;
+}
+
+tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* queries,
+                                  const tc_dtw_knn_params* p, uint32_t kind, float* lb, void* ws,
+                                  size_t ws_bytes, tc_dtw_stream stream) {
+    KnnPlan K;
+    HostSet Qs;
+    tc_dtw_status st = make_knn_plan(ix, queries, p, K, Qs);
+    if (st != TC_DTW_OK) return st;
+    if (!lb) return fail(TC_DTW_ERR_INVALID, "null lb pointer");
+    if (kind != TC_DTW_LB_MV && kind != TC_DTW_LB_PC && kind != TC_DTW_LB_TI)
+        return fail(TC_DTW_ERR_INVALID, "kind must be one of TC_DTW_LB_MV, TC_DTW_LB_PC, TC_DTW_LB_TI");
+    if (kind != TC_DTW_LB_MV) return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC / LB_TI are not available in this build");
+    if (K.plain) return fail(TC_DTW_ERR_INVALID, "params.bounds must include TC_DTW_LB_MV");
+    if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_lower_bounds_workspace_bytes()");
+    if ((st = check_device()) != TC_DTW_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const KnnPlanDev d = dev_plan(K, ix, Qs, static_cast<char*>(ws));
+    hipError_t e;
+    if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
+    if ((e = launch_lb_mv(d, lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+    return ok();
+}
+
+}  // extern "C"

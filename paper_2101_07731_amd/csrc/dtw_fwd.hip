@@ -26,10 +26,21 @@
 //
 // The virtual predecessor of (0,0) is a 0 placed on the slot of diagonal 0
 // one round before the start.
-#include "device_common.h"
-#include "internal.h"
+#include "dtw_core.h"
 
 namespace tcdtw {
+
+size_t diag_lds_bytes(int m, int n, int W, int D, int P) {
+    DiagGeom g;
+    g.init(m, n, W);
+    return (size_t)P * (size_t)(g.LQ + g.LC) * (size_t)nch_pad(D) * 16;
+}
+
+size_t rows_lds_bytes(int n, int W, int D, bool f64) {
+    (void)W;
+    const size_t LC = (size_t)n + 2 * kRowPad;
+    return LC * (size_t)nch_pad(D) * 16 + LC * (f64 ? 8 : 4);
+}
 
 // ---------------------------------------------------------------------------
 // Diagonal-pair mapping.
@@ -41,31 +52,11 @@ namespace tcdtw {
 // h = off / 2.  The padding diagonal is the top odd slot when W is even
 // (delta = W + 1) and the bottom even slot when W is odd (delta = -W - 1).
 // ---------------------------------------------------------------------------
-
-struct DiagGeom {
-    int m, n, W, G, h, R, LQ, LC;
-    __host__ __device__ void init(int m_, int n_, int W_) {
-        m = m_; n = n_; W = W_;
-        G = W + 1;
-        h = (W + (W & 1)) / 2;
-        R = (m + n) / 2;           // rounds: anti-diagonals 0 .. m+n-2
-        LQ = R + W + 1;            // query positions, index i = pos + h - W
-        LC = R + W + 2;            // candidate positions, index j = pos - h
-    }
-};
-
-size_t diag_lds_bytes(int m, int n, int W, int D, int P) {
-    DiagGeom g;
-    g.init(m, n, W);
-    return (size_t)P * (size_t)(g.LQ + g.LC) * (size_t)nch_pad(D) * 16;
-}
-
 template <typename T, int NCH, bool SAVE, bool WODD>
 __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
     extern __shared__ float4 smem[];
     const int lane = threadIdx.x;
     const int D = a.D;
-
     int m, n, W, P;
     int64_t xoff0 = 0, yoff0 = 0, soff0 = 0;
     int out0;
@@ -82,136 +73,38 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
     const int G = g.G, h = g.h, R = g.R, LQ = g.LQ, LC = g.LC;
     const int per_pair = (LQ + LC) * NCH;   // float4 per staged pair
 
-    // --- stage the wave's pairs -------------------------------------------
     int npair_here = P;
     if (a.uniform) npair_here = min(P, a.npairs - out0);
     for (int gg = 0; gg < npair_here; ++gg) {
-        const float* xs;
-        const float* ys;
-        if (a.uniform) {
-            xs = a.x + (int64_t)(out0 + gg) * m * D;
-            ys = a.y + (int64_t)(out0 + gg) * n * D;
-        } else {
-            xs = a.x + xoff0;
-            ys = a.y + yoff0;
-        }
+        const float* xs = a.uniform ? a.x + (int64_t)(out0 + gg) * m * D : a.x + xoff0;
+        const float* ys = a.uniform ? a.y + (int64_t)(out0 + gg) * n * D : a.y + yoff0;
         float4* sq = smem + gg * per_pair;
-        float4* sc = sq + LQ * NCH;
-        for (int pos = lane; pos < LQ; pos += kWave) {
-            const int i = pos + h - W;
-            const bool in = (i >= 0 && i < m);
-#pragma unroll
-            for (int k = 0; k < NCH; ++k) {
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int p = 4 * k + e;
-                    v[e] = in ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
-                }
-                sq[k * LQ + pos] = make_float4(v[0], v[1], v[2], v[3]);
-            }
-        }
-        for (int pos = lane; pos < LC; pos += kWave) {
-            const int j = pos - h;
-            const bool in = (j >= 0 && j < n);
-#pragma unroll
-            for (int k = 0; k < NCH; ++k) {
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int p = 4 * k + e;
-                    v[e] = in ? (p < D ? ys[(int64_t)j * D + p] : 0.0f) : -__builtin_inff();
-                }
-                sc[k * LC + pos] = make_float4(v[0], v[1], v[2], v[3]);
-            }
-        }
+        stage_series<NCH>(sq, LQ, g.qfirst(), xs, m, D, __builtin_inff(), lane, kWave);
+        stage_series<NCH>(sq + LQ * NCH, LC, g.cfirst(), ys, n, D, -__builtin_inff(), lane, kWave);
     }
     __syncthreads();
 
-    // --- lane roles ----------------------------------------------------------
     const int grp = lane / G;
     const int lg = lane - grp * G;
     const bool spare = grp >= npair_here;          // lanes without a pair
     const int gsrc = spare ? 0 : grp;              // spare lanes read group 0's data
-    // the padding diagonal (and spare lanes) are forced to +inf
     const bool kill_e = WODD && (lg == 0 || spare);
     const bool kill_o = !WODD && (lg == G - 1);
-
-    const float4* qb = smem + gsrc * per_pair + (W - lg);       // + k*LQ + r
-    const float4* cb = smem + gsrc * per_pair + LQ * NCH + lg;  // + k*LC + r (E), r+1 (O)
+    const float4* qb = smem + gsrc * per_pair + (W - lg);
+    const float4* cb = smem + gsrc * per_pair + LQ * NCH + lg;
 
     const T INF = inf_v<T>();
     T vE = INF, vO = INF;
     if (!spare && lg == h) vE = T(0);              // virtual D(-1,-1)
-
-    float4 qv[NCH], cE[NCH], cO[NCH];
-#pragma unroll
-    for (int k = 0; k < NCH; ++k) cE[k] = cb[k * LC + 0];
-
-    uint32_t cw = 0;
     uint32_t* codes = nullptr;
-    if (SAVE) {
-        const int64_t base = a.uniform ? (int64_t)(out0 + (spare ? 0 : grp)) * a.codes_stride : soff0;
-        codes = a.codes + base;
-    }
+    if (SAVE && !spare)
+        codes = a.codes + (a.uniform ? (int64_t)(out0 + grp) * a.codes_stride : soff0);
+    Abandon ab{nullptr, 0.0f, 0};
+    bool aband = false;
+    diag_core<T, NCH, SAVE, WODD, false>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE, vO, codes, ab,
+                                         aband, 0);
 
-
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            qv[k] = qb[k * LQ + r];
-            cO[k] = cb[k * LC + r + 1];
-        }
-        // E step: anti-diagonal 2r, even slot.  up = own odd slot, left = lane-1's odd slot.
-        {
-            const T cost = point_cost<NCH>(qv, cE, T(0));
-            const T up = vO;
-            const T left = wave_shr1(INF, vO);
-            const T diag = vE;
-            T best;
-            if (SAVE) {
-                uint32_t code = 0;
-                best = diag;
-                if (up < best) { best = up; code = 1; }
-                if (left < best) { best = left; code = 2; }
-                cw |= code << ((r & 7) * 4);
-            } else {
-                best = vmin3(diag, up, left);
-            }
-            T v = add_cost(cost, best);
-            if (kill_e) v = INF;
-            vE = v;
-        }
-        // O step: anti-diagonal 2r+1, odd slot.  up = lane+1's even slot, left = own even slot.
-        {
-            const T cost = point_cost<NCH>(qv, cO, T(0));
-            const T up = wave_shl1(INF, vE);
-            const T left = vE;
-            const T diag = vO;
-            T best;
-            if (SAVE) {
-                uint32_t code = 0;
-                best = diag;
-                if (up < best) { best = up; code = 1; }
-                if (left < best) { best = left; code = 2; }
-                cw |= code << ((r & 7) * 4 + 2);
-            } else {
-                best = vmin3(diag, up, left);
-            }
-            T v = add_cost(cost, best);
-            if (kill_o) v = INF;
-            vO = v;
-        }
-        if (SAVE && ((r & 7) == 7 || r == R - 1)) {
-            if (!spare) codes[(int64_t)(r >> 3) * G + lg] = cw;
-            cw = 0;
-        }
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) cE[k] = cO[k];
-    }
-
-    // --- result: cell (m-1, n-1) on diagonal n-m ------------------------------
-    const int sigma = (n - m) + 2 * h;
+    const int sigma = (n - m) + 2 * h;             // cell (m-1, n-1) lies on diagonal n-m
     if (!spare && lg == (sigma >> 1)) {
         const T v = (sigma & 1) ? vO : vE;
         const int out = a.uniform ? out0 + grp : out0;
@@ -228,15 +121,6 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
 // previous value.  Lane 63 writes its row into the row buffer 63 columns
 // behind lane 0's reads, so one buffer serves both.
 // ---------------------------------------------------------------------------
-
-constexpr int kRowPad = 65;   // candidate / row-buffer positions left of column 0
-
-size_t rows_lds_bytes(int n, int W, int D, bool f64) {
-    (void)W;
-    const size_t LC = (size_t)n + 2 * kRowPad;
-    return LC * (size_t)nch_pad(D) * 16 + LC * (f64 ? 8 : 4);
-}
-
 template <typename T, int NCH, bool SAVE>
 __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
     extern __shared__ float4 smem[];
@@ -254,99 +138,17 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
         m = d.m; n = d.n; W = d.W; out = d.out;
         xoff = d.xoff; yoff = d.yoff; soff = d.saved_off;
     }
-    const float* xs = a.x + xoff;
-    const float* ys = a.y + yoff;
     const int LC = n + 2 * kRowPad;
-    float4* sc = smem;                                   // [k][LC], position = j + kRowPad
-    T* rowbuf = reinterpret_cast<T*>(smem + (size_t)LC * NCH);  // [LC], position = j + kRowPad
-    const T INF = inf_v<T>();
-
-    for (int pos = lane; pos < LC; pos += kWave) {
-        const int j = pos - kRowPad;
-        const bool in = (j >= 0 && j < n);
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int p = 4 * k + e;
-                v[e] = in ? (p < D ? ys[(int64_t)j * D + p] : 0.0f) : -__builtin_inff();
-            }
-            sc[k * LC + pos] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        rowbuf[pos] = (j == -1) ? T(0) : INF;            // row -1: only the virtual D(-1,-1)
-    }
-    __syncthreads();
-
-    const int nb = (m + kRowBlock - 1) / kRowBlock;
-    const int tmax = min(n, 2 * W + kRowBlock) + kRowBlock - 1;
-    const int nwb = (tmax + 15) / 16;
-    T result = INF;
-
-    for (int b = 0; b < nb; ++b) {
-        const int i0 = b * kRowBlock;
-        const int i = i0 + lane;
-        float4 qv[NCH];
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int p = 4 * k + e;
-                v[e] = (i < m) ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
-            }
-            qv[k] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        const int jlo = max(0, i0 - W);
-        const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
-        const int T_b = jhi - jlo + kRowBlock;
-        const int k0 = jlo - i0 + W - 2 * lane;          // band offset k = t + k0 must lie in [0, 2W]
-        const float4* cl = sc + (jlo - lane + kRowPad);  // + k*LC + t
-        const T* rb = rowbuf + (jlo + kRowPad);          // + t
-        T* wb = rowbuf + (jlo - (kRowBlock - 1) + kRowPad);  // lane 63 writes + t
-        T cur = INF;
-        T prevup = (lane == 0) ? rowbuf[jlo - 1 + kRowPad] : INF;
-        const bool last = (b == nb - 1);
-        const int tend = (n - 1) - jlo + (m - 1 - i0);    // step at which lane m-1-i0 reaches column n-1
-        uint32_t cw = 0;
-        uint32_t* codes = SAVE ? a.codes + soff + (int64_t)b * nwb * kWave + lane : nullptr;
-
-
-        for (int t = 0; t < T_b; ++t) {
-            float4 cv[NCH];
-#pragma unroll
-            for (int k = 0; k < NCH; ++k) cv[k] = cl[k * LC + t];
-            const T up = wave_shr1(rb[t], cur);
-            const T diag = prevup;
-            prevup = up;
-            const T left = cur;
-            const T cost = point_cost<NCH>(qv, cv, T(0));
-            T best;
-            if (SAVE) {
-                uint32_t code = 0;
-                best = diag;
-                if (up < best) { best = up; code = 1; }
-                if (left < best) { best = left; code = 2; }
-                cw |= code << ((t & 15) * 2);
-                if ((t & 15) == 15 || t == T_b - 1) {
-                    codes[(int64_t)(t >> 4) * kWave] = cw;
-                    cw = 0;
-                }
-            } else {
-                best = vmin3(diag, up, left);
-            }
-            T v = add_cost(cost, best);
-            const unsigned kb = (unsigned)(t + k0);
-            v = (kb <= (unsigned)(2 * W)) ? v : INF;
-            cur = v;
-            if (lane == kRowBlock - 1) wb[t] = v;
-            if (last && t == tend && lane == m - 1 - i0) result = v;
-        }
-        __syncthreads();
-    }
+    float4* sc = smem;
+    T* rowbuf = reinterpret_cast<T*>(smem + (size_t)LC * NCH);
+    stage_series<NCH>(sc, LC, -kRowPad, a.y + yoff, n, D, -__builtin_inff(), lane, kWave);
+    Abandon ab{nullptr, 0.0f, 0};
+    bool aband = false;
+    const T v = rows_core<T, NCH, SAVE, false>(sc, rowbuf, LC, a.x + xoff, m, n, W, D, lane,
+                                               SAVE ? a.codes + soff : nullptr, ab, aband);
     if (lane == (m - 1) % kRowBlock) {
-        a.dist[out] = (float)result;
-        if (a.dist64) a.dist64[out] = (double)result;
+        a.dist[out] = (float)v;
+        if (a.dist64) a.dist64[out] = (double)v;
     }
 }
 

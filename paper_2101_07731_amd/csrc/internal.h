@@ -78,6 +78,95 @@ hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, int maxW, in
 hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int maxW, int nitems,
                           hipStream_t s);
 
+// ------------------------------------------------------------- index build
+struct IndexBuildArgs {
+    const float* src;         // candidate data as given
+    const int64_t* src_off;   // ragged: device copy of the given offsets
+    const int64_t* dst_off;   // ragged: offsets inside `series`
+    const int32_t* lens;      // ragged: lengths
+    const int64_t* gamma_off; // ragged: offsets inside `gamma`
+    int32_t count, ulen, D, maxlen, ntiles;
+    int64_t total_len;
+    float* series;
+    float* tiles;
+    float* gamma;
+    uint32_t* range_keys;     // 2 words, become float min / max
+};
+hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------- 1-NN
+constexpr int kQT = 8;           // queries per LB_MV tile
+constexpr int kMaxSeeds = 8;
+constexpr int kNumCounters = 8;
+constexpr int kNumStats = 16;
+enum {
+    kStPrunedMv = 0, kStPrunedPc, kStPrunedTi, kStDtwStarted, kStDtwAbandoned, kStRescored,
+    kStCells
+};
+
+// Device pointers of one search (uniform lengths).
+struct KnnPlanDev {
+    const float* Q;       // queries [nq][m][D]
+    const float* C;       // index series [nc][n][D]
+    const float* tiles;   // index tiles
+    int32_t nq, nc, m, n, D, W, ntiles, R, cap;
+    float* env;
+    float* lb;
+    int32_t* seeds;
+    float* seed_dist;
+    uint32_t* list;
+    float* list_dist;
+    int32_t* cnt;
+    uint32_t* glist;
+    int32_t* gcnt;
+    int32_t* prefix;
+    int32_t* counters;
+    unsigned long long* key;
+    unsigned long long* stats;
+};
+
+// Persistent DTW over per-query candidate lists.
+struct KnnDtwArgs {
+    const float* Q;
+    const float* C;
+    int32_t nq, m, n, D, W, P;
+    const uint32_t* list;      // [nq][cap] candidate indices (negative: none)
+    float* list_dist;          // [nq][cap] float32 DTW, +inf when abandoned
+    const int32_t* cnt;        // [nq] list lengths (unless cnt_uniform > 0)
+    int32_t cnt_uniform;
+    int32_t cap;
+    const int32_t* prefix;     // [nq+1] work items per query, prefix sums
+    int32_t* counter;          // work counter
+    unsigned long long* key;   // [nq] packed best-so-far
+    unsigned long long* stats;
+    float gamma;               // float DP relative error bound
+    int32_t abandon;
+};
+
+struct KnnFinalArgs {
+    const float* Q;
+    const float* C;
+    int32_t nq, m, n, D, W, R, cap;
+    const int32_t* seeds;
+    const float* seed_dist;
+    const uint32_t* list;
+    const float* list_dist;
+    const int32_t* cnt;
+    double ratio;              // finalists: float32 DTW <= smallest * ratio
+    int32_t* nn_idx;
+    float* nn_dist;
+    unsigned long long* stats;
+};
+
+hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s);
+hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s);
+hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s);
+hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int use_gate, hipStream_t s);
+hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_knn_finalize(const KnnFinalArgs& a, hipStream_t s);
+size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P);
+size_t knn_final_lds_bytes(int m, int n, int W, int D);
+
 inline int nchunks(int D) { return (D + 3) / 4; }
 // Supported chunk counts (template instantiations); D is padded up to one of them.
 inline int nch_pad(int D) {

@@ -1,0 +1,92 @@
+"""Python binding of the search calls of the C ABI: tc_dtw_build_index,
+tc_dtw_lower_bounds and tc_dtw_knn (argument marshalling only; torch
+provides device memory and the current stream)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+from .pairs import SeriesSet, _stream, _workspace, window_spec
+
+BOUNDS = {"plain": 0, "mv": L.LB_MV, "mv+pc": L.LB_MV | L.LB_PC, "mv+ti": L.LB_MV | L.LB_TI,
+          "mv+pc+ti": L.LB_MV | L.LB_PC | L.LB_TI}
+
+
+class Index:
+    """A candidate set prepared for searches (device buffer owned by this object)."""
+
+    def __init__(self, refs):
+        self.refs = SeriesSet(refs)
+        lib = L.lib()
+        nbytes = lib.tc_dtw_index_bytes(C.byref(self.refs.batch))
+        if nbytes == 0:
+            L.check(L.ERR_INVALID)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.refs.flat.device)
+        self.ix = L.Index()
+        L.check(lib.tc_dtw_build_index(C.byref(self.refs.batch), C.c_void_p(self.buf.data_ptr()), nbytes,
+                                       C.byref(self.ix), _stream()))
+
+    @property
+    def count(self):
+        return self.ix.count
+
+
+def params(window=None, frac=(1, 10), bounds="mv", **kw):
+    """tc_dtw_knn_params from keyword arguments (names as in the C struct)."""
+    p = L.KnnParams()
+    L.lib().tc_dtw_knn_params_default(C.byref(p))
+    p.window = window_spec(window, frac)
+    p.bounds = BOUNDS[bounds] if isinstance(bounds, str) else int(bounds)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown search parameter " + k)
+        setattr(p, k, v)
+    return p
+
+
+def lower_bounds(index, queries, kind="mv", **kw):
+    """Dense bound matrix [nq, nc] of one kind ('mv', 'pc' or 'ti')."""
+    Q = SeriesSet(queries)
+    p = params(bounds="mv", **kw)
+    k = {"mv": L.LB_MV, "pc": L.LB_PC, "ti": L.LB_TI}[kind]
+    lib = L.lib()
+    lb = torch.empty((Q.count, index.count), dtype=torch.float32, device=Q.flat.device)
+    wsb = lib.tc_dtw_lower_bounds_workspace_bytes(C.byref(index.ix), C.byref(Q.batch), C.byref(p), k)
+    if wsb == 0:
+        L.check(L.ERR_INVALID)
+    ws = _workspace(wsb, Q.flat.device)
+    L.check(lib.tc_dtw_lower_bounds(C.byref(index.ix), C.byref(Q.batch), C.byref(p), k,
+                                    C.c_void_p(lb.data_ptr()), C.c_void_p(ws.data_ptr()), wsb, _stream()))
+    return lb
+
+
+def knn(index, queries, stats=False, workspace=None, **kw):
+    """1-NN of every query: (nn_idx int32 [nq], nn_dist float32 [nq][, stats dict])."""
+    Q = SeriesSet(queries)
+    p = params(**kw)
+    lib = L.lib()
+    dev = Q.flat.device
+    idx = torch.empty(Q.count, dtype=torch.int32, device=dev)
+    dist = torch.empty(Q.count, dtype=torch.float32, device=dev)
+    wsb = lib.tc_dtw_knn_workspace_bytes(C.byref(index.ix), C.byref(Q.batch), C.byref(p))
+    if wsb == 0:
+        L.check(lib.tc_dtw_knn(C.byref(index.ix), C.byref(Q.batch), C.byref(p), None, None, None, None, 0,
+                               _stream()))
+    ws = workspace if workspace is not None and workspace.numel() >= wsb else _workspace(wsb, dev)
+    st = L.KnnStats() if stats else None
+    L.check(lib.tc_dtw_knn(C.byref(index.ix), C.byref(Q.batch), C.byref(p), C.c_void_p(idx.data_ptr()),
+                           C.c_void_p(dist.data_ptr()), C.byref(st) if st is not None else None,
+                           C.c_void_p(ws.data_ptr()), wsb, _stream()))
+    if not stats:
+        return idx, dist
+    sd = {f: getattr(st, f) for f, _ in L.KnnStats._fields_ if f != "stage_ms"}
+    sd["stage_ms"] = list(st.stage_ms)
+    return idx, dist, sd
+
+
+def knn_workspace_bytes(index, queries, **kw):
+    Q = SeriesSet(queries)
+    p = params(**kw)
+    return L.lib().tc_dtw_knn_workspace_bytes(C.byref(index.ix), C.byref(Q.batch), C.byref(p))

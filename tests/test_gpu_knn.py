@@ -1,0 +1,136 @@
+"""1-NN search and dense lower bounds on the GPU against the FP64 oracle.
+
+Bar: identical nearest-neighbour indices (ties to the lowest index) and
+distances equal to the oracle's float64 value rounded to float32 (the
+finalists are re-scored in float64 in the oracle's operation order).
+Bounds: never above the oracle's FP64 bound (they are rounded down) and
+within the documented deflation (n*D + 4) 2^-24 of it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2101_07731_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def run_knn(dev, Q, Cs, **kw):
+    from paper_2101_07731_amd import search
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    idx, dist, st = search.knn(ix, torch.from_numpy(Q).to(dev), stats=True, **kw)
+    return idx.cpu().numpy(), dist.cpu().numpy(), st
+
+
+def check_against_oracle(idx, dist, Q, Cs, num, den):
+    ri, rd = O.knn_exhaustive(Q, Cs, num=num, den=den)
+    np.testing.assert_array_equal(idx, ri)
+    np.testing.assert_array_equal(dist, rd.astype(np.float32))
+
+
+def test_plain_config_shape(dev):
+    """Plain 1-NN: 64 queries x 256 references, length 64, d=3, window 10%."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.plain_knn()
+    for bounds in ("plain", "mv"):
+        say("knn plain shape", bounds)
+        idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds=bounds)
+        check_against_oracle(idx, dist, Q, Cs, 1, 10)
+        assert st["pairs"] == 64 * 256
+        if bounds == "plain":
+            assert st["dtw_started"] == 64 * 256 and st["pruned_mv"] == 0
+        else:
+            assert st["pruned_mv"] + st["dtw_started"] == 64 * 256
+
+
+@pytest.mark.parametrize("frac", [(1, 20), (1, 10), (1, 5)])
+def test_cascade_prototypes_with_ties(dev, frac):
+    """Prototype data (near neighbours exist) plus exact duplicate references
+    so that ties must go to the lowest index."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn(nq=40, nc=600, T=96, D=8, seed=21)
+    Cs = np.concatenate([Cs, Cs[::7]])                    # duplicates at higher indices
+    Q = np.concatenate([Q, Cs[[3, 100, 599]]])            # queries equal to a reference: distance 0
+    say("knn cascade", frac, Q.shape, Cs.shape)
+    for seed_r in (1, 4, 8):
+        idx, dist, st = run_knn(dev, Q, Cs, frac=frac, bounds="mv", seed_r=seed_r)
+        check_against_oracle(idx, dist, Q, Cs, *frac)
+        assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
+    assert idx[-3] == 3 and dist[-3] == 0.0
+
+
+def test_cascade_repeatable(dev):
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn(nq=30, nc=500, T=64, D=4, seed=22)
+    a = run_knn(dev, Q, Cs, frac=(1, 10))
+    b = run_knn(dev, Q, Cs, frac=(1, 10))
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("case", [(5, 60, 700, 3, (1, 10)), (4, 40, 300, 16, (1, 4))],
+                         ids=["W70_d3", "W75_d16"])
+def test_row_mapping_search(dev, case):
+    """Bands wider than 63 use the row-systolic DTW."""
+    from paper_2101_07731_amd import synth
+    nq, nc, T, D, frac = case
+    Q, Cs = synth.long_knn(nq=nq, nc=nc, T=T, D=D, seed=23)
+    say("knn rows", case)
+    for bounds in ("plain", "mv"):
+        idx, dist, _ = run_knn(dev, Q, Cs, frac=frac, bounds=bounds)
+        check_against_oracle(idx, dist, Q, Cs, *frac)
+
+
+def test_unequal_query_and_candidate_lengths(dev):
+    rng = np.random.default_rng(24)
+    Q = np.cumsum(rng.standard_normal((12, 50, 3)), 1).astype(np.float32)
+    Cs = np.cumsum(rng.standard_normal((200, 70, 3)), 1).astype(np.float32)
+    idx, dist, _ = run_knn(dev, Q, Cs, window=5, frac=None)
+    ri, rd = O.knn_exhaustive(Q, Cs, window=5)
+    np.testing.assert_array_equal(idx, ri)
+    np.testing.assert_array_equal(dist, rd.astype(np.float32))
+
+
+def test_lb_mv_dense_matrix(dev):
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.cascade_knn(nq=19, nc=150, T=80, D=8, seed=25)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="mv", frac=(1, 10)).cpu().numpy()
+    W = O.window_eff(80, 80, 0, 1, 10)
+    ref = np.array([[O.lb_mv(q, c, W) for c in Cs] for q in Q])
+    assert np.all(lb.astype(np.float64) <= ref * (1 + 1e-12))
+    # deflation (E+3) u plus the float32 accumulation error (at most E+2 roundings), E = n*D
+    slack = 2 * (80 * 8 + 4) * 2.0 ** -24 * 1.01 + 2e-7
+    assert np.all(lb.astype(np.float64) >= ref * (1 - slack) - 1e-30)
+
+
+def test_full_size_sampled(dev):
+    """The benchmark's workload (1000 queries x 10000 references, length 256,
+    d=8, window 10%) in the same launch; every query's result is checked for
+    a sample of queries against the exhaustive FP64 oracle."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn()
+    say("knn full size", Q.shape, Cs.shape)
+    idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds="mv")
+    say("stats", st)
+    sample = np.array([0, 1, 2, 137, 500, 998, 999])
+    ri, rd = O.knn_exhaustive(Q[sample], Cs, num=1, den=10)
+    np.testing.assert_array_equal(idx[sample], ri)
+    np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
+    assert np.all((idx >= 0) & (idx < len(Cs)))
+    assert st["pruned_mv"] + st["dtw_started"] == 1000 * 10000
