@@ -93,6 +93,16 @@ int window_eff(int m, int n, tc_dtw_window w) {
     return (int)W;
 }
 
+int64_t band_cells(int m, int n, int W) {
+    int64_t c = 0;
+    for (int i = 0; i < m; ++i) {
+        const int lo = i - W > 0 ? i - W : 0;
+        const int hi = i + W < n - 1 ? i + W : n - 1;
+        if (hi >= lo) c += hi - lo + 1;
+    }
+    return c;
+}
+
 }  // namespace tcdtw
 
 extern "C" {

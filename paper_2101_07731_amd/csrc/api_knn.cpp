@@ -66,10 +66,10 @@ struct KnnPlan {
     int nq, nc, m, n, D, W, R, P, cap, ntiles;
     bool plain, abandon, gate;
     size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
-        o_counters, o_key, o_stats, bytes;
+        o_items, o_counters, o_key, o_stats, bytes;
 };
 
-static int list_pairs_per_wave(int W) { return W <= kDiagMaxW ? kWave / (W + 1) : 1; }
+
 
 static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* qb, const tc_dtw_knn_params* p,
                                    KnnPlan& K, HostSet& Qs) {
@@ -90,7 +90,7 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.abandon = !K.plain && p->early_abandon != 0;
     K.gate = (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)) != 0;
     K.R = K.plain ? 0 : std::min(std::min(p->seed_r > 0 ? p->seed_r : 4, kMaxSeeds), K.nc);
-    K.P = list_pairs_per_wave(K.W);
+    K.P = knn_dtw_max_pairs(K.W, K.D);
     K.cap = K.nc;
     K.ntiles = ix->ntiles;
     Carve c(nullptr, 0);
@@ -106,6 +106,7 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.o_glist = at(K.gate ? (size_t)K.nq * K.cap * 4 : 0);
     K.o_gcnt = at((size_t)K.nq * 4);
     K.o_prefix = at((size_t)(K.nq + 1) * 4);
+    K.o_items = 0;   // placed after P is final (below)
     K.o_counters = at(kNumCounters * 4);
     K.o_key = at((size_t)K.nq * 8);
     K.o_stats = at(kNumStats * 8);
@@ -114,6 +115,9 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     if (knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, 1) > lim || knn_final_lds_bytes(K.m, K.n, K.W, K.D) > lim)
         return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
     while (K.P > 1 && knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, K.P) > lim) --K.P;
+    // work items: chunks of P list entries per query (seeds need fewer)
+    K.o_items = at((size_t)K.nq * ((K.cap + K.P - 1) / K.P) * 4);
+    K.bytes = c.need();
     return TC_DTW_OK;
 }
 
@@ -136,6 +140,7 @@ static KnnPlanDev dev_plan(const KnnPlan& K, const tc_dtw_index* ix, const HostS
     d.glist = K.gate ? reinterpret_cast<uint32_t*>(ws + K.o_glist) : nullptr;
     d.gcnt = reinterpret_cast<int32_t*>(ws + K.o_gcnt);
     d.prefix = reinterpret_cast<int32_t*>(ws + K.o_prefix);
+    d.item_query = reinterpret_cast<int32_t*>(ws + K.o_items);
     d.counters = reinterpret_cast<int32_t*>(ws + K.o_counters);
     d.key = reinterpret_cast<unsigned long long*>(ws + K.o_key);
     d.stats = reinterpret_cast<unsigned long long*>(ws + K.o_stats);
@@ -147,7 +152,8 @@ static float dp_gamma(int m, int n, int D) {
 }
 
 static int persistent_blocks(size_t lds, int64_t max_items) {
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 163840 / std::max<size_t>(lds, 1)));
+    // one-wave blocks: up to 6 per SIMD (register file), fewer when LDS runs out
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(24, 163840 / std::max<size_t>(lds, 1)));
     int64_t nb = (int64_t)256 * per_cu;
     if (max_items < nb) nb = std::max<int64_t>(max_items, 1);
     return (int)nb;
@@ -172,11 +178,13 @@ static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, b
         a.cap = K.cap;
     }
     a.prefix = d.prefix;
+    a.item_query = d.item_query;
     a.counter = d.counters + (seeds ? 0 : 1);
     a.key = d.key;
     a.stats = d.stats;
     a.gamma = dp_gamma(K.m, K.n, K.D);
     a.abandon = abandon ? 1 : 0;
+    a.band_cells = band_cells(K.m, K.n, K.W);
     return a;
 }
 
@@ -323,6 +331,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         if ((e = launch_topr(d, s)) != hipSuccess) return hip_fail(e, "seed selection");
         const KnnDtwArgs a = list_args(K, d, true, false);
         const int64_t items = (int64_t)K.nq * ((K.R + K.P - 1) / K.P);
+        if ((e = launch_chunk_scan(a, s)) != hipSuccess) return hip_fail(e, "seed scan");
         if ((e = launch_dtw_lists(a, persistent_blocks(lds, items), s)) != hipSuccess) return hip_fail(e, "seed dtw");
     }
     mark(3);
@@ -332,10 +341,11 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     if ((e = launch_compact(d, K.plain ? 0.0 : keep, gate_e2, K.gate ? 1 : 0, s)) != hipSuccess)
         return hip_fail(e, "compaction");
     mark(4);
-    mark(5);
     {
         const KnnDtwArgs a = list_args(K, d, false, K.abandon);
         const int64_t items = (int64_t)K.nq * ((K.nc + K.P - 1) / K.P);
+        if ((e = launch_chunk_scan(a, s)) != hipSuccess) return hip_fail(e, "dtw scan");
+        mark(5);
         if ((e = launch_dtw_lists(a, persistent_blocks(lds, items), s)) != hipSuccess) return hip_fail(e, "dtw");
     }
     mark(6);
@@ -346,6 +356,8 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         f.nq = K.nq; f.m = K.m; f.n = K.n; f.D = K.D; f.W = K.W; f.R = K.R; f.cap = K.cap;
         f.seeds = d.seeds; f.seed_dist = d.seed_dist;
         f.list = d.list; f.list_dist = d.list_dist; f.cnt = d.cnt;
+        f.gcnt = nullptr;
+        f.nc = K.nc;
         const double g = dp_gamma(K.m, K.n, K.D);
         f.ratio = (1.0 + g) / (1.0 - g) * (1.0 + 1e-9);
         f.nn_idx = nn_idx; f.nn_dist = nn_dist;

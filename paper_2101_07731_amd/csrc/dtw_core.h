@@ -10,12 +10,16 @@
 
 namespace tcdtw {
 
+// The dynamic LDS of every kernel of the library, addressed by float4 index
+// so that every access is known to be an LDS access.
+extern __shared__ float4 lds4[];
+
 // ------------------------------------------------------------------ staging
 // Copies series `src` (row-major [len][D]) into LDS as [k][L][4] chunks for
 // positions pos = 0..L-1 holding series index t = pos + first; positions
 // outside [0, len) get `sentinel` in every component.
 template <int NCH>
-__device__ __forceinline__ void stage_series(float4* dst, int L, int first, const float* src, int len,
+__device__ __forceinline__ void stage_series(int dst, int L, int first, const float* src, int len,
                                              int D, float sentinel, int lane, int nlanes) {
     for (int pos = lane; pos < L; pos += nlanes) {
         const int t = pos + first;
@@ -28,7 +32,7 @@ __device__ __forceinline__ void stage_series(float4* dst, int L, int first, cons
                 const int p = 4 * k + e;
                 v[e] = in ? (p < D ? src[(int64_t)t * D + p] : 0.0f) : sentinel;
             }
-            dst[k * L + pos] = make_float4(v[0], v[1], v[2], v[3]);
+            lds4[dst + k * L + pos] = make_float4(v[0], v[1], v[2], v[3]);
         }
     }
 }
@@ -70,101 +74,160 @@ __device__ __forceinline__ float abandon_threshold(float bsf, float gamma) {
     return f;
 }
 
+// One round of the diagonal mapping: E step on anti-diagonal 2r with the
+// candidate point cin, O step on 2r+1 with the candidate point loaded into
+// cout (which the next round uses as its cin).
+template <typename T, int NCH, bool SAVE, bool WODD>
+__device__ __forceinline__ void diag_round(const int (&qk)[NCH], const int (&ck)[NCH],
+                                           int off, const float4 (&cin)[NCH], float4 (&cout)[NCH],
+                                           bool kill_e, bool kill_o, T& vE, T& vO, uint32_t& cw,
+                                           int shift) {
+    const T INF = inf_v<T>();
+    float4 qv[NCH];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        qv[k] = lds4[qk[k] + off];
+        cout[k] = lds4[ck[k] + off + 1];
+    }
+    {   // E step: up = own odd slot, left = lane-1's odd slot, diag = own even slot
+        const T cost = point_cost<NCH>(qv, cin, T(0));
+        const T up = vO;
+        const T left = wave_shr1(INF, vO);
+        T best;
+        if (SAVE) {
+            uint32_t code = 0;
+            best = vE;
+            if (up < best) { best = up; code = 1; }
+            if (left < best) { best = left; code = 2; }
+            cw |= code << shift;
+        } else {
+            best = vmin3(vE, up, left);
+        }
+        T v = add_cost(cost, best);
+        if (WODD && kill_e) v = INF;
+        vE = v;
+    }
+    {   // O step: up = lane+1's even slot, left = own even slot, diag = own odd slot
+        const T cost = point_cost<NCH>(qv, cout, T(0));
+        const T up = wave_shl1(INF, vE);
+        const T left = vE;
+        T best;
+        if (SAVE) {
+            uint32_t code = 0;
+            best = vO;
+            if (up < best) { best = up; code = 1; }
+            if (left < best) { best = left; code = 2; }
+            cw |= code << (shift + 2);
+        } else {
+            best = vmin3(vO, up, left);
+        }
+        T v = add_cost(cost, best);
+        if (!WODD && kill_o) v = INF;
+        vO = v;
+    }
+}
+
 // One wave, groups of G lanes each evaluating one pair.  qb / cb: this
-// lane's LDS bases (position offsets already applied, see dtw_fwd.hip).
-// Returns the lane's slot values after the last round through vE / vO;
-// `aband` is set for lanes of abandoned groups.
+// lane's LDS float4 indices (position offsets already applied, see
+// dtw_fwd.hip); chunk k of the query lies LQ float4 further, of the
+// candidate LC.
+// Runs rounds 0..R-1 (fewer when every group is abandoned) and returns the
+// number of rounds run; vE / vO hold the lane's slot values afterwards and
+// `aband` is set for lanes of abandoned groups.  Four rounds per iteration
+// alternate two candidate buffers, so no point is copied between rounds.
 template <typename T, int NCH, bool SAVE, bool WODD, bool ABANDON>
-__device__ __forceinline__ void diag_core(const float4* qb, int LQ, const float4* cb, int LC, int R,
+__device__ __forceinline__ int diag_core(int qb, int LQ, int cb, int LC, int R,
                                           int G, int lg, bool kill_e, bool kill_o, T& vE, T& vO,
                                           uint32_t* codes, const Abandon& ab, bool& aband,
                                           uint64_t grp_mask) {
-    const T INF = inf_v<T>();
-    float4 qv[NCH], cE[NCH], cO[NCH];
+    int qk[NCH];
+    int ck[NCH];
 #pragma unroll
-    for (int k = 0; k < NCH; ++k) cE[k] = cb[k * LC + 0];
+    for (int k = 0; k < NCH; ++k) {
+        qk[k] = qb + k * LQ;
+        ck[k] = cb + k * LC;
+    }
+    float4 cA[NCH], cB[NCH];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) cA[k] = lds4[ck[k]];
     uint32_t cw = 0;
     float thr = __builtin_inff();
-    if (ABANDON) thr = abandon_threshold(bsf_from_key(__hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), ab.gamma);
-
-    for (int r = 0; r < R; ++r) {
+    unsigned long long pend = 0;
+    if (ABANDON) {
+        thr = abandon_threshold(bsf_from_key(__hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+                                ab.gamma);
+        pend = __hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int r = 0;
+    for (; r + 4 <= R; r += 4) {
+        const int sh = (r & 4) * 4;
+        diag_round<T, NCH, SAVE, WODD>(qk, ck, 0, cA, cB, kill_e, kill_o, vE, vO, cw, sh + 0);
+        diag_round<T, NCH, SAVE, WODD>(qk, ck, 1, cB, cA, kill_e, kill_o, vE, vO, cw, sh + 4);
+        diag_round<T, NCH, SAVE, WODD>(qk, ck, 2, cA, cB, kill_e, kill_o, vE, vO, cw, sh + 8);
+        diag_round<T, NCH, SAVE, WODD>(qk, ck, 3, cB, cA, kill_e, kill_o, vE, vO, cw, sh + 12);
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
-            qv[k] = qb[k * LQ + r];
-            cO[k] = cb[k * LC + r + 1];
+            qk[k] += 4;
+            ck[k] += 4;
         }
-        {   // E step: anti-diagonal 2r.  up = own odd slot, left = lane-1's odd slot.
-            const T cost = point_cost<NCH>(qv, cE, T(0));
-            const T up = vO;
-            const T left = wave_shr1(INF, vO);
-            const T diag = vE;
-            T best;
-            if (SAVE) {
-                uint32_t code = 0;
-                best = diag;
-                if (up < best) { best = up; code = 1; }
-                if (left < best) { best = left; code = 2; }
-                cw |= code << ((r & 7) * 4);
-            } else {
-                best = vmin3(diag, up, left);
-            }
-            T v = add_cost(cost, best);
-            if (kill_e) v = INF;
-            vE = v;
+        if (SAVE && (r & 4)) {
+            if (codes) codes[(int64_t)(r >> 3) * G + lg] = cw;
+            cw = 0;
         }
-        {   // O step: anti-diagonal 2r+1.  up = lane+1's even slot, left = own even slot.
-            const T cost = point_cost<NCH>(qv, cO, T(0));
-            const T up = wave_shl1(INF, vE);
-            const T left = vE;
-            const T diag = vO;
-            T best;
-            if (SAVE) {
-                uint32_t code = 0;
-                best = diag;
-                if (up < best) { best = up; code = 1; }
-                if (left < best) { best = left; code = 2; }
-                cw |= code << ((r & 7) * 4 + 2);
-            } else {
-                best = vmin3(diag, up, left);
+        if (ABANDON && ((r + 4) & 15) == 0 && r + 4 < R) {
+            // every warping path crosses anti-diagonal 2r+6 or 2r+7 (steps advance i+j by 1 or 2)
+            const bool over = (float)vmin(vE, vO) > thr;
+            const uint64_t bal = __ballot(over);
+            if ((bal & grp_mask) == grp_mask) aband = true;
+            if ((bal & ab.valid_mask) == ab.valid_mask) {
+                r += 4;
+                return __builtin_amdgcn_readfirstlane(r);
             }
-            T v = add_cost(cost, best);
-            if (kill_o) v = INF;
-            vO = v;
+            // the key read at the previous check (a best-so-far only decreases)
+            thr = abandon_threshold(bsf_from_key(pend), ab.gamma);
+            pend = __hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    for (; r < R; ++r) {
+        diag_round<T, NCH, SAVE, WODD>(qk, ck, 0, cA, cB, kill_e, kill_o, vE, vO, cw, (r & 7) * 4);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            qk[k] += 1;
+            ck[k] += 1;
+            cA[k] = cB[k];
         }
         if (SAVE && ((r & 7) == 7 || r == R - 1)) {
             if (codes) codes[(int64_t)(r >> 3) * G + lg] = cw;
             cw = 0;
         }
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) cE[k] = cO[k];
-        if (ABANDON && (r & 15) == 15 && r + 1 < R) {
-            // every path crosses anti-diagonal 2r or 2r+1 (steps advance i+j by 1 or 2)
-            const bool over = (float)vmin(vE, vO) > thr;
-            const uint64_t bal = __ballot(over);
-            if ((bal & grp_mask) == grp_mask) aband = true;
-            if ((bal & ab.valid_mask) == ab.valid_mask) break;
-            thr = abandon_threshold(bsf_from_key(__hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), ab.gamma);
-        }
     }
+    if (SAVE && (R & 3) == 0 && (R & 4)) {
+        // R = 8k + 4 with no single-round tail: rounds 8k .. 8k+3 are not stored yet
+        if (codes) codes[(int64_t)((R - 1) >> 3) * G + lg] = cw;
+    }
+    return R;
 }
 
 // ------------------------------------------------------------- row-systolic
 constexpr int kRowPad = 65;   // candidate / row-buffer positions left of column 0
 
-// One pair per wave.  sc: staged candidate [k][LC] (position j + kRowPad),
-// rowbuf: LC values of type T.  xs: query rows in global memory.
+// One pair per wave.  sc: LDS float4 index of the staged candidate [k][LC]
+// (position j + kRowPad); the row buffer (LC values of type T) follows it.
+// xs: query rows in global memory.
 // Returns the DTW value in the lane m-1 mod 64 (others undefined).
 template <typename T, int NCH, bool SAVE, bool ABANDON>
-__device__ __forceinline__ T rows_core(const float4* sc, T* rowbuf, int LC, const float* xs, int m,
+__device__ __forceinline__ T rows_core(int sc, int LC, const float* xs, int m,
                                        int n, int W, int D, int lane, uint32_t* codes,
-                                       const Abandon& ab, bool& aband) {
+                                       const Abandon& ab, bool& aband, int* blocks_done = nullptr) {
     const T INF = inf_v<T>();
+    T* rowbuf = reinterpret_cast<T*>(lds4 + sc + (size_t)LC * NCH);
     for (int pos = lane; pos < LC; pos += kWave) rowbuf[pos] = (pos - kRowPad == -1) ? T(0) : INF;
     __syncthreads();
     const int nb = (m + kRowBlock - 1) / kRowBlock;
     const int band = min(n, 2 * W + kRowBlock);
     const int nwb = (band + kRowBlock - 1 + 15) / 16;
     T result = INF;
+    if (blocks_done) *blocks_done = nb;
     for (int b = 0; b < nb; ++b) {
         const int i0 = b * kRowBlock;
         const int i = i0 + lane;
@@ -183,9 +246,9 @@ __device__ __forceinline__ T rows_core(const float4* sc, T* rowbuf, int LC, cons
         const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
         const int T_b = jhi - jlo + kRowBlock;
         const int k0 = jlo - i0 + W - 2 * lane;          // band offset k = t + k0 must lie in [0, 2W]
-        const float4* cl = sc + (jlo - lane + kRowPad);  // + k*LC + t
-        const T* rb = rowbuf + (jlo + kRowPad);          // + t
-        T* wb = rowbuf + (jlo - (kRowBlock - 1) + kRowPad);
+        const int cl = sc + (jlo - lane + kRowPad);      // + k*LC + t
+        const int rb = jlo + kRowPad;                    // rowbuf index + t
+        const int wb = jlo - (kRowBlock - 1) + kRowPad;  // lane 63 writes rowbuf[wb + t]
         T cur = INF;
         T prevup = (lane == 0) ? rowbuf[jlo - 1 + kRowPad] : INF;
         const bool last = (b == nb - 1);
@@ -195,8 +258,8 @@ __device__ __forceinline__ T rows_core(const float4* sc, T* rowbuf, int LC, cons
         for (int t = 0; t < T_b; ++t) {
             float4 cv[NCH];
 #pragma unroll
-            for (int k = 0; k < NCH; ++k) cv[k] = cl[k * LC + t];
-            const T up = wave_shr1(rb[t], cur);
+            for (int k = 0; k < NCH; ++k) cv[k] = lds4[cl + k * LC + t];
+            const T up = wave_shr1(rowbuf[rb + t], cur);
             const T diag = prevup;
             prevup = up;
             const T left = cur;
@@ -219,7 +282,7 @@ __device__ __forceinline__ T rows_core(const float4* sc, T* rowbuf, int LC, cons
             const unsigned kb = (unsigned)(t + k0);
             v = (kb <= (unsigned)(2 * W)) ? v : INF;
             cur = v;
-            if (lane == kRowBlock - 1) wb[t] = v;
+            if (lane == kRowBlock - 1) rowbuf[wb + t] = v;
             if (last && t == tend && lane == m - 1 - i0) result = v;
         }
         __syncthreads();
@@ -231,7 +294,11 @@ __device__ __forceinline__ T rows_core(const float4* sc, T* rowbuf, int LC, cons
             const float thr = abandon_threshold(
                 bsf_from_key(__hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), ab.gamma);
             const bool over = (float)mn > thr;
-            if (__ballot(over) == ~0ull) { aband = true; break; }
+            if (__ballot(over) == ~0ull) {
+                aband = true;
+                if (blocks_done) *blocks_done = b + 1;
+                break;
+            }
         }
     }
     return result;

@@ -54,7 +54,6 @@ size_t rows_lds_bytes(int n, int W, int D, bool f64) {
 // ---------------------------------------------------------------------------
 template <typename T, int NCH, bool SAVE, bool WODD>
 __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
-    extern __shared__ float4 smem[];
     const int lane = threadIdx.x;
     const int D = a.D;
     int m, n, W, P;
@@ -78,7 +77,7 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
     for (int gg = 0; gg < npair_here; ++gg) {
         const float* xs = a.uniform ? a.x + (int64_t)(out0 + gg) * m * D : a.x + xoff0;
         const float* ys = a.uniform ? a.y + (int64_t)(out0 + gg) * n * D : a.y + yoff0;
-        float4* sq = smem + gg * per_pair;
+        const int sq = gg * per_pair;
         stage_series<NCH>(sq, LQ, g.qfirst(), xs, m, D, __builtin_inff(), lane, kWave);
         stage_series<NCH>(sq + LQ * NCH, LC, g.cfirst(), ys, n, D, -__builtin_inff(), lane, kWave);
     }
@@ -90,8 +89,8 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
     const int gsrc = spare ? 0 : grp;              // spare lanes read group 0's data
     const bool kill_e = WODD && (lg == 0 || spare);
     const bool kill_o = !WODD && (lg == G - 1);
-    const float4* qb = smem + gsrc * per_pair + (W - lg);
-    const float4* cb = smem + gsrc * per_pair + LQ * NCH + lg;
+    const int qb = gsrc * per_pair + (W - lg);
+    const int cb = gsrc * per_pair + LQ * NCH + lg;
 
     const T INF = inf_v<T>();
     T vE = INF, vO = INF;
@@ -123,7 +122,6 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T, int NCH, bool SAVE>
 __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
-    extern __shared__ float4 smem[];
     const int lane = threadIdx.x;
     const int D = a.D;
     int m, n, W, out;
@@ -139,12 +137,10 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
         xoff = d.xoff; yoff = d.yoff; soff = d.saved_off;
     }
     const int LC = n + 2 * kRowPad;
-    float4* sc = smem;
-    T* rowbuf = reinterpret_cast<T*>(smem + (size_t)LC * NCH);
-    stage_series<NCH>(sc, LC, -kRowPad, a.y + yoff, n, D, -__builtin_inff(), lane, kWave);
+    stage_series<NCH>(0, LC, -kRowPad, a.y + yoff, n, D, -__builtin_inff(), lane, kWave);
     Abandon ab{nullptr, 0.0f, 0};
     bool aband = false;
-    const T v = rows_core<T, NCH, SAVE, false>(sc, rowbuf, LC, a.x + xoff, m, n, W, D, lane,
+    const T v = rows_core<T, NCH, SAVE, false>(0, LC, a.x + xoff, m, n, W, D, lane,
                                                SAVE ? a.codes + soff : nullptr, ab, aband);
     if (lane == (m - 1) % kRowBlock) {
         a.dist[out] = (float)v;

@@ -120,6 +120,7 @@ struct KnnPlanDev {
     uint32_t* glist;
     int32_t* gcnt;
     int32_t* prefix;
+    int32_t* item_query;
     int32_t* counters;
     unsigned long long* key;
     unsigned long long* stats;
@@ -136,11 +137,13 @@ struct KnnDtwArgs {
     int32_t cnt_uniform;
     int32_t cap;
     const int32_t* prefix;     // [nq+1] work items per query, prefix sums
+    const int32_t* item_query; // [items] query of each work item
     int32_t* counter;          // work counter
     unsigned long long* key;   // [nq] packed best-so-far
     unsigned long long* stats;
     float gamma;               // float DP relative error bound
     int32_t abandon;
+    int64_t band_cells;        // cells of one pair's band (statistics)
 };
 
 struct KnnFinalArgs {
@@ -152,6 +155,8 @@ struct KnnFinalArgs {
     const uint32_t* list;
     const float* list_dist;
     const int32_t* cnt;
+    const int32_t* gcnt;       // advanced-bound list lengths (entries pruned later are counted there)
+    int32_t nc;
     double ratio;              // finalists: float32 DTW <= smallest * ratio
     int32_t* nn_idx;
     float* nn_dist;
@@ -162,9 +167,15 @@ hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s);
 hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s);
 hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s);
 hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int use_gate, hipStream_t s);
+hipError_t launch_chunk_scan(const KnnDtwArgs& a, hipStream_t s);
 hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s);
+int64_t band_cells(int m, int n, int W);
 hipError_t launch_knn_finalize(const KnnFinalArgs& a, hipStream_t s);
 size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P);
+int knn_dtw_max_pairs(int W, int D);
+// Ring size of the diagonal 1-NN kernel: the live window W + 5 plus one
+// refill of RS / 4 positions must fit.
+inline int ring_size(int W) { return W <= 27 ? 64 : 128; }
 size_t knn_final_lds_bytes(int m, int n, int W, int D);
 
 inline int nchunks(int D) { return (D + 3) / 4; }

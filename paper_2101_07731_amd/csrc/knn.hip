@@ -180,14 +180,16 @@ __global__ __launch_bounds__(256) void k_compact(const float* __restrict__ lb, i
     const bool pruned = live && (v * keep > bsf);
     const bool gated = live && !pruned && use_gate && (v > gate_e2 * bsf);
     const bool todtw = live && !pruned && !gated;
-    const uint64_t bd = __ballot(todtw), bg = __ballot(gated), bp = __ballot(pruned);
+    const uint64_t bd = __ballot(todtw), bg = __ballot(gated);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int based = 0, baseg = 0;
+    // the pruned count is derived per query at the end (pairs - seeds - listed)
     if (lane == 0) {
         if (bd) based = atomicAdd(&cnt[q], __popcll(bd));
         if (bg) baseg = atomicAdd(&gcnt[q], __popcll(bg));
-        if (bp) atomicAdd(&stats[kStPrunedMv], (unsigned long long)__popcll(bp));
     }
+    (void)pruned;
+    (void)stats;
     based = __shfl(based, 0);
     baseg = __shfl(baseg, 0);
     if (todtw) list[(int64_t)q * cap + based + __popcll(bd & below)] = (uint32_t)r;
@@ -220,6 +222,15 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const int32_t* cnt, int cnt
     }
 }
 
+// item_query[item] = q for the work items of query q (one block per query).
+__global__ __launch_bounds__(256) void k_item_map(const int32_t* __restrict__ prefix, int nq,
+                                                  int32_t* __restrict__ item_query) {
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int b = prefix[q], e = prefix[q + 1];
+        for (int t = b + threadIdx.x; t < e; t += blockDim.x) item_query[t] = q;
+    }
+}
+
 // --------------------------------------------------------------- DTW lists
 // A wave takes work items (query q, chunk of P list entries) from a global
 // counter until none are left: persistent waves balance the uneven
@@ -243,17 +254,17 @@ __device__ __forceinline__ void publish(const KnnDtwArgs& a, int q, int ref, flo
 
 template <int NCH, bool WODD>
 __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
-    extern __shared__ float4 smem[];
     const int lane = threadIdx.x;
     DiagGeom g;
     g.init(a.m, a.n, a.W);
     const int G = g.G, h = g.h, R = g.R, LQ = g.LQ, LC = g.LC, P = a.P;
-    float4* sq = smem;
-    float4* scs = smem + LQ * NCH;
+    const int sq = 0;
+    const int scs = LQ * NCH;
     const int grp = lane / G;
     const int lg = lane - grp * G;
     const int total = a.prefix[a.nq];
     int staged_q = -1;
+    unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
         int item = 0;
         if (lane == 0) item = atomicAdd(a.counter, 1);
@@ -280,20 +291,21 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
         const int gsrc = spare ? 0 : grp;
         const bool kill_e = WODD && (lg == 0 || spare);
         const bool kill_o = !WODD && (lg == G - 1);
-        const float4* qb = sq + (a.W - lg);
-        const float4* cb = scs + gsrc * LC * NCH + lg;
+        const int qb = sq + (a.W - lg);
+        const int cb = scs + gsrc * LC * NCH + lg;
         float vE = __builtin_inff(), vO = __builtin_inff();
         if (!spare && lg == h) vE = 0.0f;
         const uint64_t valid_mask = (np * G >= 64) ? ~0ull : ((1ull << (np * G)) - 1);
         const uint64_t gm = spare ? 0ull : (((G >= 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G));
         Abandon ab{a.key + q, a.gamma, valid_mask};
         bool aband = false;
+        int rounds;
         if (a.abandon)
-            diag_core<float, NCH, false, WODD, true>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE, vO,
-                                                     nullptr, ab, aband, gm);
+            rounds = diag_core<float, NCH, false, WODD, true>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE,
+                                                              vO, nullptr, ab, aband, gm);
         else
-            diag_core<float, NCH, false, WODD, false>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE, vO,
-                                                      nullptr, ab, aband, gm);
+            rounds = diag_core<float, NCH, false, WODD, false>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE,
+                                                               vO, nullptr, ab, aband, gm);
         const int sigma = (a.n - a.m) + 2 * h;
         const int myref = spare ? -1 : (int)a.list[(int64_t)q * a.cap + base + grp];
         if (!spare && lg == (sigma >> 1)) {
@@ -307,27 +319,225 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
         }
         const uint64_t bstart = __ballot(!spare && lg == 0 && myref >= 0);
         const uint64_t bab = __ballot(aband && !spare && lg == 0 && myref >= 0);
-        if (lane == 0) {
-            atomicAdd(&a.stats[kStDtwStarted], (unsigned long long)__popcll(bstart));
-            if (bab) atomicAdd(&a.stats[kStDtwAbandoned], (unsigned long long)__popcll(bab));
+        {
+            const int ns = __popcll(bstart), na = __popcll(bab);
+            w_started += ns;
+            w_aband += na;
+            // cells: completed pairs count their band, abandoned ones the share of rounds they ran
+            const double part = (double)a.band_cells * (double)rounds / (double)R;
+            w_cells += (unsigned long long)(ns - na) * (unsigned long long)a.band_cells +
+                       (unsigned long long)((double)na * part);
+        }
+    }
+    if (lane == 0 && w_started) {
+        atomicAdd(&a.stats[kStDtwStarted], w_started);
+        atomicAdd(&a.stats[kStDtwAbandoned], w_aband);
+        atomicAdd(&a.stats[kStCells], w_cells);
+    }
+}
+
+// Point t of a series (row-major [len][D]) as NCH float4 chunks; `sentinel`
+// in every component outside [0, len), 0 in padded dimensions.
+template <int NCH>
+__device__ __forceinline__ void load_point(const float* src, int len, int D, int t, float sentinel,
+                                           float4 (&out)[NCH]) {
+    if (t < 0 || t >= len) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) out[k] = make_float4(sentinel, sentinel, sentinel, sentinel);
+        return;
+    }
+    const float* p = src + (int64_t)t * D;
+    if ((D & 3) == 0) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k)
+            out[k] = (4 * k < D) ? *reinterpret_cast<const float4*>(p + 4 * k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (4 * k + e < D) ? p[4 * k + e] : 0.0f;
+            out[k] = make_float4(v[0], v[1], v[2], v[3]);
         }
     }
 }
 
-template <int NCH>
-__global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
-    extern __shared__ float4 smem[];
+// Diagonal mapping with ring buffers: each staged series keeps only RS
+// consecutive positions (slot = position mod RS, slots 0..7 mirrored after
+// RS so that four consecutive positions never wrap).  The live window of a
+// round is W + 5 positions; every RF = RS / 4 rounds the RF positions that
+// fell behind are overwritten with the next ones, loaded into registers one
+// refill ahead.  Series 0 is the query, series 1 + g the candidate of group g.
+template <int NCH, bool WODD, int RS>
+__global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
+    constexpr int RF = RS / 4, MIR = 8, STR = RS + MIR;
+    constexpr int MAXPASS = NCH <= 4 ? 3 : 1;
     const int lane = threadIdx.x;
-    const int LC = a.n + 2 * kRowPad;
-    float4* sc = smem;
-    float* rowbuf = reinterpret_cast<float*>(smem + (size_t)LC * NCH);
+    DiagGeom g;
+    g.init(a.m, a.n, a.W);
+    const int G = g.G, h = g.h, R = g.R, P = a.P, W = a.W;
+    const int per_series = NCH * STR;
+    const int grp = lane / G;
+    const int lg = lane - grp * G;
     const int total = a.prefix[a.nq];
+    unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
         int item = 0;
         if (lane == 0) item = atomicAdd(a.counter, 1);
         item = __shfl(item, 0);
         if (item >= total) break;
-        const int q = find_query(a.prefix, a.nq, item);
+        const int q = a.item_query[item];
+        const int chunk = item - a.prefix[q];
+        const int base = chunk * P;
+        const int np = min(P, a.cnt_uniform > 0 ? a.cnt_uniform - base : a.cnt[q] - base);
+        const int nser = 1 + np;
+        const float* qsrc = a.Q + (int64_t)q * a.m * a.D;
+        auto series_src = [&](int s) -> const float* {
+            if (s == 0) return qsrc;
+            const int ref = (int)a.list[(int64_t)q * a.cap + base + s - 1];
+            return a.C + (int64_t)(ref < 0 ? 0 : ref) * a.n * a.D;
+        };
+        // ring slot writer: position pos of series s
+        auto put = [&](int s, int pos, const float4 (&v)[NCH]) {
+            const int slot = pos & (RS - 1);
+            const int b0 = s * per_series + slot;
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) lds4[b0 + k * STR] = v[k];
+            if (slot < MIR) {
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) lds4[b0 + RS + k * STR] = v[k];
+            }
+        };
+        auto fetch = [&](int s, int pos, float4 (&v)[NCH]) {
+            if (s == 0) load_point<NCH>(qsrc, a.m, a.D, pos + g.qfirst(), __builtin_inff(), v);
+            else load_point<NCH>(series_src(s), a.n, a.D, pos + g.cfirst(), -__builtin_inff(), v);
+        };
+        __syncthreads();
+        // initial positions 0 .. RS-1 of every series
+        for (int x = lane; x < nser * RS; x += kWave) {
+            float4 v[NCH];
+            const int s = x / RS, pos = x - (x / RS) * RS;
+            fetch(s, pos, v);
+            put(s, pos, v);
+        }
+        // prefetch of the first refill: positions RS .. RS+RF-1
+        float4 pf[MAXPASS][NCH];
+#pragma unroll
+        for (int p = 0; p < MAXPASS; ++p) {
+            const int x = p * kWave + lane;
+            if (x < nser * RF) fetch(x / RF, RS + (x % RF), pf[p]);
+        }
+        __syncthreads();
+
+        const bool spare = grp >= np;
+        const int gsrc = spare ? 0 : grp;
+        const bool kill_e = WODD && (lg == 0 || spare);
+        const bool kill_o = !WODD && (lg == G - 1);
+        const int qbase = 0;
+        const int cbase = (1 + gsrc) * per_series;
+        float vE = __builtin_inff(), vO = __builtin_inff();
+        if (!spare && lg == h) vE = 0.0f;
+        const uint64_t valid_mask = (np * G >= 64) ? ~0ull : ((1ull << (np * G)) - 1);
+        const uint64_t gm = spare ? 0ull : (((G >= 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G));
+        bool aband = false;
+        const bool abandon = a.abandon != 0;
+        float thr = __builtin_inff();
+        unsigned long long pend = 0;
+        if (abandon) {
+            thr = abandon_threshold(bsf_from_key(__hip_atomic_load(a.key + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), a.gamma);
+            pend = __hip_atomic_load(a.key + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        float4 cA[NCH], cB[NCH];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) cA[k] = lds4[cbase + lg + k * STR];
+        uint32_t cw = 0;
+        int r = 0;
+        bool done = false;
+        while (r < R) {
+            if (r > 0 && (r & (RF - 1)) == 0) {
+                // refill: positions r-RF+RS .. r+RS-1 (prefetched), then prefetch the next refill
+#pragma unroll
+                for (int p = 0; p < MAXPASS; ++p) {
+                    const int x = p * kWave + lane;
+                    if (x < nser * RF) put(x / RF, r - RF + RS + (x % RF), pf[p]);
+                }
+#pragma unroll
+                for (int p = 0; p < MAXPASS; ++p) {
+                    const int x = p * kWave + lane;
+                    if (x < nser * RF) fetch(x / RF, r + RS + (x % RF), pf[p]);
+                }
+            }
+            const int qs = qbase + ((r + W - lg) & (RS - 1));
+            const int cs = cbase + ((r + lg + 1) & (RS - 1));
+            int qk[NCH], ck[NCH];
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) { qk[k] = qs + k * STR; ck[k] = cs - 1 + k * STR; }
+            if (r + 4 <= R) {
+                diag_round<float, NCH, false, WODD>(qk, ck, 0, cA, cB, kill_e, kill_o, vE, vO, cw, 0);
+                diag_round<float, NCH, false, WODD>(qk, ck, 1, cB, cA, kill_e, kill_o, vE, vO, cw, 0);
+                diag_round<float, NCH, false, WODD>(qk, ck, 2, cA, cB, kill_e, kill_o, vE, vO, cw, 0);
+                diag_round<float, NCH, false, WODD>(qk, ck, 3, cB, cA, kill_e, kill_o, vE, vO, cw, 0);
+                r += 4;
+            } else {
+                diag_round<float, NCH, false, WODD>(qk, ck, 0, cA, cB, kill_e, kill_o, vE, vO, cw, 0);
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) cA[k] = cB[k];
+                r += 1;
+            }
+            if (abandon && (r & 15) == 0 && r < R) {
+                // every warping path crosses one of the anti-diagonals 2r-2, 2r-1
+                const bool over = vmin(vE, vO) > thr;
+                const uint64_t bal = __ballot(over);
+                if ((bal & gm) == gm) aband = true;
+                if ((bal & valid_mask) == valid_mask) { done = true; break; }
+                thr = abandon_threshold(bsf_from_key(pend), a.gamma);
+                pend = __hip_atomic_load(a.key + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        (void)done;
+        const int rounds = r;
+        const int sigma = (a.n - a.m) + 2 * h;
+        const int myref = spare ? -1 : (int)a.list[(int64_t)q * a.cap + base + grp];
+        if (!spare && lg == (sigma >> 1)) {
+            const float v = (sigma & 1) ? vO : vE;
+            float out = __builtin_inff();
+            if (!aband && myref >= 0) {
+                out = v;
+                publish(a, q, myref, v, a.gamma);
+            }
+            a.list_dist[(int64_t)q * a.cap + base + grp] = out;
+        }
+        const uint64_t bstart = __ballot(!spare && lg == 0 && myref >= 0);
+        const uint64_t bab = __ballot(aband && !spare && lg == 0 && myref >= 0);
+        {
+            const int ns = __popcll(bstart), na = __popcll(bab);
+            w_started += ns;
+            w_aband += na;
+            const double part = (double)a.band_cells * (double)rounds / (double)R;
+            w_cells += (unsigned long long)(ns - na) * (unsigned long long)a.band_cells +
+                       (unsigned long long)((double)na * part);
+        }
+    }
+    if (lane == 0 && w_started) {
+        atomicAdd(&a.stats[kStDtwStarted], w_started);
+        atomicAdd(&a.stats[kStDtwAbandoned], w_aband);
+        atomicAdd(&a.stats[kStCells], w_cells);
+    }
+}
+
+template <int NCH>
+__global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
+    const int lane = threadIdx.x;
+    const int LC = a.n + 2 * kRowPad;
+    const int sc = 0;
+    const int total = a.prefix[a.nq];
+    unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(a.counter, 1);
+        item = __shfl(item, 0);
+        if (item >= total) break;
+        const int q = a.item_query[item];
         const int e = item - a.prefix[q];
         const int ref = (int)a.list[(int64_t)q * a.cap + e];
         __syncthreads();
@@ -336,12 +546,13 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
         Abandon ab{a.key + q, a.gamma, ~0ull};
         bool aband = false;
         float v;
+        int blocks = 0;
         if (a.abandon)
-            v = rows_core<float, NCH, false, true>(sc, rowbuf, LC, a.Q + (int64_t)q * a.m * a.D, a.m,
-                                                   a.n, a.W, a.D, lane, nullptr, ab, aband);
+            v = rows_core<float, NCH, false, true>(sc, LC, a.Q + (int64_t)q * a.m * a.D, a.m,
+                                                   a.n, a.W, a.D, lane, nullptr, ab, aband, &blocks);
         else
-            v = rows_core<float, NCH, false, false>(sc, rowbuf, LC, a.Q + (int64_t)q * a.m * a.D, a.m,
-                                                    a.n, a.W, a.D, lane, nullptr, ab, aband);
+            v = rows_core<float, NCH, false, false>(sc, LC, a.Q + (int64_t)q * a.m * a.D, a.m,
+                                                    a.n, a.W, a.D, lane, nullptr, ab, aband, &blocks);
         if (lane == (a.m - 1) % kRowBlock) {
             float out = __builtin_inff();
             if (!aband && ref >= 0) {
@@ -350,10 +561,18 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
             }
             a.list_dist[(int64_t)q * a.cap + e] = out;
         }
-        if (lane == 0 && ref >= 0) {
-            atomicAdd(&a.stats[kStDtwStarted], 1ull);
-            if (aband) atomicAdd(&a.stats[kStDtwAbandoned], 1ull);
+        if (ref >= 0) {
+            const int nb = (a.m + kRowBlock - 1) / kRowBlock;
+            w_started += 1;
+            w_aband += aband ? 1 : 0;
+            w_cells += aband ? (unsigned long long)((double)a.band_cells * blocks / nb)
+                             : (unsigned long long)a.band_cells;
         }
+    }
+    if (lane == 0 && w_started) {
+        atomicAdd(&a.stats[kStDtwStarted], w_started);
+        atomicAdd(&a.stats[kStDtwAbandoned], w_aband);
+        atomicAdd(&a.stats[kStCells], w_cells);
     }
 }
 
@@ -364,7 +583,6 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
 // lowest candidate index.
 template <int NCH, bool WODD, bool ROWS>
 __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
-    extern __shared__ float4 smem[];
     const int q = blockIdx.x, lane = threadIdx.x;
     float mn = __builtin_inff();
     const int ns = a.R, nl = a.cnt[q];
@@ -381,8 +599,8 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
     DiagGeom g;
     g.init(a.m, a.n, a.W);
     const int LQ = g.LQ, LC = g.LC;
-    float4* sq = smem;
-    float4* sc = ROWS ? smem : smem + LQ * NCH;
+    const int sq = 0;
+    const int sc = ROWS ? 0 : LQ * NCH;
     if (!ROWS)
         stage_series<NCH>(sq, LQ, g.qfirst(), a.Q + (int64_t)q * a.m * a.D, a.m, a.D, __builtin_inff(),
                           lane, kWave);
@@ -405,12 +623,11 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
                 double v;
                 if (ROWS) {
                     const int LCr = a.n + 2 * kRowPad;
-                    double* rowbuf = reinterpret_cast<double*>(sc + (size_t)LCr * NCH);
                     stage_series<NCH>(sc, LCr, -kRowPad, a.C + (int64_t)r * a.n * a.D, a.n, a.D,
                                       -__builtin_inff(), lane, kWave);
                     Abandon ab{nullptr, 0.0f, 0};
                     bool aband = false;
-                    v = rows_core<double, NCH, false, false>(sc, rowbuf, LCr, a.Q + (int64_t)q * a.m * a.D,
+                    v = rows_core<double, NCH, false, false>(sc, LCr, a.Q + (int64_t)q * a.m * a.D,
                                                              a.m, a.n, a.W, a.D, lane, nullptr, ab, aband);
                     v = __shfl(v, (a.m - 1) % kRowBlock);
                 } else {
@@ -421,8 +638,8 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
                     const bool spare = lane >= G;
                     const bool kill_e = WODD && (lg == 0 || spare);
                     const bool kill_o = !WODD && (lg == G - 1);
-                    const float4* qb = sq + (a.W - (spare ? 0 : lg));
-                    const float4* cb = sc + (spare ? 0 : lg);
+                    const int qb = sq + (a.W - (spare ? 0 : lg));
+                    const int cb = sc + (spare ? 0 : lg);
                     double vE = __builtin_inf(), vO = __builtin_inf();
                     if (lg == g.h) vE = 0.0;
                     Abandon ab{nullptr, 0.0f, 0};
@@ -442,6 +659,11 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
         a.nn_idx[q] = bestidx == 0x7fffffff ? -1 : bestidx;
         a.nn_dist[q] = (float)best;
         atomicAdd(&a.stats[kStRescored], (unsigned long long)rescored);
+        int nseeds = 0;
+        for (int k = 0; k < ns; ++k) nseeds += a.seeds[(int64_t)q * ns + k] >= 0;
+        const int gl = a.gcnt ? a.gcnt[q] : 0;
+        const int pruned = a.nc - nseeds - nl - gl;
+        if (pruned > 0) atomicAdd(&a.stats[kStPrunedMv], (unsigned long long)pruned);
     }
 }
 
@@ -481,25 +703,31 @@ hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int 
 template <int NCH>
 static hipError_t launch_dtw_lists_nch(const KnnDtwArgs& a, bool rows, int nblocks, size_t lds,
                                        hipStream_t s) {
-    if (rows)
+    if (rows) {
         hipLaunchKernelGGL(k_knn_dtw_rows<NCH>, dim3(nblocks), dim3(64), lds, s, a);
-    else if (a.W & 1)
-        hipLaunchKernelGGL((k_knn_dtw_diag<NCH, true>), dim3(nblocks), dim3(64), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_knn_dtw_diag<NCH, false>), dim3(nblocks), dim3(64), lds, s, a);
+    } else if (ring_size(a.W) == 64) {
+        if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, 64>), dim3(nblocks), dim3(64), lds, s, a);
+        else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, 64>), dim3(nblocks), dim3(64), lds, s, a);
+    } else {
+        if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, 128>), dim3(nblocks), dim3(64), lds, s, a);
+        else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, 128>), dim3(nblocks), dim3(64), lds, s, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s) {
-    // chunk prefix over the queries, then the persistent DTW kernel
+hipError_t launch_chunk_scan(const KnnDtwArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(1024), 0, s, a.cnt, a.cnt_uniform, a.nq, a.P,
                        const_cast<int32_t*>(a.prefix), a.counter);
+    hipLaunchKernelGGL(k_item_map, dim3(a.nq < 4096 ? a.nq : 4096), dim3(256), 0, s, a.prefix, a.nq,
+                       const_cast<int32_t*>(a.item_query));
+    return hipGetLastError();
+}
+
+// The persistent DTW kernel; launch_chunk_scan must precede it on the stream.
+hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s) {
     const bool rows = a.W > kDiagMaxW;
-    DiagGeom g;
-    g.init(a.m, a.n, a.W);
     const int nch = nch_pad(a.D);
-    const size_t lds = rows ? rows_lds_bytes(a.n, a.W, a.D, false)
-                            : (size_t)(g.LQ + a.P * g.LC) * nch * 16;
+    const size_t lds = knn_dtw_lds_bytes(a.m, a.n, a.W, a.D, a.P);
     switch (nch) {
         case 1: return launch_dtw_lists_nch<1>(a, rows, nblocks, lds, s);
         case 2: return launch_dtw_lists_nch<2>(a, rows, nblocks, lds, s);
@@ -514,10 +742,18 @@ hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s) {
 }
 
 size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P) {
+    (void)m;
     if (W > kDiagMaxW) return rows_lds_bytes(n, W, D, false);
-    DiagGeom g;
-    g.init(m, n, W);
-    return (size_t)(g.LQ + P * g.LC) * nch_pad(D) * 16;
+    return (size_t)(1 + P) * nch_pad(D) * (ring_size(W) + 8) * 16;
+}
+
+int knn_dtw_max_pairs(int W, int D) {
+    if (W > kDiagMaxW) return 1;
+    int P = kWave / (W + 1);
+    const int RF = ring_size(W) / 4;
+    const int maxpass = nch_pad(D) <= 4 ? 3 : 1;
+    while (P > 1 && (1 + P) * RF > maxpass * kWave) --P;
+    return P;
 }
 
 size_t knn_final_lds_bytes(int m, int n, int W, int D) {
