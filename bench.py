@@ -48,9 +48,6 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=24, help="queries in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the plain GPU search")
-    ap.add_argument("--copy-mb", type=int, default=0,
-                    help="first run one device-to-device copy of this many MiB (a reference for "
-                         "hardware byte counters)")
     return ap.parse_args()
 
 
@@ -79,12 +76,6 @@ def main():
     gen = synth.cascade_knn if args.workload == "cascade" else synth.plain_knn
     Q, Cs = gen(**gen_kw)
     dev = torch.device("cuda:0")
-    if args.copy_mb > 0:
-        src = torch.ones(args.copy_mb * 262144, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     Qd = torch.from_numpy(Q).to(dev)
     Cd = torch.from_numpy(Cs).to(dev)
     torch.cuda.synchronize()
