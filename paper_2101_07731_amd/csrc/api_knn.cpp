@@ -64,9 +64,11 @@ static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
 // Everything a uniform search needs, with workspace offsets.
 struct KnnPlan {
     int nq, nc, m, n, D, W, R, P, cap, ntiles;
-    bool plain, abandon, gate;
+    bool plain, abandon, gate, pc, ti;
+    int ngroups, max_pts;
     size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
-        o_items, o_counters, o_key, o_stats, bytes;
+        o_items, o_counters, o_key, o_stats, o_boxes, o_nbox, o_qstep, o_glb, o_tlist, o_tlb, o_tout,
+        o_tcnt, o_ppc, o_pti, o_cntmv, bytes;
 };
 
 
@@ -89,6 +91,10 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.plain = (p->bounds == 0);
     K.abandon = !K.plain && p->early_abandon != 0;
     K.gate = (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)) != 0;
+    K.pc = (p->bounds & TC_DTW_LB_PC) != 0;
+    K.ti = (p->bounds & TC_DTW_LB_TI) != 0;
+    K.ngroups = (K.n + p->pc_group - 1) / p->pc_group;
+    K.max_pts = std::min(K.m, p->pc_group + 2 * K.W);
     K.R = K.plain ? 0 : std::min(std::min(p->seed_r > 0 ? p->seed_r : 4, kMaxSeeds), K.nc);
     K.P = knn_dtw_max_pairs(K.W, K.D);
     K.cap = K.nc;
@@ -110,13 +116,37 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.o_counters = at(kNumCounters * 4);
     K.o_key = at((size_t)K.nq * 8);
     K.o_stats = at(kNumStats * 8);
+    const bool any_pc = K.pc || true;   // the dense bound matrix may ask for LB_PC / LB_TI too
+    (void)any_pc;
+    K.o_boxes = at((size_t)K.nq * K.ngroups * p->pc_clusters * K.D * 2 * 4);
+    K.o_nbox = at((size_t)K.nq * K.ngroups * 4);
+    K.o_qstep = at((size_t)K.nq * K.m * 4);
+    K.o_glb = at(K.gate ? (size_t)K.nq * K.cap * 4 : 0);
+    K.o_tlist = at(K.ti ? (size_t)K.nq * K.cap * 4 : 0);
+    K.o_tlb = at(K.ti ? (size_t)K.nq * K.cap * 4 : 0);
+    K.o_tout = at(K.ti ? (size_t)K.nq * K.cap * 4 : 0);
+    K.o_tcnt = at((size_t)K.nq * 4);
+    K.o_ppc = at((size_t)K.nq * 4);
+    K.o_pti = at((size_t)K.nq * 4);
+    K.o_cntmv = at((size_t)K.nq * 4);
     K.bytes = c.need();
+    {
+        // the boxes of one expanded window are built in LDS; its cell keys need Lv^D < 2^63
+        unsigned long long pw = 1;
+        for (int t = 0; t < K.D; ++t) {
+            if (pw > (1ull << 62) / (unsigned long long)p->pc_levels) {
+                if (K.pc) return fail(TC_DTW_ERR_UNSUPPORTED, "pc_levels^dim does not fit 63 bits");
+                break;
+            }
+            pw *= (unsigned long long)p->pc_levels;
+        }
+    }
     const size_t lim = 163840;
     if (knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, 1) > lim || knn_final_lds_bytes(K.m, K.n, K.W, K.D) > lim)
         return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
     while (K.P > 1 && knn_dtw_lds_bytes(K.m, K.n, K.W, K.D, K.P) > lim) --K.P;
-    // work items: chunks of P list entries per query (seeds need fewer)
-    K.o_items = at((size_t)K.nq * ((K.cap + K.P - 1) / K.P) * 4);
+    // work items: chunks of P list entries per query (seeds need fewer); LB_TI takes one pair per item
+    K.o_items = at((size_t)K.nq * K.cap * 4);
     K.bytes = c.need();
     return TC_DTW_OK;
 }
@@ -145,6 +175,70 @@ static KnnPlanDev dev_plan(const KnnPlan& K, const tc_dtw_index* ix, const HostS
     d.key = reinterpret_cast<unsigned long long*>(ws + K.o_key);
     d.stats = reinterpret_cast<unsigned long long*>(ws + K.o_stats);
     return d;
+}
+
+struct KnnExtra {
+    float* boxes;
+    int32_t* nbox;
+    float* qstep;
+    float* glb;
+    uint32_t* tlist;
+    float* tlb;
+    float* tout;
+    int32_t* tcnt;
+    int32_t* ppc;
+    int32_t* pti;
+    int32_t* cntmv;
+};
+
+static KnnExtra extra_plan(const KnnPlan& K, char* ws) {
+    KnnExtra x;
+    x.boxes = reinterpret_cast<float*>(ws + K.o_boxes);
+    x.nbox = reinterpret_cast<int32_t*>(ws + K.o_nbox);
+    x.qstep = reinterpret_cast<float*>(ws + K.o_qstep);
+    x.glb = K.gate ? reinterpret_cast<float*>(ws + K.o_glb) : nullptr;
+    x.tlist = K.ti ? reinterpret_cast<uint32_t*>(ws + K.o_tlist) : nullptr;
+    x.tlb = K.ti ? reinterpret_cast<float*>(ws + K.o_tlb) : nullptr;
+    x.tout = K.ti ? reinterpret_cast<float*>(ws + K.o_tout) : nullptr;
+    x.tcnt = reinterpret_cast<int32_t*>(ws + K.o_tcnt);
+    x.ppc = reinterpret_cast<int32_t*>(ws + K.o_ppc);
+    x.pti = reinterpret_cast<int32_t*>(ws + K.o_pti);
+    x.cntmv = reinterpret_cast<int32_t*>(ws + K.o_cntmv);
+    return x;
+}
+
+static PcArgs pc_args(const KnnPlan& K, const KnnPlanDev& d, const KnnExtra& x, const tc_dtw_index* ix,
+                      const tc_dtw_knn_params* p) {
+    PcArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Q = d.Q; a.C = d.C;
+    a.nq = K.nq; a.nc = K.nc; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W;
+    a.Lv = p->pc_levels; a.K = p->pc_clusters; a.w = p->pc_group;
+    a.ngroups = K.ngroups; a.max_pts = K.max_pts;
+    a.floor_len = p->pc_min_cell;
+    a.range = reinterpret_cast<const float*>(static_cast<const char*>(ix->buf) + ix->off_range);
+    a.boxes = x.boxes; a.nbox = x.nbox;
+    a.cap = K.cap;
+    a.prefix = d.prefix; a.item_query = d.item_query; a.counter = d.counters + 2;
+    a.lb_mv = d.lb;
+    a.keep = 1.0 - (double)p->prune_margin;
+    a.e2 = (double)p->trigger_pc * (double)p->trigger_pc;
+    return a;
+}
+
+static TiArgs ti_args(const KnnPlan& K, const KnnPlanDev& d, const KnnExtra& x, const tc_dtw_index* ix,
+                      const tc_dtw_knn_params* p) {
+    TiArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Q = d.Q; a.C = d.C;
+    a.qstep = x.qstep;
+    a.gamma = reinterpret_cast<const float*>(static_cast<const char*>(ix->buf) + ix->off_gamma);
+    a.nq = K.nq; a.nc = K.nc; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W;
+    a.P = p->ti_period; a.top = p->ti_top ? 1 : 0;
+    a.cap = K.cap;
+    a.prefix = d.prefix; a.item_query = d.item_query; a.counter = d.counters + 3;
+    a.e2 = (double)p->trigger_ti * (double)p->trigger_ti;
+    return a;
 }
 
 static float dp_gamma(int m, int n, int D) {
@@ -304,13 +398,18 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     tc_dtw_status st = make_knn_plan(ix, queries, p, K, Qs);
     if (st != TC_DTW_OK) return st;
     if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
-    if (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI))
-        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC / LB_TI are not available in this build");
+    if (K.ti && 2 * K.W + 1 > 128)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
-    const KnnPlanDev d = dev_plan(K, ix, Qs, w);
+    const KnnExtra x = extra_plan(K, w);
+    KnnPlanDev dd = dev_plan(K, ix, Qs, w);
+    dd.clear[0] = x.tcnt;
+    dd.clear[1] = x.ppc;
+    dd.clear[2] = x.pti;
+    const KnnPlanDev d = dd;
 
     hipEvent_t ev[8];
     const bool timed = stats != nullptr;
@@ -321,6 +420,8 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     hipError_t e;
     mark(0);
     if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
+    if (K.ti && (e = launch_query_steps(d.Q, K.nq, K.m, K.D, x.qstep, s)) != hipSuccess) return hip_fail(e, "query steps");
+    if (K.pc && (e = launch_pc_boxes(pc_args(K, d, x, ix, p), s)) != hipSuccess) return hip_fail(e, "boxes");
     mark(1);
     if (!K.plain) {
         if ((e = launch_lb_mv(d, d.lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
@@ -337,10 +438,53 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     mark(3);
     const double keep = 1.0 - (double)p->prune_margin;
     const double e_pc = p->trigger_pc, e_ti = p->trigger_ti;
-    const double gate_e2 = std::min(e_pc * e_pc, e_ti * e_ti);
+    double gate_e2 = 1e300;
+    if (K.pc) gate_e2 = std::min(gate_e2, e_pc * e_pc);
+    if (K.ti) gate_e2 = std::min(gate_e2, e_ti * e_ti);
     if ((e = launch_compact(d, K.plain ? 0.0 : keep, gate_e2, K.gate ? 1 : 0, s)) != hipSuccess)
         return hip_fail(e, "compaction");
     mark(4);
+    if (K.gate) {
+        // Sec. 6: advanced bounds only for gated pairs; LB_PC first, then LB_TI
+        if ((e = launch_copy_i32(d.cnt, x.cntmv, K.nq, s)) != hipSuccess) return hip_fail(e, "snapshot");
+        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * ((K.cap + 63) / 64));
+        RouteArgs r;
+        std::memset(&r, 0, sizeof r);
+        r.nq = K.nq; r.nc = K.nc; r.cap = K.cap;
+        r.lb_mv = d.lb; r.key = d.key; r.keep = keep;
+        r.dtw_list = d.list; r.dtw_cnt = d.cnt;
+        if (K.pc) {
+            PcArgs a = pc_args(K, d, x, ix, p);
+            a.in_list = d.glist; a.in_cnt = d.gcnt; a.in_uniform = 0;
+            a.out_lb = x.glb; a.key = d.key;
+            if ((e = launch_list_items(d.gcnt, 0, K.nq, 64, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+                return hip_fail(e, "pc items");
+            if ((e = launch_lb_pc(a, pc_blocks, s)) != hipSuccess) return hip_fail(e, "lb_pc");
+            r.in_list = d.glist; r.in_cnt = d.gcnt; r.lb_prev = nullptr; r.lb_new = x.glb;
+            r.next_list = K.ti ? x.tlist : nullptr; r.next_lb = x.tlb; r.next_cnt = x.tcnt;
+            r.next_e2 = e_ti * e_ti;
+            r.pruned = x.ppc;
+            if ((e = launch_route(r, K.cap, s)) != hipSuccess) return hip_fail(e, "route pc");
+        } else if (K.ti) {
+            // no LB_PC: every gated pair goes to the LB_TI list with its LB_MV
+            r.in_list = d.glist; r.in_cnt = d.gcnt; r.lb_prev = nullptr; r.lb_new = nullptr;
+            r.next_list = x.tlist; r.next_lb = x.tlb; r.next_cnt = x.tcnt; r.next_e2 = -1.0;
+            r.pruned = x.ppc;
+            if ((e = launch_route(r, K.cap, s)) != hipSuccess) return hip_fail(e, "route mv");
+        }
+        if (K.ti) {
+            TiArgs a = ti_args(K, d, x, ix, p);
+            a.in_list = x.tlist; a.out_lb = x.tout; a.lb_in = x.tlb; a.key = d.key;
+            if ((e = launch_list_items(x.tcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+                return hip_fail(e, "ti items");
+            const int ti_blocks = persistent_blocks((size_t)K.m * 4 + 16, (int64_t)K.nq * K.cap);
+            if ((e = launch_lb_ti(a, ti_blocks, s)) != hipSuccess) return hip_fail(e, "lb_ti");
+            RouteArgs r2 = r;
+            r2.in_list = x.tlist; r2.in_cnt = x.tcnt; r2.lb_prev = x.tlb; r2.lb_new = x.tout;
+            r2.next_list = nullptr; r2.pruned = x.pti;
+            if ((e = launch_route(r2, K.cap, s)) != hipSuccess) return hip_fail(e, "route ti");
+        }
+    }
     {
         const KnnDtwArgs a = list_args(K, d, false, K.abandon);
         const int64_t items = (int64_t)K.nq * ((K.nc + K.P - 1) / K.P);
@@ -356,7 +500,10 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         f.nq = K.nq; f.m = K.m; f.n = K.n; f.D = K.D; f.W = K.W; f.R = K.R; f.cap = K.cap;
         f.seeds = d.seeds; f.seed_dist = d.seed_dist;
         f.list = d.list; f.list_dist = d.list_dist; f.cnt = d.cnt;
-        f.gcnt = nullptr;
+        f.gcnt = K.gate ? d.gcnt : nullptr;
+        f.cnt_mv = K.gate ? x.cntmv : nullptr;
+        f.pruned_pc = K.gate ? x.ppc : nullptr;
+        f.pruned_ti = K.gate ? x.pti : nullptr;
         f.nc = K.nc;
         const double g = dp_gamma(K.m, K.n, K.D);
         f.ratio = (1.0 + g) / (1.0 - g) * (1.0 + 1e-9);
@@ -412,15 +559,35 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
     if (!lb) return fail(TC_DTW_ERR_INVALID, "null lb pointer");
     if (kind != TC_DTW_LB_MV && kind != TC_DTW_LB_PC && kind != TC_DTW_LB_TI)
         return fail(TC_DTW_ERR_INVALID, "kind must be one of TC_DTW_LB_MV, TC_DTW_LB_PC, TC_DTW_LB_TI");
-    if (kind != TC_DTW_LB_MV) return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC / LB_TI are not available in this build");
+    if (kind == TC_DTW_LB_TI && 2 * K.W + 1 > 128)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
     if (K.plain) return fail(TC_DTW_ERR_INVALID, "params.bounds must include TC_DTW_LB_MV");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_lower_bounds_workspace_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const KnnPlanDev d = dev_plan(K, ix, Qs, static_cast<char*>(ws));
+    const KnnExtra x = extra_plan(K, static_cast<char*>(ws));
     hipError_t e;
     if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
-    if ((e = launch_lb_mv(d, lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+    if (kind == TC_DTW_LB_MV) {
+        if ((e = launch_lb_mv(d, lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+    } else if (kind == TC_DTW_LB_PC) {
+        PcArgs a = pc_args(K, d, x, ix, p);
+        if ((e = launch_pc_boxes(a, s)) != hipSuccess) return hip_fail(e, "boxes");
+        a.in_list = nullptr; a.in_uniform = K.nc; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
+        if ((e = launch_list_items(nullptr, K.nc, K.nq, 64, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+            return hip_fail(e, "pc items");
+        if ((e = launch_lb_pc(a, persistent_blocks(0, (int64_t)K.nq * ((K.nc + 63) / 64)), s)) != hipSuccess)
+            return hip_fail(e, "lb_pc");
+    } else {
+        if ((e = launch_query_steps(d.Q, K.nq, K.m, K.D, x.qstep, s)) != hipSuccess) return hip_fail(e, "query steps");
+        TiArgs a = ti_args(K, d, x, ix, p);
+        a.in_list = nullptr; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
+        if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+            return hip_fail(e, "ti items");
+        if ((e = launch_lb_ti(a, persistent_blocks((size_t)K.m * 4 + 16, (int64_t)K.nq * K.nc), s)) != hipSuccess)
+            return hip_fail(e, "lb_ti");
+    }
     return ok();
 }
 

@@ -1,0 +1,512 @@
+// Advanced lower bounds of the cascade for gfx950: the point-clustering bound
+// LB_PC (Sec. 5) and the triangle bound LB_TI (Sec. 4.1-4.2), evaluated on
+// per-query candidate lists (the gated pairs of the 1-NN search, or every
+// candidate for the dense bound matrix), and the routing of gated pairs
+// (Sec. 6, selective deployment).
+//
+// Rounding: every value returned never exceeds the exact bound of the
+// float32 inputs (u = 2^-24):
+//  * LB_PC: a sum of n non-negative per-point minima, each a fused
+//    multiply-add chain of D terms; scaled by 1 - (n + D + 5) u and rounded
+//    down;
+//  * LB_TI: a computed triangle bound L_f after r recursion steps from an
+//    exact distance differs from the exact recursion by at most
+//    (D/2 + 3 + r) u U_f (U_f the matching upper bound, which grows by the
+//    same steps as the allowance), so L_f - (D/2 + 5 + r_max) u U_f is used
+//    before the clamp at zero; the sum of the squared column minima is
+//    scaled by 1 - (n + 5) u and rounded down.
+#include <algorithm>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace tcdtw {
+
+extern __shared__ float4 lds4[];
+
+__device__ __forceinline__ float rdown(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);
+    return f;
+}
+
+__device__ __forceinline__ uint32_t okey(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float okey_to_float(uint32_t k) {
+    const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(b);
+}
+
+__device__ __forceinline__ float key_bsf(const unsigned long long* key) {
+    const unsigned long long k = __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __uint_as_float((uint32_t)(k >> 32));
+}
+
+// --------------------------------------------------------- query steps
+// delta[q][i] = e(q_{i-1}, q_i) (delta[q][0] = 0), the query-side distances
+// of Eqs. 7-8, computed once per query (Sec. 4.1).
+__global__ void k_query_steps(const float* __restrict__ Q, int nq, int m, int D, float* __restrict__ delta) {
+    const int64_t total = (int64_t)nq * m;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % m);
+        float s = 0.0f;
+        if (i > 0) {
+            const float* a = Q + t * D;
+            for (int p = 0; p < D; ++p) {
+                const float d = a[p] - a[p - D];
+                s = __builtin_fmaf(d, d, s);
+            }
+        }
+        delta[t] = __builtin_sqrtf(s);
+    }
+}
+
+// ------------------------------------------------------------------- K4
+// Boxes of one query's expanded windows (Sec. 5, quantisation-based
+// clustering with uniform window grouping): one wave per (group, query).
+// Cell assignment in float32 exactly as written: per-dimension range of the
+// window's points, cell length max((hi - lo) / Lv, floor), digit
+// min(Lv - 1, floor((x - lo) / len)), key = digits in base Lv with
+// dimension 0 most significant.  The first K-1 distinct cells in key order
+// own a box each; later cells share box K.  Boxes are the tight [min, max]
+// of their member points.  LDS: keys (u64), first-occurrence flags, then
+// K*D*2 ordered-int box bounds.
+__global__ __launch_bounds__(64) void k_pc_boxes(PcArgs a) {
+    const int lane = threadIdx.x;
+    const int g = blockIdx.x, q = blockIdx.y;
+    const int m = a.m, n = a.n, D = a.D, W = a.W, w = a.w, K = a.K, Lv = a.Lv;
+    const int jfirst = g * w, jlast = min(n - 1, g * w + w - 1);
+    const int ilo = max(0, jfirst - W), ihi = min(m - 1, jlast + W);
+    const int npts = ihi - ilo + 1;
+    const float* Q = a.Q + (int64_t)q * m * D;
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(lds4);
+    int32_t* first = reinterpret_cast<int32_t*>(keys + a.max_pts);
+    uint32_t* bx = reinterpret_cast<uint32_t*>(first + a.max_pts);   // [K][D][2]
+    for (int t = lane; t < K * D; t += kWave) {
+        bx[2 * t] = 0xffffffffu;
+        bx[2 * t + 1] = 0u;
+    }
+    for (int i = lane; i < npts; i += kWave) keys[i] = 0ull;
+    __syncthreads();
+    for (int p = 0; p < D; ++p) {
+        float lo = __builtin_inff(), hi = -__builtin_inff();
+        for (int i = ilo + lane; i <= ihi; i += kWave) {
+            const float x = Q[(int64_t)i * D + p];
+            lo = __builtin_fminf(lo, x);
+            hi = __builtin_fmaxf(hi, x);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo = __builtin_fminf(lo, __shfl_xor(lo, o));
+            hi = __builtin_fmaxf(hi, __shfl_xor(hi, o));
+        }
+        float fl = a.floor_len;
+        if (!(fl > 0.0f) && a.range) fl = (float)(1e-5 * (double)(a.range[1] - a.range[0]));
+        float len = (hi - lo) / (float)Lv;
+        if (len < fl) len = fl;
+        for (int i = ilo + lane; i <= ihi; i += kWave) {
+            const float x = Q[(int64_t)i * D + p];
+            int dgt = 0;
+            if (len > 0.0f) dgt = (int)__builtin_floorf((x - lo) / len);
+            if (dgt > Lv - 1) dgt = Lv - 1;
+            keys[i - ilo] = keys[i - ilo] * (unsigned long long)Lv + (unsigned long long)dgt;
+        }
+        __syncthreads();
+    }
+    // first occurrence of each key, then the rank of each point's key among the distinct keys
+    int M = 0;
+    for (int i = lane; i < npts; i += kWave) {
+        const unsigned long long ki = keys[i];
+        int f = 1;
+        for (int t = 0; t < i; ++t) f &= (keys[t] != ki) ? 1 : 0;
+        first[i] = f;
+        M += f;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) M += __shfl_xor(M, o);
+    __syncthreads();
+    for (int i = lane; i < npts; i += kWave) {
+        const unsigned long long ki = keys[i];
+        int rank = 0;
+        for (int t = 0; t < npts; ++t) rank += (first[t] && keys[t] < ki) ? 1 : 0;
+        const int b = rank < K - 1 ? rank : K - 1;
+        for (int p = 0; p < D; ++p) {
+            const uint32_t kv = okey(Q[(int64_t)(ilo + i) * D + p]);
+            atomicMin(&bx[2 * (b * D + p)], kv);
+            atomicMax(&bx[2 * (b * D + p) + 1], kv);
+        }
+    }
+    __syncthreads();
+    const int nb = M < K ? M : K;
+    float* out = a.boxes + ((int64_t)q * a.ngroups + g) * K * D * 2;
+    for (int t = lane; t < K * D; t += kWave) {
+        const int b = t / D;
+        out[2 * t] = b < nb ? okey_to_float(bx[2 * t]) : __builtin_inff();
+        out[2 * t + 1] = b < nb ? okey_to_float(bx[2 * t + 1]) : -__builtin_inff();
+    }
+    if (lane == 0) a.nbox[(int64_t)q * a.ngroups + g] = nb;
+}
+
+// ------------------------------------------------------------------- K5
+// LB_PC of a chunk of up to 64 listed candidates of one query (lanes over
+// candidates; the boxes of the current group are wave-uniform scalar loads):
+// per candidate point the smallest squared distance to a box of its group,
+// summed over points (Sec. 5, Fig. 4(a)).  In search mode a pair is only
+// evaluated when its LB_MV exceeds e^2 * bsf, and a chunk stops as soon as
+// every lane's partial sum already proves its pair prunable.
+template <int DMAX>
+__global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
+    const int lane = threadIdx.x;
+    const int D = a.D, n = a.n, K = a.K, w = a.w;
+    const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.prefix[a.nq]) break;
+        const int q = a.item_query[item];
+        const int e = (item - a.prefix[q]) * kWave + lane;
+        const int cnt = a.in_uniform > 0 ? a.in_uniform : a.in_cnt[q];
+        bool live = e < cnt;
+        const int ref = live ? (a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e) : 0;
+        float bsf = __builtin_inff();
+        if (a.key) {
+            bsf = key_bsf(a.key + q);
+            // selective deployment: only pairs with LB_MV > e^2 bsf
+            const float mv = live ? a.lb_mv[(int64_t)q * a.nc + ref] : 0.0f;
+            if (live && !((double)mv > a.e2 * (double)bsf)) {
+                a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
+                live = false;
+            }
+        }
+        if (__ballot(live) == 0ull) continue;
+        const float* c = a.C + (int64_t)ref * n * D;
+        const float* bxq = a.boxes + (int64_t)q * a.ngroups * K * D * 2;
+        const int32_t* nbq = a.nbox + (int64_t)q * a.ngroups;
+        const double stop = a.key ? (double)bsf / a.keep : __builtin_inf();
+        float acc = 0.0f;
+        for (int j0 = 0; j0 < n; j0 += w) {
+            const int g = j0 / w;
+            const int nb = nbq[g];
+            const float* bg = bxq + (int64_t)g * K * D * 2;
+            const int j1 = min(n, j0 + w);
+            for (int j = j0; j < j1; ++j) {
+                float cv[DMAX];
+#pragma unroll
+                for (int p = 0; p < DMAX; ++p) cv[p] = p < D ? c[(int64_t)j * D + p] : 0.0f;
+                float best = __builtin_inff();
+                for (int b = 0; b < nb; ++b) {
+                    const float* bb = bg + b * D * 2;
+                    float s = 0.0f;
+#pragma unroll
+                    for (int p = 0; p < DMAX; ++p) {
+                        if (p < D) {
+                            const float t = __builtin_fmaxf(__builtin_fmaxf(bb[2 * p] - cv[p], cv[p] - bb[2 * p + 1]), 0.0f);
+                            s = __builtin_fmaf(t, t, s);
+                        }
+                    }
+                    best = __builtin_fminf(best, s);
+                }
+                acc += best;
+            }
+            if (a.key && __ballot(live && !((double)acc * defl > stop)) == 0ull) break;
+        }
+        if (live) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
+    }
+}
+
+// ------------------------------------------------------------------- K6
+// LB_TI (LB_TIP with optional TOP, Sec. 4.1-4.2, Fig. 3) of one listed
+// pair per wave.  Lane k (and k + 64 with two slots) holds band offset k,
+// i.e. cell (i, i - W + k) of row i.  The cell of row i+1 on the same
+// column is offset k - 1, so both the (L, U) pair (Eqs. 7-8) and the
+// running column minimum of max(0, L) move one lane down per row (DPP
+// shift); a column's minimum is final when it leaves offset 0.  Exact rows
+// (i = 0 and i mod P = 0) compute e(q_i, c_j) (query point from scalar
+// loads, candidate point per lane); the top cell of each row takes the
+// precomputed e(q_i, c_{i+W}) under TOP, else Eqs. 9-10 from its left
+// neighbour with gamma_j = e(c_{j-1}, c_j) from the index.
+template <int SLOTS>
+__global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
+    float* top = reinterpret_cast<float*>(lds4);       // [m] exact top distances (TOP)
+    const int lane = threadIdx.x;
+    const int m = a.m, n = a.n, D = a.D, W = a.W, P = a.P;
+    const int KB = 2 * W + 1;                          // band offsets 0 .. 2W
+    const float INF = __builtin_inff();
+    const double u = 1.0 / 16777216.0;
+    // longest recursion chain since an exact value (rows, plus one top step per row without TOP)
+    const int rmax = P > 0 ? (a.top ? P - 1 : 2 * (P - 1) + 1) : (a.top ? m : 2 * m + 1);
+    const float slack = (float)((0.5 * D + 5.0 + rmax) * u * 1.02);
+    const double defl = 1.0 - (double)(n + 5) * u * 1.001;
+    const int kt = KB - 1;                             // top offset
+    const int kl = kt > 0 ? kt - 1 : 0;                // its left neighbour
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.prefix[a.nq]) break;
+        const int q = a.item_query[item];
+        const int e = item - a.prefix[q];
+        const int ref = a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e;
+        if (a.key) {
+            // selective deployment: only pairs whose bound so far exceeds e^2 bsf
+            const float cur = a.lb_in[(int64_t)q * a.cap + e];
+            const float bsf = key_bsf(a.key + q);
+            if (wave_uniform(!((double)cur > a.e2 * (double)bsf))) {
+                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;
+                continue;
+            }
+        }
+        const float* qs = a.Q + (int64_t)q * m * D;
+        const float* cs = a.C + (int64_t)ref * n * D;
+        const float* dq = a.qstep + (int64_t)q * m;
+        const float* gc = a.gamma + (int64_t)ref * n;
+        __syncthreads();
+        if (a.top) {
+            for (int i = lane; i < m; i += kWave) {
+                const int j = i + W;
+                float d = INF;
+                if (j < n) {
+                    float s = 0.0f;
+                    for (int p = 0; p < D; ++p) {
+                        const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
+                        s = __builtin_fmaf(t, t, s);
+                    }
+                    d = __builtin_sqrtf(s);
+                }
+                top[i] = d;
+            }
+        }
+        __syncthreads();
+        float L[SLOTS], U[SLOTS], cm[SLOTS];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) { L[s] = -INF; U[s] = INF; cm[s] = INF; }
+        float acc = 0.0f;
+        for (int i = 0; i < m; ++i) {
+            const bool exact_row = (i == 0) || (P > 0 && i % P == 0);
+            const float di = dq[i];
+            // row i-1 values of the same column (offset k+1)
+            float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
+            if (SLOTS == 1) {
+                Ln[0] = wave_shl1(-INF, L[0]);
+                Un[0] = wave_shl1(INF, U[0]);
+                cmn[0] = wave_shl1(INF, cm[0]);
+            } else {
+                Ln[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(L[SLOTS - 1]), 0)), L[0]);
+                Un[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(U[SLOTS - 1]), 0)), U[0]);
+                cmn[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(cm[SLOTS - 1]), 0)), cm[0]);
+                Ln[SLOTS - 1] = wave_shl1(-INF, L[SLOTS - 1]);
+                Un[SLOTS - 1] = wave_shl1(INF, U[SLOTS - 1]);
+                cmn[SLOTS - 1] = wave_shl1(INF, cm[SLOTS - 1]);
+            }
+            // the column at offset 0 of row i-1 is not in row i's band: its minimum is final
+            const float leaving = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cm[0])));
+            if (i > 0 && leaving < INF) acc += leaving * leaving;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int k = lane + 64 * s;
+                const int j = i - W + k;
+                const bool cell = (k < KB) && j >= 0 && j < n;
+                float lo = -INF, hi = INF;
+                if (cell) {
+                    if (exact_row) {
+                        float sacc = 0.0f;
+                        for (int p = 0; p < D; ++p) {
+                            const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
+                            sacc = __builtin_fmaf(t, t, sacc);
+                        }
+                        lo = hi = __builtin_sqrtf(sacc);
+                    } else if (k < kt) {
+                        lo = __builtin_fmaxf(Ln[s] - di, di - Un[s]);   // Eq. 7
+                        hi = Un[s] + di;                                 // Eq. 8
+                    } else if (a.top) {
+                        lo = hi = top[i];
+                    }
+                }
+                L[s] = lo;
+                U[s] = hi;
+            }
+            if (!exact_row && !a.top) {
+                // top cell from (i, j-1), Eqs. 9-10 (exact when it has no left neighbour)
+                const bool hi_slot = (kl >> 6) != 0;
+                const float Lsel = hi_slot ? L[SLOTS - 1] : L[0];
+                const float Usel = hi_slot ? U[SLOTS - 1] : U[0];
+                const float Ll = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Lsel), kl & 63));
+                const float Ul = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Usel), kl & 63));
+                const int j = i - W + kt;
+                if (lane == (kt & 63) && j >= 0 && j < n) {
+                    float lo, hi;
+                    if (kt >= 1 && j >= 1) {
+                        const float gj = gc[j];
+                        lo = __builtin_fmaxf(Ll - gj, gj - Ul);          // Eq. 9
+                        hi = Ul + gj;                                    // Eq. 10
+                    } else {
+                        float sacc = 0.0f;
+                        for (int p = 0; p < D; ++p) {
+                            const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
+                            sacc = __builtin_fmaf(t, t, sacc);
+                        }
+                        lo = hi = __builtin_sqrtf(sacc);
+                    }
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s)
+                        if (s == (kt >> 6)) { L[s] = lo; U[s] = hi; }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int k = lane + 64 * s;
+                const int j = i - W + k;
+                const bool cell = (k < KB) && j >= 0 && j < n;
+                // a safe lower bound of the Euclidean point distance, clamped at 0
+                const float safe = __builtin_fmaxf(__builtin_fmaf(-slack, U[s], L[s]), 0.0f);
+                cm[s] = __builtin_fminf(cmn[s], cell ? safe : INF);
+            }
+        }
+        // columns still in the band after the last row
+        float tail = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int k = lane + 64 * s;
+            const int j = m - 1 - W + k;
+            if (k < KB && j >= 0 && j < n && cm[s] < INF) tail += cm[s] * cm[s];
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) tail += __shfl_xor(tail, o);
+        if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)(acc + tail) * defl);
+    }
+}
+
+// ---------------------------------------------------------------- routing
+// After an advanced bound: lb = max(bound so far, new bound) (a value < 0
+// means "not evaluated").  Pairs with lb * keep > bsf are skipped (counted),
+// the others go to the next bound's list (with their lb) when that bound is
+// deployed for them, else to the DTW list.  Wave ballot + one atomic per
+// wave and output list.
+__global__ __launch_bounds__(256) void k_route(RouteArgs a) {
+    const int q = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int cnt = a.in_cnt[q];
+    const bool valid = e < cnt;
+    const double bsf = (double)key_bsf(a.key + q);
+    int ref = 0;
+    float lb = 0.0f;
+    if (valid) {
+        ref = (int)a.in_list[(int64_t)q * a.cap + e];
+        const float prev = a.lb_prev ? a.lb_prev[(int64_t)q * a.cap + e] : a.lb_mv[(int64_t)q * a.nc + ref];
+        const float nb = a.lb_new ? a.lb_new[(int64_t)q * a.cap + e] : -1.0f;   // null: not evaluated
+        lb = nb > prev ? nb : prev;
+    }
+    const bool pruned = valid && ((double)lb * a.keep > bsf);
+    const bool next = valid && !pruned && a.next_list && ((double)lb > a.next_e2 * bsf);
+    const bool dtw = valid && !pruned && !next;
+    const uint64_t bd = __ballot(dtw), bn = __ballot(next), bp = __ballot(pruned);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int based = 0, basen = 0;
+    if (lane == 0) {
+        if (bd) based = atomicAdd(&a.dtw_cnt[q], __popcll(bd));
+        if (bn) basen = atomicAdd(&a.next_cnt[q], __popcll(bn));
+        if (bp) atomicAdd(&a.pruned[q], __popcll(bp));
+    }
+    based = __shfl(based, 0);
+    basen = __shfl(basen, 0);
+    if (dtw) a.dtw_list[(int64_t)q * a.cap + based + __popcll(bd & below)] = (uint32_t)ref;
+    if (next) {
+        const int pos = basen + __popcll(bn & below);
+        a.next_list[(int64_t)q * a.cap + pos] = (uint32_t)ref;
+        a.next_lb[(int64_t)q * a.cap + pos] = lb;
+    }
+}
+
+// ----------------------------------------------------------------- launch
+hipError_t launch_query_steps(const float* Q, int nq, int m, int D, float* delta, hipStream_t s) {
+    const int64_t total = (int64_t)nq * m;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_query_steps, dim3(blocks), dim3(256), 0, s, Q, nq, m, D, delta);
+    return hipGetLastError();
+}
+
+size_t pc_boxes_lds_bytes(int max_pts, int K, int D) {
+    return (size_t)max_pts * (8 + 4) + (size_t)K * D * 2 * 4 + 16;
+}
+
+hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s) {
+    const size_t lds = pc_boxes_lds_bytes(a.max_pts, a.K, a.D);
+    hipLaunchKernelGGL(k_pc_boxes, dim3(a.ngroups, a.nq), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
+    if (a.D <= 4) hipLaunchKernelGGL(k_lb_pc<4>, dim3(nblocks), dim3(64), 0, s, a);
+    else if (a.D <= 8) hipLaunchKernelGGL(k_lb_pc<8>, dim3(nblocks), dim3(64), 0, s, a);
+    else if (a.D <= 16) hipLaunchKernelGGL(k_lb_pc<16>, dim3(nblocks), dim3(64), 0, s, a);
+    else if (a.D <= 32) hipLaunchKernelGGL(k_lb_pc<32>, dim3(nblocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_lb_pc<64>, dim3(nblocks), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s) {
+    const size_t lds = (size_t)a.m * 4 + 16;
+    if (2 * a.W + 1 <= 64) hipLaunchKernelGGL(k_lb_ti<1>, dim3(nblocks), dim3(64), lds, s, a);
+    else hipLaunchKernelGGL(k_lb_ti<2>, dim3(nblocks), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_route(const RouteArgs& a, int max_in, hipStream_t s) {
+    if (max_in <= 0) return hipSuccess;
+    dim3 grid((max_in + 255) / 256, a.nq);
+    hipLaunchKernelGGL(k_route, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// items per query for a list processed in chunks of `per` entries
+__global__ __launch_bounds__(1024) void k_list_scan(const int32_t* cnt, int cnt_uniform, int nq, int per,
+                                                    int32_t* prefix, int32_t* counter) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) { carry = 0; prefix[0] = 0; *counter = 0; }
+    __syncthreads();
+    for (int base = 0; base < nq; base += 1024) {
+        const int q = base + threadIdx.x;
+        const int c = cnt_uniform > 0 ? cnt_uniform : (q < nq ? cnt[q] : 0);
+        part[threadIdx.x] = q < nq ? (c + per - 1) / per : 0;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (q < nq) prefix[q + 1] = carry + part[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_list_items(const int32_t* __restrict__ prefix, int nq,
+                                                    int32_t* __restrict__ item_query) {
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int b = prefix[q], e = prefix[q + 1];
+        for (int t = b + threadIdx.x; t < e; t += blockDim.x) item_query[t] = q;
+    }
+}
+
+hipError_t launch_list_items(const int32_t* cnt, int cnt_uniform, int nq, int per, int32_t* prefix,
+                             int32_t* item_query, int32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, cnt, cnt_uniform, nq, per, prefix, counter);
+    hipLaunchKernelGGL(k_list_items, dim3(nq < 4096 ? nq : 4096), dim3(256), 0, s, prefix, nq, item_query);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) dst[t] = src[t];
+}
+
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_i32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0, s, src,
+                       dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace tcdtw

@@ -37,6 +37,24 @@ __device__ __forceinline__ double wave_shl1(double old, double v) {
     return __builtin_bit_cast(double, r);
 }
 
+// Next work item of a persistent one-wave loop: lane 0 takes it from the
+// counter and the value is read from lane 0 into a scalar register, so the
+// item is wave-uniform by construction and every exit and skip of the loop
+// that depends on it is a uniform branch.  (A shuffle broadcast leaves the
+// value in a vector register; the compiler may then treat the loop exits as
+// divergent and split the loop so that lanes 1..63 re-read the broadcast
+// while lane 0 waits at the atomic, which never ends.)  Call with all 64
+// lanes active.
+__device__ __forceinline__ int wave_next_item(int* counter) {
+    int v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(counter, 1);
+    return __builtin_amdgcn_readlane(v, 0);
+}
+
+// A condition made wave-uniform from lane 0's value (for conditions that are
+// equal in every lane but computed from vector registers).
+__device__ __forceinline__ bool wave_uniform(bool c) { return __builtin_amdgcn_readlane((int)c, 0) != 0; }
+
 __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
 template <typename T> __device__ __forceinline__ T vmin3(T a, T b, T c) { return vmin(vmin(a, b), c); }

@@ -124,6 +124,7 @@ struct KnnPlanDev {
     int32_t* counters;
     unsigned long long* key;
     unsigned long long* stats;
+    int32_t* clear[3];    // optional extra per-query counters zeroed with the others
 };
 
 // Persistent DTW over per-query candidate lists.
@@ -155,7 +156,10 @@ struct KnnFinalArgs {
     const uint32_t* list;
     const float* list_dist;
     const int32_t* cnt;
-    const int32_t* gcnt;       // advanced-bound list lengths (entries pruned later are counted there)
+    const int32_t* gcnt;       // gated pairs (advanced bounds)
+    const int32_t* cnt_mv;     // DTW-list length right after the LB_MV compaction (null: cnt)
+    const int32_t* pruned_pc;  // [nq] or null
+    const int32_t* pruned_ti;  // [nq] or null
     int32_t nc;
     double ratio;              // finalists: float32 DTW <= smallest * ratio
     int32_t* nn_idx;
@@ -177,6 +181,74 @@ int knn_dtw_max_pairs(int W, int D);
 // refill of RS / 4 positions must fit.
 inline int ring_size(int W) { return W <= 27 ? 64 : 128; }
 size_t knn_final_lds_bytes(int m, int n, int W, int D);
+
+// --------------------------------------------------------- advanced bounds
+struct PcArgs {
+    const float* Q;            // queries [nq][m][D]
+    const float* C;            // candidates [nc][n][D]
+    int32_t nq, nc, m, n, D, W;
+    int32_t Lv, K, w, ngroups, max_pts;
+    float floor_len;           // <= 0: 1e-5 * (range[1] - range[0])
+    const float* range;        // index value range (min, max)
+    float* boxes;              // [nq][ngroups][K][D][2]
+    int32_t* nbox;             // [nq][ngroups]
+    // list evaluation
+    const uint32_t* in_list;   // [nq][cap] or null (every candidate)
+    const int32_t* in_cnt;
+    int32_t in_uniform;        // > 0: every query lists this many entries
+    int32_t cap;
+    float* out_lb;             // [nq][cap]
+    const int32_t* prefix;
+    const int32_t* item_query;
+    int32_t* counter;
+    const unsigned long long* key;   // null: dense mode (no gate, no early stop)
+    const float* lb_mv;        // [nq][nc] (search mode)
+    double e2, keep;
+};
+
+struct TiArgs {
+    const float* Q;
+    const float* C;
+    const float* qstep;        // [nq][m] query steps
+    const float* gamma;        // [nc][n] candidate steps (index)
+    int32_t nq, nc, m, n, D, W, P, top;
+    const uint32_t* in_list;
+    int32_t cap;
+    float* out_lb;
+    const float* lb_in;        // [nq][cap] bound so far of each listed pair (search mode)
+    const int32_t* prefix;
+    const int32_t* item_query;
+    int32_t* counter;
+    const unsigned long long* key;
+    double e2;
+};
+
+struct RouteArgs {
+    int32_t nq, nc, cap;
+    const uint32_t* in_list;
+    const int32_t* in_cnt;
+    const float* lb_prev;      // [nq][cap] or null: take LB_MV from lb_mv
+    const float* lb_mv;        // [nq][nc]
+    const float* lb_new;       // [nq][cap], < 0 when not evaluated
+    const unsigned long long* key;
+    double keep, next_e2;
+    uint32_t* dtw_list;
+    int32_t* dtw_cnt;
+    uint32_t* next_list;       // null: no further bound
+    float* next_lb;
+    int32_t* next_cnt;
+    int32_t* pruned;           // [nq]
+};
+
+hipError_t launch_query_steps(const float* Q, int nq, int m, int D, float* delta, hipStream_t s);
+size_t pc_boxes_lds_bytes(int max_pts, int K, int D);
+hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s);
+hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_route(const RouteArgs& a, int max_in, hipStream_t s);
+hipError_t launch_list_items(const int32_t* cnt, int cnt_uniform, int nq, int per, int32_t* prefix,
+                             int32_t* item_query, int32_t* counter, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s);
 
 inline int nchunks(int D) { return (D + 3) / 4; }
 // Supported chunk counts (template instantiations); D is padded up to one of them.

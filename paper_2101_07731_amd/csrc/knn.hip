@@ -35,12 +35,16 @@ __device__ __forceinline__ float round_up_pos(double x) {
 
 // ------------------------------------------------------------------ setup
 __global__ void k_knn_init(int nq, unsigned long long* key, int32_t* cnt, int32_t* gcnt,
-                           int32_t* counters, unsigned long long* stats) {
+                           int32_t* counters, unsigned long long* stats, int32_t* c0, int32_t* c1,
+                           int32_t* c2) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int q = t; q < nq; q += gridDim.x * blockDim.x) {
         key[q] = 0x7f800000ffffffffull;     // best-so-far +inf, no candidate yet
         cnt[q] = 0;
         if (gcnt) gcnt[q] = 0;
+        if (c0) c0[q] = 0;
+        if (c1) c1[q] = 0;
+        if (c2) c2[q] = 0;
     }
     if (t < kNumCounters) counters[t] = 0;
     if (t < kNumStats) stats[t] = 0;
@@ -266,9 +270,7 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
     int staged_q = -1;
     unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1);
-        item = __shfl(item, 0);
+        const int item = wave_next_item(a.counter);
         if (item >= total) break;
         const int q = find_query(a.prefix, a.nq, item);
         const int chunk = item - a.prefix[q];
@@ -382,9 +384,7 @@ __global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
     const int total = a.prefix[a.nq];
     unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1);
-        item = __shfl(item, 0);
+        const int item = wave_next_item(a.counter);
         if (item >= total) break;
         const int q = a.item_query[item];
         const int chunk = item - a.prefix[q];
@@ -533,9 +533,7 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
     const int total = a.prefix[a.nq];
     unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1);
-        item = __shfl(item, 0);
+        const int item = wave_next_item(a.counter);
         if (item >= total) break;
         const int q = a.item_query[item];
         const int e = item - a.prefix[q];
@@ -662,15 +660,18 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
         int nseeds = 0;
         for (int k = 0; k < ns; ++k) nseeds += a.seeds[(int64_t)q * ns + k] >= 0;
         const int gl = a.gcnt ? a.gcnt[q] : 0;
-        const int pruned = a.nc - nseeds - nl - gl;
+        const int direct = a.cnt_mv ? a.cnt_mv[q] : nl;
+        const int pruned = a.nc - nseeds - direct - gl;
         if (pruned > 0) atomicAdd(&a.stats[kStPrunedMv], (unsigned long long)pruned);
+        if (a.pruned_pc && a.pruned_pc[q]) atomicAdd(&a.stats[kStPrunedPc], (unsigned long long)a.pruned_pc[q]);
+        if (a.pruned_ti && a.pruned_ti[q]) atomicAdd(&a.stats[kStPrunedTi], (unsigned long long)a.pruned_ti[q]);
     }
 }
 
 // ------------------------------------------------------------------ launch
 hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s) {
     hipLaunchKernelGGL(k_knn_init, dim3((p.nq + 255) / 256 + 1), dim3(256), 0, s, p.nq, p.key, p.cnt,
-                       p.gcnt, p.counters, p.stats);
+                       p.gcnt, p.counters, p.stats, p.clear[0], p.clear[1], p.clear[2]);
     if (p.env) {
         const int64_t total = (int64_t)((p.nq + kQT - 1) / kQT) * kQT * p.n * p.D;
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);

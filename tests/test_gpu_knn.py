@@ -134,3 +134,76 @@ def test_full_size_sampled(dev):
     np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
     assert np.all((idx >= 0) & (idx < len(Cs)))
     assert st["pruned_mv"] + st["dtw_started"] == 1000 * 10000
+
+
+def _pc_floor(Cs):
+    """The smallest cell length the library derives from the index: 1e-5 of the
+    float32 value range, computed as float32(1e-5 * float64(max - min))."""
+    rng = np.float32(Cs.max()) - np.float32(Cs.min())
+    return float(np.float32(1e-5 * np.float64(rng)))
+
+
+@pytest.mark.parametrize("case", [(8, 3, (1, 10), 2, 6, 6), (16, 4, (1, 5), 3, 4, 6), (33, 2, (1, 10), 2, 16, 3)],
+                         ids=["d8_W8_L2_K6", "d4_W16_L3_K4", "d2_W3_L2_K16_w3"])
+def test_lb_pc_dense_matrix(dev, case):
+    from paper_2101_07731_amd import search, synth
+    D, seed, frac, Lv, K, w = case
+    T = 80 if D != 2 else 33
+    Q, Cs = synth.cascade_knn(nq=11, nc=90, T=T, D=D, seed=30 + seed)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_pc dense", case)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="pc", frac=frac, pc_levels=Lv,
+                             pc_clusters=K, pc_group=w).cpu().numpy().astype(np.float64)
+    W = O.window_eff(T, T, 0, *frac)
+    fl = _pc_floor(Cs)
+    ref = np.array([[O.lb_pc(q, c, W, Lv=Lv, K=K, w=w, floor_len=fl) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12))
+    slack = 2 * (T + D + 5) * 2.0 ** -24 * 1.01 + 1e-7
+    np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
+
+
+@pytest.mark.parametrize("P,top", [(5, 1), (0, 0), (3, 0), (0, 1), (1, 0)])
+@pytest.mark.parametrize("frac", [(1, 10), (1, 5)])
+def test_lb_ti_dense_matrix(dev, P, top, frac):
+    from paper_2101_07731_amd import search, synth
+    T, D = 100, 6
+    Q, Cs = synth.cascade_knn(nq=9, nc=70, T=T, D=D, seed=40)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_ti dense", P, top, frac)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="ti", frac=frac, ti_period=P,
+                             ti_top=top).cpu().numpy().astype(np.float64)
+    W = O.window_eff(T, T, 0, *frac)
+    ref = np.array([[O.lb_ti(q, c, W, P=P, top=top) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12) + 1e-30)
+    # the rounding allowance lowers each point bound by at most ~(D/2 + 5 + r) u times its upper bound
+    np.testing.assert_allclose(lb, ref, rtol=2e-3, atol=1e-3 * max(1.0, ref.max()))
+
+
+@pytest.mark.parametrize("bounds", ["mv+pc", "mv+ti", "mv+pc+ti"])
+@pytest.mark.parametrize("frac", [(1, 20), (1, 10), (1, 5)])
+def test_cascade_with_advanced_bounds(dev, bounds, frac):
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn(nq=30, nc=700, T=96, D=8, seed=26)
+    Cs = np.concatenate([Cs, Cs[::9]])
+    say("knn", bounds, frac)
+    for e in (0.0, 0.1, 0.5):
+        idx, dist, st = run_knn(dev, Q, Cs, frac=frac, bounds=bounds, trigger_pc=e, trigger_ti=e)
+        check_against_oracle(idx, dist, Q, Cs, *frac)
+        assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == st["pairs"], st
+        if "pc" not in bounds:
+            assert st["pruned_pc"] == 0
+        if "ti" not in bounds:
+            assert st["pruned_ti"] == 0
+
+
+def test_full_size_sampled_full_cascade(dev):
+    """The benchmark workload with LB_MV, LB_PC and LB_TI deployed."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn()
+    idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds="mv+pc+ti")
+    say("stats full cascade", st)
+    sample = np.array([3, 400, 777])
+    ri, rd = O.knn_exhaustive(Q[sample], Cs, num=1, den=10)
+    np.testing.assert_array_equal(idx[sample], ri)
+    np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
+    assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == 1000 * 10000
