@@ -209,20 +209,68 @@ __device__ __forceinline__ int diag_core(int qb, int LQ, int cb, int LC, int R,
 }
 
 // ------------------------------------------------------------- row-systolic
-constexpr int kRowPad = 65;   // candidate / row-buffer positions left of column 0
+constexpr int kRowPad = 65;   // row-buffer positions left of column 0
 
-// One pair per wave.  sc: LDS float4 index of the staged candidate [k][LC]
-// (position j + kRowPad); the row buffer (LC values of type T) follows it.
-// xs: query rows in global memory.
-// Returns the DTW value in the lane m-1 mod 64 (others undefined).
+// Point t of a series (row-major [len][D]) as NCH float4 chunks; `sentinel`
+// in every component outside [0, len), 0 in padded dimensions.
+template <int NCH>
+__device__ __forceinline__ void load_point(const float* src, int len, int D, int t, float sentinel,
+                                           float4 (&out)[NCH]) {
+    if (t < 0 || t >= len) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) out[k] = make_float4(sentinel, sentinel, sentinel, sentinel);
+        return;
+    }
+    const float* p = src + (int64_t)t * D;
+    if ((D & 3) == 0) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k)
+            out[k] = (4 * k < D) ? *reinterpret_cast<const float4*>(p + 4 * k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (4 * k + e < D) ? p[4 * k + e] : 0.0f;
+            out[k] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+// Row-systolic mapping, one pair per wave: lane l owns row i0 + l of a
+// block of 64 rows and sweeps the block's band columns, lane l reading
+// column jlo - l + t at step t; up and diag come from lane l - 1 by a DPP
+// shift (lane 0 from the row buffer), left from the lane itself.
+//
+// LDS at float4 index sc: a ring of kRowRing = 128 candidate positions
+// ([k][128] float4, column j at slot (j + 64) mod 128), then the row buffer
+// (T[n + 2 kRowPad], column j at j + kRowPad) holding the last row of the
+// previous block.  At step t the wave reads columns jlo + t - 63 .. jlo + t,
+// so 128 positions hold everything live: at the start of a block columns
+// jlo - 63 .. jlo + 64 are loaded, and every 64 steps the next 64 columns
+// (prefetched into registers during the previous 64 steps) replace the 64
+// that no lane reads any more.  LDS therefore does not grow with the window
+// or the dimension count beyond 2 KB per float4 chunk.  Candidate positions
+// outside [0, n) hold -inf, query rows past m hold +inf, so cells outside
+// the matrix cost +inf.  xs: query rows, ys: candidate, in global memory.
+// Returns the DTW value in the lane (m - 1) mod 64 (others undefined).
+constexpr int kRowRing = 2 * kRowBlock;
+
 template <typename T, int NCH, bool SAVE, bool ABANDON>
-__device__ __forceinline__ T rows_core(int sc, int LC, const float* xs, int m,
+__device__ __forceinline__ T rows_core(int sc, const float* xs, const float* ys, int m,
                                        int n, int W, int D, int lane, uint32_t* codes,
                                        const Abandon& ab, bool& aband, int* blocks_done = nullptr) {
     const T INF = inf_v<T>();
-    T* rowbuf = reinterpret_cast<T*>(lds4 + sc + (size_t)LC * NCH);
-    for (int pos = lane; pos < LC; pos += kWave) rowbuf[pos] = (pos - kRowPad == -1) ? T(0) : INF;
-    __syncthreads();
+    const float NINF = -__builtin_inff();
+    constexpr int RS = kRowRing, mask = kRowRing - 1;
+    T* rowbuf = reinterpret_cast<T*>(lds4 + sc + RS * NCH);
+    const int LB = n + 2 * kRowPad;
+    for (int pos = lane; pos < LB; pos += kWave) rowbuf[pos] = (pos - kRowPad == -1) ? T(0) : INF;
+    auto put = [&](int j, const float4 (&v)[NCH]) {
+        const int slot = sc + ((j + kRowBlock) & mask);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) lds4[slot + k * RS] = v[k];
+    };
     const int nb = (m + kRowBlock - 1) / kRowBlock;
     const int band = min(n, 2 * W + kRowBlock);
     const int nwb = (band + kRowBlock - 1 + 15) / 16;
@@ -244,9 +292,17 @@ __device__ __forceinline__ T rows_core(int sc, int LC, const float* xs, int m,
         }
         const int jlo = max(0, i0 - W);
         const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
+        {   // columns jlo - 63 .. jlo + 64
+            float4 v0[NCH], v1[NCH];
+            load_point<NCH>(ys, n, D, jlo - (kRowBlock - 1) + lane, NINF, v0);
+            load_point<NCH>(ys, n, D, jlo + 1 + lane, NINF, v1);
+            put(jlo - (kRowBlock - 1) + lane, v0);
+            put(jlo + 1 + lane, v1);
+        }
+        __syncthreads();
         const int T_b = jhi - jlo + kRowBlock;
         const int k0 = jlo - i0 + W - 2 * lane;          // band offset k = t + k0 must lie in [0, 2W]
-        const int cl = sc + (jlo - lane + kRowPad);      // + k*LC + t
+        const int cs0 = jlo - lane + kRowBlock;          // ring slot of step t: (cs0 + t) & mask
         const int rb = jlo + kRowPad;                    // rowbuf index + t
         const int wb = jlo - (kRowBlock - 1) + kRowPad;  // lane 63 writes rowbuf[wb + t]
         T cur = INF;
@@ -255,35 +311,44 @@ __device__ __forceinline__ T rows_core(int sc, int LC, const float* xs, int m,
         const int tend = (n - 1) - jlo + (m - 1 - i0);
         uint32_t cw = 0;
         uint32_t* cp = SAVE ? codes + (int64_t)b * nwb * kWave + lane : nullptr;
-        for (int t = 0; t < T_b; ++t) {
-            float4 cv[NCH];
+        for (int t0 = 0; t0 < T_b; t0 += kRowBlock) {
+            // columns for steps t0 + 64 .. t0 + 127, written after steps t0 .. t0 + 63
+            const bool refill = t0 + kRowBlock < T_b;
+            float4 nx[NCH];
+            if (refill) load_point<NCH>(ys, n, D, jlo + t0 + kRowBlock + 1 + lane, NINF, nx);
+            const int t1 = min(T_b, t0 + kRowBlock);
+            for (int t = t0; t < t1; ++t) {
+                const int cl = sc + ((cs0 + t) & mask);
+                float4 cv[NCH];
 #pragma unroll
-            for (int k = 0; k < NCH; ++k) cv[k] = lds4[cl + k * LC + t];
-            const T up = wave_shr1(rowbuf[rb + t], cur);
-            const T diag = prevup;
-            prevup = up;
-            const T left = cur;
-            const T cost = point_cost<NCH>(qv, cv, T(0));
-            T best;
-            if (SAVE) {
-                uint32_t code = 0;
-                best = diag;
-                if (up < best) { best = up; code = 1; }
-                if (left < best) { best = left; code = 2; }
-                cw |= code << ((t & 15) * 2);
-                if ((t & 15) == 15 || t == T_b - 1) {
-                    cp[(int64_t)(t >> 4) * kWave] = cw;
-                    cw = 0;
+                for (int k = 0; k < NCH; ++k) cv[k] = lds4[cl + k * RS];
+                const T up = wave_shr1(rowbuf[rb + t], cur);
+                const T diag = prevup;
+                prevup = up;
+                const T left = cur;
+                const T cost = point_cost<NCH>(qv, cv, T(0));
+                T best;
+                if (SAVE) {
+                    uint32_t code = 0;
+                    best = diag;
+                    if (up < best) { best = up; code = 1; }
+                    if (left < best) { best = left; code = 2; }
+                    cw |= code << ((t & 15) * 2);
+                    if ((t & 15) == 15 || t == T_b - 1) {
+                        cp[(int64_t)(t >> 4) * kWave] = cw;
+                        cw = 0;
+                    }
+                } else {
+                    best = vmin3(diag, up, left);
                 }
-            } else {
-                best = vmin3(diag, up, left);
+                T v = add_cost(cost, best);
+                const unsigned kb = (unsigned)(t + k0);
+                v = (kb <= (unsigned)(2 * W)) ? v : INF;
+                cur = v;
+                if (lane == kRowBlock - 1) rowbuf[wb + t] = v;
+                if (last && t == tend && lane == m - 1 - i0) result = v;
             }
-            T v = add_cost(cost, best);
-            const unsigned kb = (unsigned)(t + k0);
-            v = (kb <= (unsigned)(2 * W)) ? v : INF;
-            cur = v;
-            if (lane == kRowBlock - 1) rowbuf[wb + t] = v;
-            if (last && t == tend && lane == m - 1 - i0) result = v;
+            if (refill) put(jlo + t0 + kRowBlock + 1 + lane, nx);
         }
         __syncthreads();
         if (ABANDON && b + 1 < nb) {
@@ -302,6 +367,11 @@ __device__ __forceinline__ T rows_core(int sc, int LC, const float* xs, int m,
         }
     }
     return result;
+}
+
+// LDS bytes of rows_core for candidate length n (tbytes = sizeof(T)).
+__host__ __device__ inline size_t rows_core_lds(int n, int nch, int tbytes) {
+    return (size_t)kRowRing * nch * 16 + (size_t)(n + 2 * kRowPad) * tbytes;
 }
 
 }  // namespace tcdtw

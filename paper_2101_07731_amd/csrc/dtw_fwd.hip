@@ -16,10 +16,13 @@
 //    point and one new candidate point per round from LDS.
 //  * row-systolic blocks (any W_eff, used above 63): lane l owns row
 //    i0 + l of a block of 64 rows and sweeps the block's band columns; the
-//    last row of a block is kept in an LDS row buffer for the next block.
+//    last row of a block is kept in an LDS row buffer for the next block,
+//    and the candidate streams through a 128-position LDS ring refilled
+//    every 64 steps (so LDS does not grow with the window).
 //
-// Series are staged in LDS as [chunk][t][4] floats (conflict-free 16-byte
-// reads) with sentinel points outside the series: +inf on the query side,
+// Diagonal pairs stage whole series in LDS as [chunk][t][4] floats
+// (conflict-free 16-byte reads) with sentinel points outside the series
+// (the ring of the row mapping uses the same sentinels): +inf on the query side,
 // -inf on the candidate side, so a cell outside the matrix has cost +inf
 // and no edge test is needed.  The single padding diagonal of each pair is
 // forced to +inf.
@@ -37,9 +40,7 @@ size_t diag_lds_bytes(int m, int n, int W, int D, int P) {
 }
 
 size_t rows_lds_bytes(int n, int W, int D, bool f64) {
-    (void)W;
-    const size_t LC = (size_t)n + 2 * kRowPad;
-    return LC * (size_t)nch_pad(D) * 16 + LC * (f64 ? 8 : 4);
+    return rows_core_lds(n, nch_pad(D), f64 ? 8 : 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -118,7 +119,8 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
 // column j = jlo + t - l.  up = lane l-1's previous value (lane 0: the
 // row buffer), diag = the up value of the previous step, left = own
 // previous value.  Lane 63 writes its row into the row buffer 63 columns
-// behind lane 0's reads, so one buffer serves both.
+// behind lane 0's reads, so one buffer serves both.  The candidate streams
+// through a ring (rows_core in dtw_core.h).
 // ---------------------------------------------------------------------------
 template <typename T, int NCH, bool SAVE>
 __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
@@ -136,11 +138,9 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
         m = d.m; n = d.n; W = d.W; out = d.out;
         xoff = d.xoff; yoff = d.yoff; soff = d.saved_off;
     }
-    const int LC = n + 2 * kRowPad;
-    stage_series<NCH>(0, LC, -kRowPad, a.y + yoff, n, D, -__builtin_inff(), lane, kWave);
     Abandon ab{nullptr, 0.0f, 0};
     bool aband = false;
-    const T v = rows_core<T, NCH, SAVE, false>(0, LC, a.x + xoff, m, n, W, D, lane,
+    const T v = rows_core<T, NCH, SAVE, false>(0, a.x + xoff, a.y + yoff, m, n, W, D, lane,
                                                SAVE ? a.codes + soff : nullptr, ab, aband);
     if (lane == (m - 1) % kRowBlock) {
         a.dist[out] = (float)v;

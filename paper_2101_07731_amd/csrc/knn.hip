@@ -338,32 +338,6 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
     }
 }
 
-// Point t of a series (row-major [len][D]) as NCH float4 chunks; `sentinel`
-// in every component outside [0, len), 0 in padded dimensions.
-template <int NCH>
-__device__ __forceinline__ void load_point(const float* src, int len, int D, int t, float sentinel,
-                                           float4 (&out)[NCH]) {
-    if (t < 0 || t >= len) {
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) out[k] = make_float4(sentinel, sentinel, sentinel, sentinel);
-        return;
-    }
-    const float* p = src + (int64_t)t * D;
-    if ((D & 3) == 0) {
-#pragma unroll
-        for (int k = 0; k < NCH; ++k)
-            out[k] = (4 * k < D) ? *reinterpret_cast<const float4*>(p + 4 * k) : make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (4 * k + e < D) ? p[4 * k + e] : 0.0f;
-            out[k] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-    }
-}
-
 // Diagonal mapping with ring buffers: each staged series keeps only RS
 // consecutive positions (slot = position mod RS, slots 0..7 mirrored after
 // RS so that four consecutive positions never wrap).  The live window of a
@@ -528,7 +502,6 @@ __global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
 template <int NCH>
 __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
     const int lane = threadIdx.x;
-    const int LC = a.n + 2 * kRowPad;
     const int sc = 0;
     const int total = a.prefix[a.nq];
     unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
@@ -538,18 +511,17 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
         const int q = a.item_query[item];
         const int e = item - a.prefix[q];
         const int ref = (int)a.list[(int64_t)q * a.cap + e];
+        const float* cser = a.C + (int64_t)(ref < 0 ? 0 : ref) * a.n * a.D;
         __syncthreads();
-        stage_series<NCH>(sc, LC, -kRowPad, a.C + (int64_t)(ref < 0 ? 0 : ref) * a.n * a.D, a.n, a.D,
-                          -__builtin_inff(), lane, kWave);
         Abandon ab{a.key + q, a.gamma, ~0ull};
         bool aband = false;
         float v;
         int blocks = 0;
         if (a.abandon)
-            v = rows_core<float, NCH, false, true>(sc, LC, a.Q + (int64_t)q * a.m * a.D, a.m,
+            v = rows_core<float, NCH, false, true>(sc, a.Q + (int64_t)q * a.m * a.D, cser, a.m,
                                                    a.n, a.W, a.D, lane, nullptr, ab, aband, &blocks);
         else
-            v = rows_core<float, NCH, false, false>(sc, LC, a.Q + (int64_t)q * a.m * a.D, a.m,
+            v = rows_core<float, NCH, false, false>(sc, a.Q + (int64_t)q * a.m * a.D, cser, a.m,
                                                     a.n, a.W, a.D, lane, nullptr, ab, aband, &blocks);
         if (lane == (a.m - 1) % kRowBlock) {
             float out = __builtin_inff();
@@ -620,13 +592,11 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
                 __syncthreads();
                 double v;
                 if (ROWS) {
-                    const int LCr = a.n + 2 * kRowPad;
-                    stage_series<NCH>(sc, LCr, -kRowPad, a.C + (int64_t)r * a.n * a.D, a.n, a.D,
-                                      -__builtin_inff(), lane, kWave);
                     Abandon ab{nullptr, 0.0f, 0};
                     bool aband = false;
-                    v = rows_core<double, NCH, false, false>(sc, LCr, a.Q + (int64_t)q * a.m * a.D,
-                                                             a.m, a.n, a.W, a.D, lane, nullptr, ab, aband);
+                    v = rows_core<double, NCH, false, false>(sc, a.Q + (int64_t)q * a.m * a.D,
+                                                             a.C + (int64_t)r * a.n * a.D, a.m, a.n, a.W,
+                                                             a.D, lane, nullptr, ab, aband);
                     v = __shfl(v, (a.m - 1) % kRowBlock);
                 } else {
                     stage_series<NCH>(sc, LC, g.cfirst(), a.C + (int64_t)r * a.n * a.D, a.n, a.D,
@@ -744,7 +714,7 @@ hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s) {
 
 size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P) {
     (void)m;
-    if (W > kDiagMaxW) return rows_lds_bytes(n, W, D, false);
+    if (W > kDiagMaxW) return rows_core_lds(n, nch_pad(D), 4);
     return (size_t)(1 + P) * nch_pad(D) * (ring_size(W) + 8) * 16;
 }
 
@@ -758,7 +728,7 @@ int knn_dtw_max_pairs(int W, int D) {
 }
 
 size_t knn_final_lds_bytes(int m, int n, int W, int D) {
-    if (W > kDiagMaxW) return rows_lds_bytes(n, W, D, true);
+    if (W > kDiagMaxW) return rows_core_lds(n, nch_pad(D), 8);
     DiagGeom g;
     g.init(m, n, W);
     return (size_t)(g.LQ + g.LC) * nch_pad(D) * 16;
