@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define TC_DTW_ABI_VERSION 1
+#define TC_DTW_ABI_VERSION 2
 
 typedef struct ihipStream_t* tc_dtw_stream; /* same type as hipStream_t; NULL = default stream */
 
@@ -55,14 +55,18 @@ typedef enum {
     TC_DTW_ERR_DEVICE = 4       /* no usable gfx950 device, or a HIP call failed */
 } tc_dtw_status;
 
-/* A set of D-dimensional float32 series.
- *   data    DEVICE  series s occupies data[offset[s] .. offset[s] + len[s]*dim),
+/* A set of float32 series.
+ *   data    DEVICE  series s occupies data[offset[s] .. offset[s] + len[s]*D_s),
  *                   row-major [t][d] (a torch [B, T, D] tensor when uniform).
- *   offset  HOST    per-series start in floats, or NULL: s * uniform_len * dim.
+ *   offset  HOST    per-series start in floats, or NULL: the series packed
+ *                   back to back in order (s * uniform_len * dim when uniform).
  *   len     HOST    per-series length, or NULL: every series has uniform_len.
  *   count   number of series (>= 1).
- *   dim     D, shared by all series of the set (1..64).
- *   uniform_len  length of every series when len == NULL, else ignored. */
+ *   dim     D of every series (1..64) when dims == NULL, else ignored.
+ *   uniform_len  length of every series when len == NULL, else ignored.
+ *   dims    HOST    per-series D_s (1..64), or NULL: every series has dim.
+ *                   Accepted by the pair calls (banded, backward, pairs
+ *                   plans); the search calls need one D per set. */
 typedef struct {
     const float* data;
     const int64_t* offset;
@@ -70,6 +74,7 @@ typedef struct {
     int32_t count;
     int32_t dim;
     int32_t uniform_len;
+    const int32_t* dims;
 } tc_dtw_batch;
 
 /* Window specification (see conventions above). */
@@ -130,6 +135,77 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
                               const void* saved, const float* grad_dist,
                               float* grad_x, float* grad_y,
                               void* ws, size_t ws_bytes, tc_dtw_stream stream);
+
+/* ------------------------------------------------- reusable pair plans ---
+ * A plan fixes the shapes of a batch of pairs once: lengths, dims, W_eff,
+ * which wave mapping evaluates each pair (diagonal pairs for narrow bands,
+ * row-systolic blocks otherwise), and the order of the work.  The pairs are
+ * grouped into classes of one mapping and one dimension class, each run by
+ * one persistent launch whose waves take pairs, longest first, from a
+ * device counter.  tc_dtw_banded_run and tc_dtw_backward_run then only
+ * enqueue kernels (no host-to-device copies, no allocation), so a caller
+ * can capture them in a HIP graph and replay them with new data laid out
+ * like the planned batch.  This is the batched form of Sec. 2, Eq. 1 over
+ * many pairs of uneven lengths and dims; results equal tc_dtw_banded's.
+ *
+ * tc_dtw_tuning (HOST, may be NULL for the defaults):
+ *   diag_max_w    pairs with W_eff <= diag_max_w (and whose two series fit
+ *                 32 KB of LDS) use the diagonal mapping, the others the
+ *                 row mapping; -1..63, default 63.
+ *   waves_per_cu  resident waves per CU of the persistent launches, 1..32;
+ *                 0 means 16.  Fewer when a class's LDS does not allow them.
+ * tc_dtw_pairs_plan_bytes: size of the DEVICE plan buffer (0 on invalid
+ *   arguments).  x->data and y->data are not read by the plan calls.
+ * tc_dtw_pairs_plan_build: fills `plan` (HOST) and copies the pair
+ *   descriptors into `buf` (DEVICE, caller-owned, must outlive every run)
+ *   on `stream`, then waits for that copy.  Errors: as tc_dtw_banded, and
+ *   UNSUPPORTED when the batch needs more than TC_DTW_PLAN_MAX_CLASSES
+ *   classes.
+ * tc_dtw_banded_run: as tc_dtw_banded on x, y (DEVICE base pointers; the
+ *   planned offsets are relative to them); `saved` (DEVICE, or NULL) must
+ *   hold plan->saved_bytes.  A run resets the plan's counters itself; runs
+ *   of one plan must not overlap (they share the counters).
+ * tc_dtw_backward_run: as tc_dtw_backward, with `saved` written by a
+ *   tc_dtw_banded_run of the same plan. */
+typedef struct {
+    int32_t diag_max_w;
+    int32_t waves_per_cu;
+} tc_dtw_tuning;
+
+#define TC_DTW_PLAN_MAX_CLASSES 32
+
+typedef struct {
+    int32_t rows;        /* 1: row mapping, 0: diagonal mapping */
+    int32_t wodd;        /* diagonal mapping: W_eff of every pair of the class is odd */
+    int32_t dim;         /* largest D of the class */
+    int32_t nitems;      /* pairs in the class */
+    int32_t maxm, maxn, maxw;
+    int32_t reserved;
+    int64_t max_words;   /* largest argmin-code record of the class (u32 words) */
+    int64_t desc_off;    /* byte offset of the class's descriptors in the plan buffer */
+} tc_dtw_plan_class;
+
+typedef struct {
+    void* buf;           /* DEVICE plan buffer */
+    size_t bytes;
+    int32_t npairs;
+    int32_t nclasses;
+    int32_t waves_per_cu;
+    int32_t reserved;
+    int64_t saved_bytes; /* bytes of the `saved` buffer of a recording forward */
+    tc_dtw_plan_class cls[TC_DTW_PLAN_MAX_CLASSES];
+} tc_dtw_pairs_plan;
+
+size_t tc_dtw_pairs_plan_bytes(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_window win,
+                               const tc_dtw_tuning* tune);
+tc_dtw_status tc_dtw_pairs_plan_build(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_window win,
+                                      const tc_dtw_tuning* tune, void* buf, size_t bytes,
+                                      tc_dtw_pairs_plan* plan, tc_dtw_stream stream);
+tc_dtw_status tc_dtw_banded_run(const tc_dtw_pairs_plan* plan, const float* x, const float* y,
+                                uint32_t flags, float* dist, void* saved, tc_dtw_stream stream);
+tc_dtw_status tc_dtw_backward_run(const tc_dtw_pairs_plan* plan, const float* x, const float* y,
+                                  const void* saved, const float* grad_dist, float* grad_x,
+                                  float* grad_y, tc_dtw_stream stream);
 
 /* -------------------------------------------------------------- index ---
  * tc_dtw_build_index: prepares a candidate (reference) set for repeated

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcdtw.so")
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
 F64 = 1
+ABI_VERSION = 2
 
 
 class TcDtwError(RuntimeError):
@@ -25,7 +26,26 @@ class TcDtwError(RuntimeError):
 class Batch(C.Structure):
     _fields_ = [("data", C.c_void_p), ("offset", C.POINTER(C.c_int64)),
                 ("len", C.POINTER(C.c_int32)), ("count", C.c_int32), ("dim", C.c_int32),
-                ("uniform_len", C.c_int32)]
+                ("uniform_len", C.c_int32), ("dims", C.POINTER(C.c_int32))]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("diag_max_w", C.c_int32), ("waves_per_cu", C.c_int32)]
+
+
+PLAN_MAX_CLASSES = 32
+
+
+class PlanClass(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("wodd", C.c_int32), ("dim", C.c_int32), ("nitems", C.c_int32),
+                ("maxm", C.c_int32), ("maxn", C.c_int32), ("maxw", C.c_int32), ("reserved", C.c_int32),
+                ("max_words", C.c_int64), ("desc_off", C.c_int64)]
+
+
+class PairsPlan(C.Structure):
+    _fields_ = [("buf", C.c_void_p), ("bytes", C.c_size_t), ("npairs", C.c_int32), ("nclasses", C.c_int32),
+                ("waves_per_cu", C.c_int32), ("reserved", C.c_int32), ("saved_bytes", C.c_int64),
+                ("cls", PlanClass * PLAN_MAX_CLASSES)]
 
 
 class Window(C.Structure):
@@ -71,6 +91,13 @@ _SIGS = {
     "tc_dtw_backward_workspace_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
     "tc_dtw_backward": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tc_dtw_pairs_plan_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window, C.POINTER(Tuning)]),
+    "tc_dtw_pairs_plan_build": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.POINTER(Tuning),
+                                          C.c_void_p, C.c_size_t, C.POINTER(PairsPlan), C.c_void_p]),
+    "tc_dtw_banded_run": (C.c_int, [C.POINTER(PairsPlan), C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    "tc_dtw_backward_run": (C.c_int, [C.POINTER(PairsPlan), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
     "tc_dtw_index_bytes": (C.c_size_t, [C.POINTER(Batch)]),
     "tc_dtw_build_index": (C.c_int, [C.POINTER(Batch), C.c_void_p, C.c_size_t, C.POINTER(Index), C.c_void_p]),
     "tc_dtw_knn_params_default": (None, [C.POINTER(KnnParams)]),
@@ -97,7 +124,7 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    if L.tc_dtw_abi_version() != 1:
+    if L.tc_dtw_abi_version() != ABI_VERSION:
         raise ImportError("libtcdtw.so ABI version mismatch")
     _lib = L
     return L

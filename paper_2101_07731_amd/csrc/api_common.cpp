@@ -50,13 +50,23 @@ tc_dtw_status read_set(const tc_dtw_batch* b, const char* what, HostSet& out) {
     if (!b) return fail(TC_DTW_ERR_INVALID, w + ": null batch");
     if (!b->data) return fail(TC_DTW_ERR_INVALID, w + ": null data pointer");
     if (b->count < 1) return fail(TC_DTW_ERR_INVALID, w + ": count must be >= 1");
-    if (b->dim < 1) return fail(TC_DTW_ERR_INVALID, w + ": dim must be >= 1");
-    if (b->dim > 64) return fail(TC_DTW_ERR_UNSUPPORTED, w + ": dim > 64 is not supported");
     out = HostSet();
     out.count = b->count;
-    out.dim = b->dim;
     out.data = b->data;
-    if (!b->len && !b->offset) {
+    if (b->dims) {
+        out.mixed = true;
+        out.dims.assign(b->dims, b->dims + b->count);
+        for (int s = 0; s < b->count; ++s) {
+            if (out.dims[s] < 1) return fail(TC_DTW_ERR_INVALID, w + ": every dims[s] must be >= 1");
+            if (out.dims[s] > 64) return fail(TC_DTW_ERR_UNSUPPORTED, w + ": dim > 64 is not supported");
+            if (out.dims[s] > out.dim) out.dim = out.dims[s];
+        }
+    } else {
+        if (b->dim < 1) return fail(TC_DTW_ERR_INVALID, w + ": dim must be >= 1");
+        if (b->dim > 64) return fail(TC_DTW_ERR_UNSUPPORTED, w + ": dim > 64 is not supported");
+        out.dim = b->dim;
+    }
+    if (!b->len && !b->offset && !b->dims) {
         if (b->uniform_len < 1) return fail(TC_DTW_ERR_INVALID, w + ": uniform_len must be >= 1");
         out.uniform = true;
         out.ulen = b->uniform_len;
@@ -72,7 +82,7 @@ tc_dtw_status read_set(const tc_dtw_batch* b, const char* what, HostSet& out) {
         out.len[s] = L;
         out.off[s] = b->offset ? b->offset[s] : next;
         if (out.off[s] < 0) return fail(TC_DTW_ERR_INVALID, w + ": negative offset");
-        next = out.off[s] + (int64_t)L * b->dim;
+        next = out.off[s] + (int64_t)L * out.dimension(s);
         if (L > out.maxlen) out.maxlen = L;
     }
     return TC_DTW_OK;

@@ -19,14 +19,17 @@ tc_dtw_status check_device();
 
 // Host view of a batch: lengths and float offsets of every series.
 struct HostSet {
-    int count = 0, dim = 0;
-    bool uniform = false;
+    int count = 0, dim = 0;       // dim: the largest D of the set
+    bool uniform = false;         // one length and one D, packed densely
+    bool mixed = false;           // per-series D given
     int ulen = 0;
     int maxlen = 0;
     const float* data = nullptr;
     std::vector<int32_t> len;
     std::vector<int64_t> off;
+    std::vector<int32_t> dims;
     int length(int s) const { return uniform ? ulen : len[s]; }
+    int dimension(int s) const { return mixed ? dims[s] : dim; }
     int64_t offset(int s) const { return uniform ? (int64_t)s * ulen * dim : off[s]; }
 };
 

@@ -78,6 +78,7 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     tc_dtw_status st;
     if ((st = check_index(ix)) != TC_DTW_OK) return st;
     if ((st = read_set(qb, "queries", Qs)) != TC_DTW_OK) return st;
+    if (Qs.mixed) return fail(TC_DTW_ERR_UNSUPPORTED, "a search needs one dim for all queries (dims must be NULL)");
     if ((st = check_params(p)) != TC_DTW_OK) return st;
     if (Qs.dim != ix->dim) return fail(TC_DTW_ERR_INVALID, "queries and index have different dims");
     if (!Qs.uniform || ix->uniform_len <= 0)
@@ -310,7 +311,7 @@ void tc_dtw_knn_params_default(tc_dtw_knn_params* p) {
 
 size_t tc_dtw_index_bytes(const tc_dtw_batch* refs) {
     HostSet R;
-    if (read_set(refs, "refs", R) != TC_DTW_OK) return 0;
+    if (read_set(refs, "refs", R) != TC_DTW_OK || R.mixed) return 0;
     return index_layout(R).bytes;
 }
 
@@ -319,6 +320,7 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
     HostSet R;
     tc_dtw_status st = read_set(refs, "refs", R);
     if (st != TC_DTW_OK) return st;
+    if (R.mixed) return fail(TC_DTW_ERR_UNSUPPORTED, "an index needs one dim for all references (dims must be NULL)");
     if (!buf || !out) return fail(TC_DTW_ERR_INVALID, "null index buffer or output");
     const IndexLayout L = index_layout(R);
     if (bytes < L.bytes) return fail(TC_DTW_ERR_WORKSPACE, "index buffer smaller than tc_dtw_index_bytes()");

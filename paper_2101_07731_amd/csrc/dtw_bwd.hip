@@ -25,9 +25,9 @@ struct CodeMap {
     // row layout
     int W, nwb;
     bool diag;
-    __device__ void init(int m, int n, int W_) {
+    __device__ void init(int m, int n, int W_, bool rows) {
         W = W_;
-        diag = (W <= kDiagMaxW);
+        diag = !rows;
         G = W + 1;
         off = W + (W & 1);
         const int tmax = min(n, 2 * W + kRowBlock) + kRowBlock - 1;
@@ -51,29 +51,30 @@ struct CodeMap {
     }
 };
 
-__global__ __launch_bounds__(64) void dtw_bwd_kernel(DtwBwdArgs a) {
+__device__ void bwd_item(const DtwBwdArgs& a, int item) {
     extern __shared__ int32_t sbw[];
     const int lane = threadIdx.x;
-    int m, n, W, pid;
+    int m, n, W, pid, D;
+    bool rows;
     int64_t xoff, yoff, soff;
     if (a.uniform) {
-        m = a.m; n = a.n; W = a.W; pid = blockIdx.x;
+        m = a.m; n = a.n; W = a.W; pid = item; D = a.D;
+        rows = a.urows != 0;
         xoff = (int64_t)pid * m * a.D; yoff = (int64_t)pid * n * a.D;
         soff = (int64_t)pid * a.codes_stride;
     } else {
-        const PairDesc d = a.desc[blockIdx.x];
-        m = d.m; n = d.n; W = d.W; pid = d.out;
+        const PairDesc d = a.desc[item];
+        m = d.m; n = d.n; W = d.W; pid = d.out; D = d.D; rows = d.rows != 0;
         xoff = d.xoff; yoff = d.yoff; soff = d.saved_off;
     }
-    const int D = a.D;
     int32_t* rlo = sbw;
     int32_t* rhi = rlo + m;
     int32_t* clo = rhi + m;
     int32_t* chi = clo + n;
     uint32_t* scodes = reinterpret_cast<uint32_t*>(sbw + a.runs_ints);
     CodeMap cm;
-    cm.init(m, n, W);
-    const int64_t words = codes_words(m, n, W);
+    cm.init(m, n, W, rows);
+    const int64_t words = codes_words(m, n, W, rows);
     const bool staged = words <= a.stage_cap;
     const uint32_t* gcodes = a.codes + soff;
     if (staged) {
@@ -129,16 +130,34 @@ __global__ __launch_bounds__(64) void dtw_bwd_kernel(DtwBwdArgs a) {
     }
 }
 
-hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int maxW, int nitems,
-                          hipStream_t s) {
+__global__ __launch_bounds__(64) void dtw_bwd_kernel(DtwBwdArgs a) {
+    if (!a.counter) {
+        bwd_item(a, blockIdx.x);
+        return;
+    }
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.nitems) break;
+        __syncthreads();
+        bwd_item(a, item);
+    }
+}
+
+size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words) {
+    const int64_t cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
+    return (size_t)(2 * (maxm + maxn)) * 4 + (size_t)cap * 4;
+}
+
+hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int nitems,
+                          int grid, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     DtwBwdArgs b = a;
     b.runs_ints = 2 * (maxm + maxn);
     // the kernel stages a pair's codes only when they fit the reserved words
-    const int64_t words = codes_words(maxm, maxn, maxW);
-    b.stage_cap = words < kBwdCodeLdsWords ? words : kBwdCodeLdsWords;
-    const size_t lds = (size_t)b.runs_ints * 4 + (size_t)b.stage_cap * 4;
-    hipLaunchKernelGGL(dtw_bwd_kernel, dim3(nitems), dim3(64), lds, s, b);
+    b.stage_cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
+    b.nitems = nitems;
+    const size_t lds = bwd_lds_bytes(maxm, maxn, max_words);
+    hipLaunchKernelGGL(dtw_bwd_kernel, dim3(b.counter ? grid : nitems), dim3(64), lds, s, b);
     return hipGetLastError();
 }
 

@@ -54,18 +54,17 @@ size_t rows_lds_bytes(int n, int W, int D, bool f64) {
 // (delta = W + 1) and the bottom even slot when W is odd (delta = -W - 1).
 // ---------------------------------------------------------------------------
 template <typename T, int NCH, bool SAVE, bool WODD>
-__global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
+__device__ __forceinline__ void diag_item(const DtwFwdArgs& a, int item) {
     const int lane = threadIdx.x;
-    const int D = a.D;
-    int m, n, W, P;
+    int m, n, W, P, D;
     int64_t xoff0 = 0, yoff0 = 0, soff0 = 0;
     int out0;
     if (a.uniform) {
-        m = a.m; n = a.n; W = a.W; P = a.P;
-        out0 = blockIdx.x * P;
+        m = a.m; n = a.n; W = a.W; P = a.P; D = a.D;
+        out0 = item * P;
     } else {
-        const PairDesc d = a.desc[blockIdx.x];
-        m = d.m; n = d.n; W = d.W; P = 1;
+        const PairDesc d = a.desc[item];
+        m = d.m; n = d.n; W = d.W; P = 1; D = d.D;
         xoff0 = d.xoff; yoff0 = d.yoff; soff0 = d.saved_off; out0 = d.out;
     }
     DiagGeom g;
@@ -113,6 +112,21 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
     }
 }
 
+// One item per block, or persistent waves over a.nitems items.
+template <typename T, int NCH, bool SAVE, bool WODD>
+__global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
+    if (!a.counter) {
+        diag_item<T, NCH, SAVE, WODD>(a, blockIdx.x);
+        return;
+    }
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.nitems) break;
+        __syncthreads();
+        diag_item<T, NCH, SAVE, WODD>(a, item);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row-systolic mapping: one pair per wave.  Block b holds rows
 // i0 = 64 b .. i0 + 63; lane l owns row i0 + l and at step t evaluates
@@ -123,19 +137,18 @@ __global__ __launch_bounds__(64) void dtw_diag_kernel(DtwFwdArgs a) {
 // through a ring (rows_core in dtw_core.h).
 // ---------------------------------------------------------------------------
 template <typename T, int NCH, bool SAVE>
-__global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
+__device__ __forceinline__ void rows_item(const DtwFwdArgs& a, int item) {
     const int lane = threadIdx.x;
-    const int D = a.D;
-    int m, n, W, out;
+    int m, n, W, out, D;
     int64_t xoff, yoff, soff;
     if (a.uniform) {
-        m = a.m; n = a.n; W = a.W;
-        out = blockIdx.x;
+        m = a.m; n = a.n; W = a.W; D = a.D;
+        out = item;
         xoff = (int64_t)out * m * D; yoff = (int64_t)out * n * D;
         soff = (int64_t)out * a.codes_stride;
     } else {
-        const PairDesc d = a.desc[blockIdx.x];
-        m = d.m; n = d.n; W = d.W; out = d.out;
+        const PairDesc d = a.desc[item];
+        m = d.m; n = d.n; W = d.W; out = d.out; D = d.D;
         xoff = d.xoff; yoff = d.yoff; soff = d.saved_off;
     }
     Abandon ab{nullptr, 0.0f, 0};
@@ -148,53 +161,79 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
     }
 }
 
+template <typename T, int NCH, bool SAVE>
+__global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
+    if (!a.counter) {
+        rows_item<T, NCH, SAVE>(a, blockIdx.x);
+        return;
+    }
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.nitems) break;
+        __syncthreads();
+        rows_item<T, NCH, SAVE>(a, item);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launch: the mapping is chosen by the largest W_eff of the launch.
 // ---------------------------------------------------------------------------
 
 template <typename T, int NCH, bool SAVE>
-static hipError_t launch_nch(const DtwFwdArgs& a, int maxW, int nitems, size_t lds, hipStream_t s) {
-    if (maxW <= kDiagMaxW) {
+static hipError_t launch_nch(const DtwFwdArgs& a, bool rows, int grid, size_t lds, hipStream_t s) {
+    if (!rows) {
         // every item of a launch shares the parity of W (a ragged caller splits by parity)
         if (a.wodd) {
-            hipLaunchKernelGGL((dtw_diag_kernel<T, NCH, SAVE, true>), dim3(nitems), dim3(64), lds, s, a);
+            hipLaunchKernelGGL((dtw_diag_kernel<T, NCH, SAVE, true>), dim3(grid), dim3(64), lds, s, a);
         } else {
-            hipLaunchKernelGGL((dtw_diag_kernel<T, NCH, SAVE, false>), dim3(nitems), dim3(64), lds, s, a);
+            hipLaunchKernelGGL((dtw_diag_kernel<T, NCH, SAVE, false>), dim3(grid), dim3(64), lds, s, a);
         }
     } else {
-        hipLaunchKernelGGL((dtw_rows_kernel<T, NCH, SAVE>), dim3(nitems), dim3(64), lds, s, a);
+        hipLaunchKernelGGL((dtw_rows_kernel<T, NCH, SAVE>), dim3(grid), dim3(64), lds, s, a);
     }
     return hipGetLastError();
 }
 
 template <typename T, bool SAVE>
-static hipError_t launch_t(const DtwFwdArgs& a, int maxW, int nitems, size_t lds, hipStream_t s) {
+static hipError_t launch_t(const DtwFwdArgs& a, bool rows, int grid, size_t lds, hipStream_t s) {
     switch (nch_pad(a.D)) {
-        case 1: return launch_nch<T, 1, SAVE>(a, maxW, nitems, lds, s);
-        case 2: return launch_nch<T, 2, SAVE>(a, maxW, nitems, lds, s);
-        case 3: return launch_nch<T, 3, SAVE>(a, maxW, nitems, lds, s);
-        case 4: return launch_nch<T, 4, SAVE>(a, maxW, nitems, lds, s);
-        case 6: return launch_nch<T, 6, SAVE>(a, maxW, nitems, lds, s);
-        case 8: return launch_nch<T, 8, SAVE>(a, maxW, nitems, lds, s);
-        case 12: return launch_nch<T, 12, SAVE>(a, maxW, nitems, lds, s);
-        case 16: return launch_nch<T, 16, SAVE>(a, maxW, nitems, lds, s);
+        case 1: return launch_nch<T, 1, SAVE>(a, rows, grid, lds, s);
+        case 2: return launch_nch<T, 2, SAVE>(a, rows, grid, lds, s);
+        case 3: return launch_nch<T, 3, SAVE>(a, rows, grid, lds, s);
+        case 4: return launch_nch<T, 4, SAVE>(a, rows, grid, lds, s);
+        case 6: return launch_nch<T, 6, SAVE>(a, rows, grid, lds, s);
+        case 8: return launch_nch<T, 8, SAVE>(a, rows, grid, lds, s);
+        case 12: return launch_nch<T, 12, SAVE>(a, rows, grid, lds, s);
+        case 16: return launch_nch<T, 16, SAVE>(a, rows, grid, lds, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, int maxW, int nitems,
+// Clears n counters with a kernel (a memset node misbehaves under graph replay).
+__global__ void k_zero_i32(int32_t* p, int n) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+size_t fwd_lds_bytes(const DtwFwdArgs& a, bool rows, bool f64) {
+    return rows ? rows_lds_bytes(a.n, a.W, a.D, f64) : diag_lds_bytes(a.m, a.n, a.W, a.D, a.P);
+}
+
+// a.m, a.n, a.W, a.D: the largest of the launch (they size the LDS); with
+// a.counter set, `grid` persistent waves share the a.nitems items.
+hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, bool rows, int nitems, int grid,
                           hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    size_t lds;
-    if (maxW <= kDiagMaxW) {
-        lds = diag_lds_bytes(a.m, a.n, a.W, a.D, a.P);
-    } else {
-        lds = rows_lds_bytes(a.n, a.W, a.D, f64);
-    }
-    if (f64) return save ? launch_t<double, true>(a, maxW, nitems, lds, s)
-                         : launch_t<double, false>(a, maxW, nitems, lds, s);
-    return save ? launch_t<float, true>(a, maxW, nitems, lds, s)
-                : launch_t<float, false>(a, maxW, nitems, lds, s);
+    DtwFwdArgs b = a;
+    b.nitems = nitems;
+    const int g = b.counter ? grid : nitems;
+    const size_t lds = fwd_lds_bytes(b, rows, f64);
+    if (f64) return save ? launch_t<double, true>(b, rows, g, lds, s) : launch_t<double, false>(b, rows, g, lds, s);
+    return save ? launch_t<float, true>(b, rows, g, lds, s) : launch_t<float, false>(b, rows, g, lds, s);
 }
 
 }  // namespace tcdtw

@@ -18,6 +18,8 @@ struct PairDesc {
     int64_t saved_off;    // u32-word offset of the pair's argmin codes
     int32_t m, n, W;      // lengths and W_eff
     int32_t out;          // output slot
+    int32_t D;            // dimensions of both series
+    int32_t rows;         // 1: row-systolic mapping (code layout follows the mapping)
 };
 
 // Arguments of the forward DTW kernels.
@@ -35,6 +37,8 @@ struct DtwFwdArgs {
     double* dist64;          // optional
     uint32_t* codes;         // optional argmin codes
     int64_t codes_stride;    // uniform: u32 words per pair
+    int32_t* counter;        // non-null: persistent waves take items 0..nitems-1 from it
+    int32_t nitems;
 };
 
 // Arguments of the backward kernel.
@@ -53,13 +57,16 @@ struct DtwBwdArgs {
     float* grad_y;
     int32_t runs_ints;       // LDS ints reserved for the row/column runs (>= 2*(m+n) of every pair)
     int64_t stage_cap;       // u32 words of LDS available for staging a pair's codes
+    int32_t* counter;        // non-null: persistent waves take items 0..nitems-1 from it
+    int32_t nitems;
+    int32_t urows;           // uniform: the pairs ran on the row mapping
 };
 
 // Size of the argmin-code record of one pair (u32 words).  Diagonal
 // mapping: 4 bits per lane per round, 8 rounds per word, (W+1) lanes.
 // Row mapping: 2 bits per lane per step, 16 steps per word, per 64-row block.
-__host__ __device__ inline int64_t codes_words(int m, int n, int W) {
-    if (W <= kDiagMaxW) {
+__host__ __device__ inline int64_t codes_words(int m, int n, int W, bool rows) {
+    if (!rows) {
         const int R = (m + n) / 2;
         return (int64_t)((R + 7) / 8) * (W + 1);
     }
@@ -69,14 +76,20 @@ __host__ __device__ inline int64_t codes_words(int m, int n, int W) {
     const int nwb = (tmax + 15) / 16;
     return (int64_t)nb * nwb * kWave;
 }
+__host__ __device__ inline int64_t codes_words(int m, int n, int W) {
+    return codes_words(m, n, W, W > kDiagMaxW);
+}
 // LDS bytes of the forward kernels.
 size_t diag_lds_bytes(int m, int n, int W, int D, int P);
 size_t rows_lds_bytes(int n, int W, int D, bool f64);
 
-hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, int maxW, int nitems,
+hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, bool rows, int nitems, int grid,
                           hipStream_t s);
-hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int maxW, int nitems,
-                          hipStream_t s);
+size_t fwd_lds_bytes(const DtwFwdArgs& a, bool rows, bool f64);
+hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int nitems,
+                          int grid, hipStream_t s);
+size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words);
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
 
 // ------------------------------------------------------------- index build
 struct IndexBuildArgs {

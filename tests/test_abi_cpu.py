@@ -33,11 +33,11 @@ def test_library_exports_every_declared_function():
     lib = L.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.tc_dtw_abi_version() == 1
+    assert lib.tc_dtw_abi_version() == 2
 
 
 def _batch(count=2, dim=3, ulen=8, data=0x1000):
-    return L.Batch(data, None, None, count, dim, ulen)
+    return L.Batch(data, None, None, count, dim, ulen, None)
 
 
 def test_invalid_arguments_rejected_before_any_device_call():
@@ -46,7 +46,7 @@ def test_invalid_arguments_rejected_before_any_device_call():
     x, y = _batch(), _batch()
     d = C.c_void_p(0x2000)
     cases = [
-        (L.Batch(0, None, None, 2, 3, 8), y, w, d, L.ERR_INVALID),      # null data
+        (L.Batch(0, None, None, 2, 3, 8, None), y, w, d, L.ERR_INVALID),  # null data
         (_batch(count=0), y, w, d, L.ERR_INVALID),                       # empty set
         (_batch(count=3), y, w, d, L.ERR_INVALID),                       # count mismatch
         (_batch(dim=4), y, w, d, L.ERR_INVALID),                         # dim mismatch
@@ -69,8 +69,8 @@ def test_invalid_arguments_rejected_before_any_device_call():
 def test_ragged_batches_need_a_workspace():
     lib = L.lib()
     lens = (C.c_int32 * 3)(5, 9, 7)
-    x = L.Batch(0x1000, None, lens, 3, 2, 0)
-    y = L.Batch(0x1000, None, lens, 3, 2, 0)
+    x = L.Batch(0x1000, None, lens, 3, 2, 0, None)
+    y = L.Batch(0x1000, None, lens, 3, 2, 0, None)
     w = L.Window(0, 1, 10)
     need = lib.tc_dtw_banded_workspace_bytes(C.byref(x), C.byref(y), w, 0)
     assert need > 0
@@ -86,3 +86,46 @@ def test_status_strings():
     lib = L.lib()
     for s in range(5):
         assert lib.tc_dtw_status_string(s)
+
+
+def test_mixed_dims_and_plans_validated_on_the_host():
+    lib = L.lib()
+    lens = (C.c_int32 * 3)(5, 9, 7)
+    dx = (C.c_int32 * 3)(2, 8, 3)
+    dy_bad = (C.c_int32 * 3)(2, 8, 4)
+    dz = (C.c_int32 * 3)(2, 0, 3)
+    x = L.Batch(0x1000, None, lens, 3, 0, 0, dx)
+    y = L.Batch(0x1000, None, lens, 3, 0, 0, dx)
+    w = L.Window(0, 1, 10)
+    assert lib.tc_dtw_banded_workspace_bytes(C.byref(x), C.byref(y), w, 0) > 0
+    assert lib.tc_dtw_saved_bytes(C.byref(x), C.byref(y), w) > 0
+    ybad = L.Batch(0x1000, None, lens, 3, 0, 0, dy_bad)
+    st = lib.tc_dtw_banded(C.byref(x), C.byref(ybad), w, 0, C.c_void_p(0x2000), None, None, 0, None)
+    assert st == L.ERR_INVALID and b"same dim" in lib.tc_dtw_last_error()
+    z = L.Batch(0x1000, None, lens, 3, 0, 0, dz)
+    assert lib.tc_dtw_banded(C.byref(z), C.byref(z), w, 0, C.c_void_p(0x2000), None, None, 0, None) == L.ERR_INVALID
+    # plans: size query, tuning validation, null plan / buffer
+    t = L.Tuning(63, 0)
+    assert lib.tc_dtw_pairs_plan_bytes(C.byref(x), C.byref(y), w, C.byref(t)) > 0
+    assert lib.tc_dtw_pairs_plan_bytes(C.byref(x), C.byref(y), w, None) > 0
+    for bad in (L.Tuning(64, 0), L.Tuning(-2, 0), L.Tuning(63, 33), L.Tuning(63, -1)):
+        assert lib.tc_dtw_pairs_plan_bytes(C.byref(x), C.byref(y), w, C.byref(bad)) == 0
+        st = lib.tc_dtw_pairs_plan_build(C.byref(x), C.byref(y), w, C.byref(bad), C.c_void_p(0x3000), 1 << 20,
+                                         C.byref(L.PairsPlan()), None)
+        assert st == L.ERR_INVALID
+    st = lib.tc_dtw_pairs_plan_build(C.byref(x), C.byref(y), w, None, C.c_void_p(0x3000), 1 << 20, None, None)
+    assert st == L.ERR_INVALID
+    st = lib.tc_dtw_banded_run(None, C.c_void_p(0x1000), C.c_void_p(0x1000), 0, C.c_void_p(0x2000), None, None)
+    assert st == L.ERR_INVALID
+    st = lib.tc_dtw_backward_run(None, None, None, None, None, None, None, None)
+    assert st == L.ERR_INVALID
+
+
+def test_search_calls_need_one_dim():
+    lib = L.lib()
+    lens = (C.c_int32 * 2)(5, 9)
+    dx = (C.c_int32 * 2)(2, 3)
+    refs = L.Batch(0x1000, None, lens, 2, 0, 0, dx)
+    assert lib.tc_dtw_index_bytes(C.byref(refs)) == 0
+    st = lib.tc_dtw_build_index(C.byref(refs), C.c_void_p(0x2000), 1 << 20, C.byref(L.Index()), None)
+    assert st == L.ERR_UNSUPPORTED
