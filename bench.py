@@ -47,8 +47,108 @@ def parse():
     ap.add_argument("--frac", default=None, help="window fraction num/den, e.g. 1/10")
     ap.add_argument("--cpu-queries", type=int, default=24, help="queries in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time the plain GPU search")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the plain GPU search, the full cascade, batched uneven pairs, "
+                         "forward+backward pairs and long-series 1-NN")
     return ap.parse_args()
+
+
+def _events_ms(fn, reps):
+    """Average ms of fn() over reps runs, timed with events on torch's current
+    stream (the stream the library enqueues on)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def band_cells(m, n, W):
+    return sum(max(0, min(n - 1, i + W) - max(0, i - W) + 1) for i in range(m))
+
+
+def w_eff(m, n, num, den):
+    W = max(m, n) * num // den
+    return min(max(W, abs(m - n)), max(m, n) - 1)
+
+
+def extra_batched_pairs(dev, reps=5):
+    """4096 pairs, lengths uniform in [64, 2048] (independent), d in {2,4,8,16,32},
+    window 10%: autotuned plan, replayed from a HIP graph."""
+    import torch
+    from paper_2101_07731_amd import pairs, synth
+    xs, ys = synth.ragged_pairs()
+    X = [torch.from_numpy(a).to(dev) for a in xs]
+    Y = [torch.from_numpy(a).to(dev) for a in ys]
+    cells = sum(band_cells(a.shape[0], b.shape[0], w_eff(a.shape[0], b.shape[0], 1, 10)) for a, b in zip(xs, ys))
+    t0 = time.perf_counter()
+    best, times = pairs.autotune(X, Y, frac=(1, 10), reps=2)
+    tune_s = time.perf_counter() - t0
+    plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=best[0], waves_per_cu=best[1])
+    gf = pairs.GraphedForward(plan)
+    ms_graph = _events_ms(gf.replay, reps)
+    default = pairs.Plan(X, Y, frac=(1, 10))
+    dist = torch.empty(default.count, dtype=torch.float32, device=dev)
+    ms_default = _events_ms(lambda: default.forward(dist=dist), reps)
+    ms_direct = _events_ms(lambda: pairs.banded(X, Y, frac=(1, 10)), 2)
+    return {"workload": "4096 pairs, lengths U[64,2048] independent, d in {2,4,8,16,32}, window 10%",
+            "pairs_per_s": round(len(xs) / (ms_graph * 1e-3), 1),
+            "gcups": round(cells / (ms_graph * 1e-3) / 1e9, 2),
+            "ms_graph_replay": round(ms_graph, 3),
+            "ms_default_plan": round(ms_default, 3),
+            "ms_direct_call_incl_planning": round(ms_direct, 3),
+            "autotuned": {"diag_max_w": best[0], "waves_per_cu": best[1], "tune_s": round(tune_s, 2),
+                          "choices_ms": {"%d/%d" % k: round(v, 3) for k, v in sorted(times.items())}},
+            "classes": default.classes()}
+
+
+def extra_fwd_bwd(dev, reps=5):
+    """DTW as a loss: 256 pairs of length 512, d = 12, window 10%: forward
+    recording the argmin codes, then the adjoint backward."""
+    import torch
+    from paper_2101_07731_amd import pairs, synth
+    x, y = synth.loss_pairs()
+    X, Y = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    B, T = x.shape[0], x.shape[1]
+    g = torch.ones(B, device=dev)
+
+    def step():
+        _, saved = pairs.banded(X, Y, frac=(1, 10), save=True)
+        pairs.backward(X, Y, saved, g, frac=(1, 10))
+
+    ms_fb = _events_ms(step, reps)
+    ms_f = _events_ms(lambda: pairs.banded(X, Y, frac=(1, 10)), reps)
+    return {"workload": "256 pairs, length 512, d=12, window 10% (W=51)",
+            "fwd_bwd_pairs_per_s": round(B / (ms_fb * 1e-3), 1),
+            "fwd_pairs_per_s": round(B / (ms_f * 1e-3), 1),
+            "ms_fwd_bwd": round(ms_fb, 3), "ms_fwd": round(ms_f, 3),
+            "fwd_gcups": round(B * band_cells(T, T, T // 10) / (ms_f * 1e-3) / 1e9, 2)}
+
+
+def extra_long_knn(dev, reps=3):
+    """200 queries x 2000 references, length 1024, d = 16, window 10% (row mapping)."""
+    import torch
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.long_knn()
+    Qd, Cd = torch.from_numpy(Q).to(dev), torch.from_numpy(Cs).to(dev)
+    ix = search.Index(Cd)
+    out = {"workload": "200 x 2000, length 1024, d=16, window 10% (W=102)"}
+    for bounds in ("mv", "plain"):
+        st = {}
+
+        def run():
+            st.update(search.knn(ix, Qd, frac=(1, 10), bounds=bounds, stats=True)[2])
+
+        ms = _events_ms(run, reps)
+        out[bounds] = {"queries_per_s": round(Q.shape[0] / (ms * 1e-3), 1), "ms": round(ms, 3),
+                       "pct_dtw_pruned": round(100 * (1 - st["dtw_started"] / st["pairs"]), 3),
+                       "dtw_gcups": round(st["cells"] / (st["stage_ms"][5] * 1e-3) / 1e9, 2)}
+    return out
 
 
 def cpu_threads():
@@ -151,6 +251,21 @@ def main():
     }
 
     if args.extras:
+        kwf = dict(frac=frac, bounds="mv+pc+ti")
+        search.knn(ix, Qd, **kwf)
+        stf = {}
+
+        def full():
+            stf.update(search.knn(ix, Qd, stats=True, **kwf)[2])
+
+        msf = _events_ms(full, 3)
+        out["full_cascade"] = {"bounds": "mv+pc+ti", "queries_per_s": round(nq / (msf * 1e-3), 2),
+                               "pruned_pc": stf["pruned_pc"], "pruned_ti": stf["pruned_ti"],
+                               "pct_dtw_pruned": round(100.0 * (1 - stf["dtw_started"] / stf["pairs"]), 3),
+                               "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3)}
+        out["batched_pairs"] = extra_batched_pairs(dev)
+        out["dtw_loss"] = extra_fwd_bwd(dev)
+        out["long_knn"] = extra_long_knn(dev)
         kwp = dict(frac=frac, bounds="plain")
         search.knn(ix, Qd, **kwp)
         torch.cuda.synchronize()
