@@ -89,7 +89,7 @@ def extra_batched_pairs(dev, reps=5):
     t0 = time.perf_counter()
     best, times = pairs.autotune(X, Y, frac=(1, 10), reps=2)
     tune_s = time.perf_counter() - t0
-    plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=best[0], waves_per_cu=best[1])
+    plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=best[0], waves_per_cu=best[1], waves_per_pair=best[2])
     gf = pairs.GraphedForward(plan)
     ms_graph = _events_ms(gf.replay, reps)
     default = pairs.Plan(X, Y, frac=(1, 10))
@@ -102,8 +102,9 @@ def extra_batched_pairs(dev, reps=5):
             "ms_graph_replay": round(ms_graph, 3),
             "ms_default_plan": round(ms_default, 3),
             "ms_direct_call_incl_planning": round(ms_direct, 3),
-            "autotuned": {"diag_max_w": best[0], "waves_per_cu": best[1], "tune_s": round(tune_s, 2),
-                          "choices_ms": {"%d/%d" % k: round(v, 3) for k, v in sorted(times.items())}},
+            "autotuned": {"diag_max_w": best[0], "waves_per_cu": best[1], "waves_per_pair": best[2],
+                          "tune_s": round(tune_s, 2),
+                          "choices_ms": {"%d/%d/%d" % k: round(v, 3) for k, v in sorted(times.items())}},
             "classes": default.classes()}
 
 

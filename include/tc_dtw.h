@@ -154,6 +154,11 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
  *                 row mapping; -1..63, default 63.
  *   waves_per_cu  resident waves per CU of the persistent launches, 1..32;
  *                 0 means 16.  Fewer when a class's LDS does not allow them.
+ *   waves_per_pair  largest number of waves that share one pair on the row
+ *                 mapping, 1, 2, 4 or 8 (0 means 8): a pair of m rows runs
+ *                 its 64-row blocks on K = 1 (m <= 128), 2 (<= 512),
+ *                 4 (<= 1024) or 8 waves, capped here and by LDS; the waves
+ *                 pipeline the blocks through a shared row buffer.
  * tc_dtw_pairs_plan_bytes: size of the DEVICE plan buffer (0 on invalid
  *   arguments).  x->data and y->data are not read by the plan calls.
  * tc_dtw_pairs_plan_build: fills `plan` (HOST) and copies the pair
@@ -170,6 +175,7 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
 typedef struct {
     int32_t diag_max_w;
     int32_t waves_per_cu;
+    int32_t waves_per_pair;
 } tc_dtw_tuning;
 
 #define TC_DTW_PLAN_MAX_CLASSES 32
@@ -180,7 +186,7 @@ typedef struct {
     int32_t dim;         /* largest D of the class */
     int32_t nitems;      /* pairs in the class */
     int32_t maxm, maxn, maxw;
-    int32_t reserved;
+    int32_t waves_per_pair; /* row mapping: waves sharing each pair (1: one wave per pair) */
     int64_t max_words;   /* largest argmin-code record of the class (u32 words) */
     int64_t desc_off;    /* byte offset of the class's descriptors in the plan buffer */
 } tc_dtw_plan_class;

@@ -30,7 +30,7 @@ class Batch(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("diag_max_w", C.c_int32), ("waves_per_cu", C.c_int32)]
+    _fields_ = [("diag_max_w", C.c_int32), ("waves_per_cu", C.c_int32), ("waves_per_pair", C.c_int32)]
 
 
 PLAN_MAX_CLASSES = 32
@@ -38,7 +38,7 @@ PLAN_MAX_CLASSES = 32
 
 class PlanClass(C.Structure):
     _fields_ = [("rows", C.c_int32), ("wodd", C.c_int32), ("dim", C.c_int32), ("nitems", C.c_int32),
-                ("maxm", C.c_int32), ("maxn", C.c_int32), ("maxw", C.c_int32), ("reserved", C.c_int32),
+                ("maxm", C.c_int32), ("maxn", C.c_int32), ("maxw", C.c_int32), ("waves_per_pair", C.c_int32),
                 ("max_words", C.c_int64), ("desc_off", C.c_int64)]
 
 

@@ -25,6 +25,7 @@ constexpr int kDefaultWavesPerCu = 16;
 struct PairClass {
     bool rows = false, wodd = false;
     int nch = 1;
+    int K = 1;                // row mapping: waves per pair
     int maxm = 0, maxn = 0, maxW = 0;
     int64_t max_words = 0;
     double work = 0;
@@ -36,6 +37,7 @@ struct PairsPlan {
     bool urows = false;       // uniform: row mapping
     int m = 0, n = 0, W = 0, D = 0, npairs = 0;
     int waves_per_cu = kDefaultWavesPerCu;
+    int waves_per_pair = 8;
     std::vector<PairClass> classes;
     int64_t saved_words = 0;
     int64_t codes_stride = 0;   // uniform
@@ -61,6 +63,16 @@ static bool use_rows(int m, int n, int W, int D, int diag_max) {
     return W > diag_max || diag_lds_bytes(m, n, W, D, 1) > kDiagLdsBudget;
 }
 
+// Waves sharing a pair on the row mapping: by its number of 64-row blocks,
+// capped by the tuning and by LDS (sized for a float64 row buffer).
+static int waves_for(int m, int n, int D, int cap) {
+    const int nb = (m + kRowBlock - 1) / kRowBlock;
+    int K = nb <= 2 ? 1 : nb <= 8 ? 2 : nb <= 16 ? 4 : 8;
+    K = std::min(K, cap);
+    while (K > 1 && pipe_lds_bytes(n, D, K, true) > 163840) K /= 2;
+    return std::max(K, 1);
+}
+
 // force_plan: plan even a uniform batch (the reusable plans always do).
 static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, tc_dtw_window w,
                                const tc_dtw_tuning* tune, bool force_plan, PairsPlan& P, HostSet& X,
@@ -80,8 +92,12 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
             return fail(TC_DTW_ERR_INVALID, "tuning.diag_max_w must lie in -1..63");
         if (tune->waves_per_cu < 0 || tune->waves_per_cu > 32)
             return fail(TC_DTW_ERR_INVALID, "tuning.waves_per_cu must lie in 0..32");
+        const int wp = tune->waves_per_pair;
+        if (wp != 0 && wp != 1 && wp != 2 && wp != 4 && wp != 8)
+            return fail(TC_DTW_ERR_INVALID, "tuning.waves_per_pair must be 0, 1, 2, 4 or 8");
         diag_max = tune->diag_max_w;
         if (tune->waves_per_cu > 0) P.waves_per_cu = tune->waves_per_cu;
+        if (wp > 0) P.waves_per_pair = wp;
     }
     P.D = X.dim;
     P.npairs = X.count;
@@ -95,9 +111,10 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
         P.saved_words = P.codes_stride * P.npairs;
         return TC_DTW_OK;
     }
-    // class key: mapping kind (diag even, diag odd, rows) x dimension class
-    int index[3][17];
-    for (auto& r : index) std::fill(r, r + 17, -1);
+    // class key: mapping kind (diag even, diag odd, rows) x dimension class x waves per pair
+    int index[3][17][9];
+    for (auto& r : index)
+        for (auto& q : r) std::fill(q, q + 9, -1);
     int64_t soff = 0;
     for (int b = 0; b < P.npairs; ++b) {
         PairDesc d;
@@ -115,7 +132,8 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
         soff += words;
         const int kind = d.rows ? 2 : (d.W & 1);
         const int nch = nch_pad(d.D);
-        int& ci = index[kind][nch];
+        const int K = d.rows ? waves_for(d.m, d.n, 4 * nch, P.waves_per_pair) : 1;
+        int& ci = index[kind][nch][K];
         if (ci < 0) {
             if ((int)P.classes.size() == TC_DTW_PLAN_MAX_CLASSES)
                 return fail(TC_DTW_ERR_UNSUPPORTED, "too many pair classes");
@@ -124,6 +142,7 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
             P.classes.back().rows = d.rows != 0;
             P.classes.back().wodd = kind == 1;
             P.classes.back().nch = nch;
+            P.classes.back().K = K;
         }
         PairClass& c = P.classes[ci];
         c.maxm = std::max(c.maxm, d.m);
@@ -184,6 +203,7 @@ static void to_public(const PairsPlan& P, const std::vector<size_t>& off, void* 
         o.maxm = c.maxm;
         o.maxn = c.maxn;
         o.maxw = c.maxW;
+        o.waves_per_pair = c.K;
         o.max_words = c.max_words;
         o.desc_off = (int64_t)off[k];
     }
@@ -237,10 +257,19 @@ static tc_dtw_status run_fwd(const tc_dtw_pairs_plan* p, const float* x, const f
         a.dist = dist;
         a.codes = static_cast<uint32_t*>(saved);
         a.counter = counters + k;
-        const size_t lds = fwd_lds_bytes(a, c.rows != 0, f64);
-        if (lds > lim) return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
-        e = launch_dtw_fwd(a, f64, saved != nullptr, c.rows != 0, c.nitems,
-                           persistent_grid(lds, p->waves_per_cu, c.nitems), s);
+        const int K = c.rows ? c.waves_per_pair : 1;
+        if (K > 1) {
+            const size_t lds = pipe_lds_bytes(c.maxn, c.dim, K, f64);
+            if (lds > lim) return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
+            const int per_cu = std::max(1, std::min(p->waves_per_cu / K, (int)(lim / lds)));
+            const int grid = std::max(1, std::min(c.nitems, 256 * per_cu));
+            e = launch_dtw_rows_pipe(a, f64, saved != nullptr, K, c.nitems, grid, s);
+        } else {
+            const size_t lds = fwd_lds_bytes(a, c.rows != 0, f64);
+            if (lds > lim) return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
+            e = launch_dtw_fwd(a, f64, saved != nullptr, c.rows != 0, c.nitems,
+                               persistent_grid(lds, p->waves_per_cu, c.nitems), s);
+        }
         if (e != hipSuccess) return hip_fail(e, "dtw forward launch");
     }
     return ok();

@@ -369,6 +369,147 @@ __device__ __forceinline__ T rows_core(int sc, const float* xs, const float* ys,
     return result;
 }
 
+// Row mapping with K waves per pair (one workgroup of 64 K threads): wave
+// v runs row blocks v, v + K, v + 2K, ... of the pair, each exactly as in
+// rows_core, with its own candidate ring.  All blocks share one row buffer:
+// block b reads row i0 - 1 at column c (lane 0, step c - jlo) and writes
+// row i0 + 63 there 63 steps later, and block b + 1 may read column c only
+// after block b has written it.  Each wave publishes its progress
+// (block * kProgStride + steps done) in LDS after every 64 steps; before a
+// chunk of 64 steps a block waits until its predecessor has done the steps
+// that write the columns the chunk reads.  A block waits only on the block
+// before it, so the chain always ends at block 0 and cannot deadlock; the
+// wait is also bounded (kSpinLimit sleeps), after which `late` is set, the
+// wave waits no more, and the caller reports the pair as NaN instead of
+// hanging.
+constexpr int kProgStride = 1 << 20;
+constexpr int kSpinLimit = 1 << 17;   // x s_sleep 2 (128 clocks): ~7 ms, several times the longest legitimate wait
+
+template <typename T, int NCH, bool SAVE>
+__device__ __forceinline__ T rows_core_pipe(int ring, T* rowbuf, int* prog, int K, int wv,
+                                            const float* xs, const float* ys, int m, int n, int W,
+                                            int D, int lane, uint32_t* codes, bool& late) {
+    const T INF = inf_v<T>();
+    const float NINF = -__builtin_inff();
+    constexpr int RS = kRowRing, mask = kRowRing - 1;
+    auto put = [&](int j, const float4 (&v)[NCH]) {
+        const int slot = ring + ((j + kRowBlock) & mask);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) lds4[slot + k * RS] = v[k];
+    };
+    const int nb = (m + kRowBlock - 1) / kRowBlock;
+    const int band = min(n, 2 * W + kRowBlock);
+    const int nwb = (band + kRowBlock - 1 + 15) / 16;
+    const int pw = wv == 0 ? K - 1 : wv - 1;   // wave of the previous block
+    T result = INF;
+    for (int b = wv; b < nb; b += K) {
+        const int i0 = b * kRowBlock;
+        const int i = i0 + lane;
+        float4 qv[NCH];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = 4 * k + e;
+                v[e] = (i < m) ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
+            }
+            qv[k] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        const int jlo = max(0, i0 - W);
+        const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
+        // the previous block: its first column and its step count
+        const int pjlo = max(0, i0 - kRowBlock - W);
+        const int pT = b > 0 ? min(n - 1, i0 - 1 + W) - pjlo + kRowBlock : 0;
+        {
+            float4 v0[NCH], v1[NCH];
+            load_point<NCH>(ys, n, D, jlo - (kRowBlock - 1) + lane, NINF, v0);
+            load_point<NCH>(ys, n, D, jlo + 1 + lane, NINF, v1);
+            put(jlo - (kRowBlock - 1) + lane, v0);
+            put(jlo + 1 + lane, v1);
+        }
+        const int T_b = jhi - jlo + kRowBlock;
+        const int k0 = jlo - i0 + W - 2 * lane;
+        const int cs0 = jlo - lane + kRowBlock;
+        const int rb = jlo + kRowPad;
+        const int wb = jlo - (kRowBlock - 1) + kRowPad;
+        T cur = INF;
+        T prevup = INF;
+        const bool last = (b == nb - 1);
+        const int tend = (n - 1) - jlo + (m - 1 - i0);
+        uint32_t cw = 0;
+        uint32_t* cp = SAVE ? codes + (int64_t)b * nwb * kWave + lane : nullptr;
+        for (int t0 = 0; t0 < T_b; t0 += kRowBlock) {
+            if (b > 0 && K > 1 && !late) {
+                // columns up to jlo + t0 + 63 are written by the previous block's step
+                // (column - pjlo + 63); it must have completed that many steps
+                const int need = min(pT, jlo - pjlo + t0 + 2 * kRowBlock - 1);
+                const int target = (b - 1) * kProgStride + need;
+                int spins = 0;
+                for (;;) {
+                    const int p = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(prog + pw, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+                    if (p >= target) break;
+                    if (++spins > kSpinLimit) {
+                        late = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            if (t0 == 0) prevup = (lane == 0) ? rowbuf[jlo - 1 + kRowPad] : INF;
+            const bool refill = t0 + kRowBlock < T_b;
+            float4 nx[NCH];
+            if (refill) load_point<NCH>(ys, n, D, jlo + t0 + kRowBlock + 1 + lane, NINF, nx);
+            const int t1 = min(T_b, t0 + kRowBlock);
+            for (int t = t0; t < t1; ++t) {
+                const int cl = ring + ((cs0 + t) & mask);
+                float4 cv[NCH];
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) cv[k] = lds4[cl + k * RS];
+                const T up = wave_shr1(rowbuf[rb + t], cur);
+                const T diag = prevup;
+                prevup = up;
+                const T left = cur;
+                const T cost = point_cost<NCH>(qv, cv, T(0));
+                T best;
+                if (SAVE) {
+                    uint32_t code = 0;
+                    best = diag;
+                    if (up < best) { best = up; code = 1; }
+                    if (left < best) { best = left; code = 2; }
+                    cw |= code << ((t & 15) * 2);
+                    if ((t & 15) == 15 || t == T_b - 1) {
+                        cp[(int64_t)(t >> 4) * kWave] = cw;
+                        cw = 0;
+                    }
+                } else {
+                    best = vmin3(diag, up, left);
+                }
+                T v = add_cost(cost, best);
+                const unsigned kb = (unsigned)(t + k0);
+                v = (kb <= (unsigned)(2 * W)) ? v : INF;
+                cur = v;
+                if (lane == kRowBlock - 1) rowbuf[wb + t] = v;
+                if (last && t == tend && lane == m - 1 - i0) result = v;
+            }
+            if (refill) put(jlo + t0 + kRowBlock + 1 + lane, nx);
+            // this block has completed t1 steps, its row-buffer writes included
+            if (K > 1 && lane == 0)
+                __hip_atomic_store(prog + wv, b * kProgStride + t1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    return result;
+}
+
+// LDS bytes of the K-wave row kernel: K rings, the row buffer, K progress
+// counters, the work item and a status flag.
+__host__ __device__ inline size_t rows_pipe_lds(int n, int nch, int K, int tbytes) {
+    const size_t rings = (size_t)K * kRowRing * nch * 16;
+    const size_t rowbuf = ((size_t)(n + 2 * kRowPad) * tbytes + 15) & ~(size_t)15;
+    return rings + rowbuf + (size_t)(K + 2) * 4;
+}
+
 // LDS bytes of rows_core for candidate length n (tbytes = sizeof(T)).
 __host__ __device__ inline size_t rows_core_lds(int n, int nch, int tbytes) {
     return (size_t)kRowRing * nch * 16 + (size_t)(n + 2 * kRowPad) * tbytes;

@@ -176,6 +176,87 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Row mapping with K waves per pair (rows_core_pipe): persistent workgroups
+// of 64 K threads take pairs from a device counter.  LDS: K candidate rings,
+// the row buffer of the launch's longest candidate, K progress counters, the
+// current item and a flag raised when a wait ran out (the pair's distance is
+// then NaN).
+// ---------------------------------------------------------------------------
+template <typename T, int NCH, bool SAVE>
+__global__ __launch_bounds__(512) void dtw_rows_pipe_kernel(DtwFwdArgs a) {
+    const int K = blockDim.x / kWave;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const T INF = inf_v<T>();
+    T* rowbuf = reinterpret_cast<T*>(lds4 + K * kRowRing * NCH);
+    const size_t rb_bytes = ((size_t)(a.n + 2 * kRowPad) * sizeof(T) + 15) & ~(size_t)15;
+    int* prog = reinterpret_cast<int*>(reinterpret_cast<char*>(rowbuf) + rb_bytes);
+    int* sitem = prog + K;
+    int* sflag = sitem + 1;
+    for (;;) {
+        if (threadIdx.x == 0) *sitem = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(*sitem);
+        if (item >= a.nitems) break;
+        const PairDesc d = a.desc[item];
+        const int m = d.m, n = d.n, W = d.W, D = d.D;
+        const int LB = n + 2 * kRowPad;
+        for (int pos = threadIdx.x; pos < LB; pos += blockDim.x) rowbuf[pos] = (pos == kRowPad - 1) ? T(0) : INF;
+        if (threadIdx.x < K) prog[threadIdx.x] = -1;
+        if (threadIdx.x == 0) *sflag = 0;
+        __syncthreads();
+        bool late = false;
+        const T v = rows_core_pipe<T, NCH, SAVE>(wv * kRowRing * NCH, rowbuf, prog, K, wv, a.x + d.xoff,
+                                                 a.y + d.yoff, m, n, W, D, lane,
+                                                 SAVE ? a.codes + d.saved_off : nullptr, late);
+        if (late) *sflag = 1;
+        __syncthreads();
+        if (wv == ((m - 1) / kRowBlock) % K && lane == (m - 1) % kRowBlock) {
+            const bool bad = *sflag != 0;
+            a.dist[d.out] = bad ? __builtin_nanf("") : (float)v;
+            if (a.dist64) a.dist64[d.out] = bad ? __builtin_nan("") : (double)v;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NCH, bool SAVE>
+static hipError_t launch_pipe_nch(const DtwFwdArgs& a, int K, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((dtw_rows_pipe_kernel<T, NCH, SAVE>), dim3(grid), dim3(kWave * K), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool SAVE>
+static hipError_t launch_pipe_t(const DtwFwdArgs& a, int K, int grid, size_t lds, hipStream_t s) {
+    switch (nch_pad(a.D)) {
+        case 1: return launch_pipe_nch<T, 1, SAVE>(a, K, grid, lds, s);
+        case 2: return launch_pipe_nch<T, 2, SAVE>(a, K, grid, lds, s);
+        case 3: return launch_pipe_nch<T, 3, SAVE>(a, K, grid, lds, s);
+        case 4: return launch_pipe_nch<T, 4, SAVE>(a, K, grid, lds, s);
+        case 6: return launch_pipe_nch<T, 6, SAVE>(a, K, grid, lds, s);
+        case 8: return launch_pipe_nch<T, 8, SAVE>(a, K, grid, lds, s);
+        case 12: return launch_pipe_nch<T, 12, SAVE>(a, K, grid, lds, s);
+        case 16: return launch_pipe_nch<T, 16, SAVE>(a, K, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t pipe_lds_bytes(int maxn, int D, int K, bool f64) {
+    return rows_pipe_lds(maxn, nch_pad(D), K, f64 ? 8 : 4);
+}
+
+// a.counter and a.desc set, a.n / a.D the launch's largest; `grid` workgroups of K waves.
+hipError_t launch_dtw_rows_pipe(const DtwFwdArgs& a, bool f64, bool save, int K, int nitems, int grid,
+                                hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (K < 2 || K > 8 || !a.counter) return hipErrorInvalidValue;
+    DtwFwdArgs b = a;
+    b.nitems = nitems;
+    const size_t lds = pipe_lds_bytes(b.n, b.D, K, f64);
+    if (f64) return save ? launch_pipe_t<double, true>(b, K, grid, lds, s) : launch_pipe_t<double, false>(b, K, grid, lds, s);
+    return save ? launch_pipe_t<float, true>(b, K, grid, lds, s) : launch_pipe_t<float, false>(b, K, grid, lds, s);
+}
+
+// ---------------------------------------------------------------------------
 // Launch: the mapping is chosen by the largest W_eff of the launch.
 // ---------------------------------------------------------------------------
 

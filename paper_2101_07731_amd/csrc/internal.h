@@ -86,6 +86,10 @@ size_t rows_lds_bytes(int n, int W, int D, bool f64);
 hipError_t launch_dtw_fwd(const DtwFwdArgs& a, bool f64, bool save, bool rows, int nitems, int grid,
                           hipStream_t s);
 size_t fwd_lds_bytes(const DtwFwdArgs& a, bool rows, bool f64);
+// Row mapping with K (2..8) waves per pair, persistent workgroups over a.nitems items.
+hipError_t launch_dtw_rows_pipe(const DtwFwdArgs& a, bool f64, bool save, int K, int nitems, int grid,
+                                hipStream_t s);
+size_t pipe_lds_bytes(int maxn, int D, int K, bool f64);
 hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int nitems,
                           int grid, hipStream_t s);
 size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words);

@@ -156,10 +156,10 @@ class Plan:
     a CUDA (HIP) graph.  Data passed to them must be laid out like x and y
     (the flat buffers of SeriesSet)."""
 
-    def __init__(self, x, y, window=None, frac=(1, 10), diag_max_w=63, waves_per_cu=0):
+    def __init__(self, x, y, window=None, frac=(1, 10), diag_max_w=63, waves_per_cu=0, waves_per_pair=0):
         self.X, self.Y = SeriesSet(x), SeriesSet(y)
         self.win = window_spec(window, frac)
-        self.tuning = L.Tuning(int(diag_max_w), int(waves_per_cu))
+        self.tuning = L.Tuning(int(diag_max_w), int(waves_per_cu), int(waves_per_pair))
         lib = L.lib()
         dev = self.X.flat.device
         nb = lib.tc_dtw_pairs_plan_bytes(C.byref(self.X.batch), C.byref(self.Y.batch), self.win,
@@ -207,8 +207,8 @@ class Plan:
         return gx, gy
 
     def classes(self):
-        """The plan's launches: (mapping, dim class, pairs, max m, max n, max W_eff)."""
-        return [("rows" if c.rows else "diag", c.dim, c.nitems, c.maxm, c.maxn, c.maxw)
+        """The plan's launches: (mapping, dim class, pairs, max m, max n, max W_eff, waves per pair)."""
+        return [("rows" if c.rows else "diag", c.dim, c.nitems, c.maxm, c.maxn, c.maxw, c.waves_per_pair)
                 for c in self.plan.cls[:self.plan.nclasses]]
 
 
@@ -239,8 +239,9 @@ class GraphedForward:
 
 _TUNED = {}
 
-DIAG_CHOICES = (-1, 15, 31, 63)
-WAVE_CHOICES = (4, 8, 16, 24)
+DIAG_CHOICES = (-1, 31, 63)
+WAVE_CHOICES = (8, 16, 24)
+PAIR_CHOICES = (1, 4, 8)
 
 
 def shape_key(x, y, window=None, frac=(1, 10)):
@@ -253,25 +254,27 @@ def shape_key(x, y, window=None, frac=(1, 10)):
     return (desc(X), desc(Y), window, frac)
 
 
-def autotune(x, y, window=None, frac=(1, 10), reps=3, diag_choices=DIAG_CHOICES, wave_choices=WAVE_CHOICES):
-    """Times the plan's forward for every (diag_max_w, waves_per_cu) choice and
-    returns ((diag_max_w, waves_per_cu), {choice: ms}); the best choice is
-    remembered per shape key (see `tuned_plan`)."""
+def autotune(x, y, window=None, frac=(1, 10), reps=3, diag_choices=DIAG_CHOICES, wave_choices=WAVE_CHOICES,
+             pair_choices=PAIR_CHOICES):
+    """Times the plan's forward for every (diag_max_w, waves_per_cu,
+    waves_per_pair) choice and returns (best choice, {choice: ms}); the best
+    choice is remembered per shape key (see `tuned_plan`)."""
     key = shape_key(x, y, window, frac)
     times = {}
     for dm in diag_choices:
         for wv in wave_choices:
-            plan = Plan(x, y, window=window, frac=frac, diag_max_w=dm, waves_per_cu=wv)
-            dist = torch.empty(plan.count, dtype=torch.float32, device=plan.device)
-            plan.forward(dist=dist)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
+            for wp in pair_choices:
+                plan = Plan(x, y, window=window, frac=frac, diag_max_w=dm, waves_per_cu=wv, waves_per_pair=wp)
+                dist = torch.empty(plan.count, dtype=torch.float32, device=plan.device)
                 plan.forward(dist=dist)
-            e1.record()
-            torch.cuda.synchronize()
-            times[(dm, wv)] = e0.elapsed_time(e1) / reps
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    plan.forward(dist=dist)
+                e1.record()
+                torch.cuda.synchronize()
+                times[(dm, wv, wp)] = e0.elapsed_time(e1) / reps
     best = min(times, key=times.get)
     _TUNED[key] = best
     return best, times
@@ -282,5 +285,5 @@ def tuned_plan(x, y, window=None, frac=(1, 10), **kw):
     key = shape_key(x, y, window, frac)
     if key not in _TUNED:
         autotune(x, y, window=window, frac=frac, **kw)
-    dm, wv = _TUNED[key]
-    return Plan(x, y, window=window, frac=frac, diag_max_w=dm, waves_per_cu=wv)
+    dm, wv, wp = _TUNED[key]
+    return Plan(x, y, window=window, frac=frac, diag_max_w=dm, waves_per_cu=wv, waves_per_pair=wp)

@@ -105,10 +105,11 @@ def test_mixed_dims_and_plans_validated_on_the_host():
     z = L.Batch(0x1000, None, lens, 3, 0, 0, dz)
     assert lib.tc_dtw_banded(C.byref(z), C.byref(z), w, 0, C.c_void_p(0x2000), None, None, 0, None) == L.ERR_INVALID
     # plans: size query, tuning validation, null plan / buffer
-    t = L.Tuning(63, 0)
+    t = L.Tuning(63, 0, 0)
     assert lib.tc_dtw_pairs_plan_bytes(C.byref(x), C.byref(y), w, C.byref(t)) > 0
     assert lib.tc_dtw_pairs_plan_bytes(C.byref(x), C.byref(y), w, None) > 0
-    for bad in (L.Tuning(64, 0), L.Tuning(-2, 0), L.Tuning(63, 33), L.Tuning(63, -1)):
+    for bad in (L.Tuning(64, 0, 0), L.Tuning(-2, 0, 0), L.Tuning(63, 33, 0), L.Tuning(63, -1, 0),
+                L.Tuning(63, 0, 3), L.Tuning(63, 0, 16)):
         assert lib.tc_dtw_pairs_plan_bytes(C.byref(x), C.byref(y), w, C.byref(bad)) == 0
         st = lib.tc_dtw_pairs_plan_build(C.byref(x), C.byref(y), w, C.byref(bad), C.c_void_p(0x3000), 1 << 20,
                                          C.byref(L.PairsPlan()), None)

@@ -65,19 +65,22 @@ def test_direct_mixed_dims(dev):
 
 @pytest.mark.parametrize("diag_max_w", [-1, 7, 31, 63])
 @pytest.mark.parametrize("waves", [0, 1, 5])
-def test_plan_every_tuning_matches(dev, diag_max_w, waves):
+@pytest.mark.parametrize("per_pair", [1, 8])
+def test_plan_every_tuning_matches(dev, diag_max_w, waves, per_pair):
     from paper_2101_07731_amd import pairs
-    xs, ys = small_mixed(12, npairs=48)
-    say("batch plan", diag_max_w, waves)
+    xs, ys = small_mixed(12, npairs=48, tmax=1200)
+    say("batch plan", diag_max_w, waves, per_pair)
     X, Y = to_dev(xs, dev), to_dev(ys, dev)
     direct = pairs.banded(X, Y, frac=(1, 10)).cpu().numpy()
-    plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=diag_max_w, waves_per_cu=waves)
+    plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=diag_max_w, waves_per_cu=waves, waves_per_pair=per_pair)
     got = plan.forward().cpu().numpy()
     np.testing.assert_array_equal(got, direct)
     got64 = plan.forward(f64=True).cpu().numpy()
     np.testing.assert_array_equal(got64, oracle_mixed(xs, ys, (1, 10)).astype(np.float32))
     if diag_max_w == -1:
         assert all(c[0] == "rows" for c in plan.classes())
+    if per_pair == 8:
+        assert any(c[6] > 1 for c in plan.classes())
 
 
 def test_plan_backward_matches_oracle_path_gradient(dev):
@@ -86,16 +89,16 @@ def test_plan_backward_matches_oracle_path_gradient(dev):
     xs, ys = [], []
     for k in range(14):
         D = int(rng.choice([1, 3, 4, 8, 12]))
-        m, n = int(rng.integers(2, 160)), int(rng.integers(2, 160))
+        m, n = int(rng.integers(2, 700)), int(rng.integers(2, 700))
         # jitter breaks ties between predecessors
         xs.append((np.cumsum(rng.standard_normal((m, D)), 0) + 1e-3 * rng.standard_normal((m, D))).astype(np.float32))
         ys.append((np.cumsum(rng.standard_normal((n, D)), 0) + 1e-3 * rng.standard_normal((n, D))).astype(np.float32))
     say("batch plan backward", len(xs))
     X, Y = to_dev(xs, dev), to_dev(ys, dev)
     g = torch.from_numpy(rng.uniform(0.5, 2.0, size=len(xs)).astype(np.float32)).to(dev)
-    for dm in (63, -1):
+    for dm, wp in ((63, 1), (-1, 8)):
         # a float64 forward takes the oracle's path, so the gradients agree to float32 rounding
-        plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=dm)
+        plan = pairs.Plan(X, Y, frac=(1, 10), diag_max_w=dm, waves_per_pair=wp)
         saved = plan.saved_buffer()
         dist = plan.forward(saved=saved, f64=True).cpu().numpy()
         gx, gy = plan.backward(saved, g)
@@ -139,8 +142,9 @@ def test_autotune_picks_a_choice(dev):
     xs, ys = small_mixed(15, npairs=64, tmax=200)
     X, Y = to_dev(xs, dev), to_dev(ys, dev)
     say("batch autotune")
-    best, times = pairs.autotune(X, Y, frac=(1, 10), reps=2, diag_choices=(-1, 63), wave_choices=(4, 16))
-    assert best in times and len(times) == 4
+    best, times = pairs.autotune(X, Y, frac=(1, 10), reps=2, diag_choices=(-1, 63), wave_choices=(4, 16),
+                                 pair_choices=(1, 4))
+    assert best in times and len(times) == 8
     plan = pairs.tuned_plan(X, Y, frac=(1, 10))
     np.testing.assert_allclose(plan.forward().cpu().numpy(), oracle_mixed(xs, ys, (1, 10)), rtol=1e-5)
 
