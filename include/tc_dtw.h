@@ -155,10 +155,12 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
  *   waves_per_cu  resident waves per CU of the persistent launches, 1..32;
  *                 0 means 16.  Fewer when a class's LDS does not allow them.
  *   waves_per_pair  largest number of waves that share one pair on the row
- *                 mapping, 1, 2, 4 or 8 (0 means 8): a pair of m rows runs
- *                 its 64-row blocks on K = 1 (m <= 128), 2 (<= 512),
- *                 4 (<= 1024) or 8 waves, capped here and by LDS; the waves
- *                 pipeline the blocks through a shared row buffer.
+ *                 mapping, 1, 2, 4 or 8 (0 means 8).  A pair gets K > 1
+ *                 waves only when one wave alone would take longer than the
+ *                 whole batch spread over 256 wave slots (K = that ratio
+ *                 rounded up to 2, 4 or 8), capped here and by LDS; the K
+ *                 waves pipeline its 64-row blocks through a shared row
+ *                 buffer.
  * tc_dtw_pairs_plan_bytes: size of the DEVICE plan buffer (0 on invalid
  *   arguments).  x->data and y->data are not read by the plan calls.
  * tc_dtw_pairs_plan_build: fills `plan` (HOST) and copies the pair
@@ -169,7 +171,12 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
  * tc_dtw_banded_run: as tc_dtw_banded on x, y (DEVICE base pointers; the
  *   planned offsets are relative to them); `saved` (DEVICE, or NULL) must
  *   hold plan->saved_bytes.  A run resets the plan's counters itself; runs
- *   of one plan must not overlap (they share the counters).
+ *   of one plan must not overlap (they share the counters).  The classes
+ *   run concurrently: the run forks from `stream` to TC_DTW_RUN_STREAMS
+ *   streams the library creates once per device (default priority) and
+ *   joins back with events, so the work is ordered after everything
+ *   already on `stream` and everything enqueued later waits for it (also
+ *   when `stream` is being captured into a graph).
  * tc_dtw_backward_run: as tc_dtw_backward, with `saved` written by a
  *   tc_dtw_banded_run of the same plan. */
 typedef struct {
@@ -179,6 +186,7 @@ typedef struct {
 } tc_dtw_tuning;
 
 #define TC_DTW_PLAN_MAX_CLASSES 32
+#define TC_DTW_RUN_STREAMS 4
 
 typedef struct {
     int32_t rows;        /* 1: row mapping, 0: diagonal mapping */
@@ -189,6 +197,9 @@ typedef struct {
     int32_t waves_per_pair; /* row mapping: waves sharing each pair (1: one wave per pair) */
     int64_t max_words;   /* largest argmin-code record of the class (u32 words) */
     int64_t desc_off;    /* byte offset of the class's descriptors in the plan buffer */
+    double work;         /* band cells x (2 D + 2) summed over the class: balances the streams */
+    int32_t stream;      /* which of the library's streams runs the class */
+    int32_t reserved;
 } tc_dtw_plan_class;
 
 typedef struct {

@@ -39,7 +39,8 @@ PLAN_MAX_CLASSES = 32
 class PlanClass(C.Structure):
     _fields_ = [("rows", C.c_int32), ("wodd", C.c_int32), ("dim", C.c_int32), ("nitems", C.c_int32),
                 ("maxm", C.c_int32), ("maxn", C.c_int32), ("maxw", C.c_int32), ("waves_per_pair", C.c_int32),
-                ("max_words", C.c_int64), ("desc_off", C.c_int64)]
+                ("max_words", C.c_int64), ("desc_off", C.c_int64), ("work", C.c_double),
+                ("stream", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PairsPlan(C.Structure):

@@ -63,11 +63,31 @@ static bool use_rows(int m, int n, int W, int D, int diag_max) {
     return W > diag_max || diag_lds_bytes(m, n, W, D, 1) > kDiagLdsBudget;
 }
 
-// Waves sharing a pair on the row mapping: by its number of 64-row blocks,
-// capped by the tuning and by LDS (sized for a float64 row buffer).
-static int waves_for(int m, int n, int D, int cap) {
+// Steps x lane-operations of one wave running a pair on the row mapping:
+// its 64-row blocks each sweep the block's band columns plus 63.
+static double rows_wave_cost(int m, int n, int W, int D) {
     const int nb = (m + kRowBlock - 1) / kRowBlock;
-    int K = nb <= 2 ? 1 : nb <= 8 ? 2 : nb <= 16 ? 4 : 8;
+    double steps = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int i0 = b * kRowBlock;
+        steps += std::min(n - 1, i0 + kRowBlock - 1 + W) - std::max(0, i0 - W) + kRowBlock;
+    }
+    return steps * (2.0 * D + 14.0);
+}
+
+// Waves sharing a pair on the row mapping.  One wave per pair keeps every
+// wave busy (waiting waves of a pipelined pair cost throughput), but a pair
+// whose single-wave time exceeds the time the whole batch needs would be
+// the critical path: it gets K = that ratio, rounded up to 2, 4 or 8,
+// capped by the tuning and by LDS (sized for a float64 row buffer).  The
+// batch time is estimated as its work spread over 256 wave slots (the
+// 1024 SIMDs at the quarter of peak issue that row kernels reach with
+// mixed shapes).  A pair of at most two row blocks has nothing to pipeline.
+static int waves_for(int m, int n, int W, int D, double spread, int cap) {
+    const int nb = (m + kRowBlock - 1) / kRowBlock;
+    if (nb <= 2 || spread <= 0) return 1;
+    const double ratio = rows_wave_cost(m, n, W, D) / spread;
+    int K = ratio <= 1.0 ? 1 : ratio <= 2.0 ? 2 : ratio <= 4.0 ? 4 : 8;
     K = std::min(K, cap);
     while (K > 1 && pipe_lds_bytes(n, D, K, true) > 163840) K /= 2;
     return std::max(K, 1);
@@ -111,6 +131,13 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
         P.saved_words = P.codes_stride * P.npairs;
         return TC_DTW_OK;
     }
+    // the batch's row-mapping work spread over the chip's SIMDs
+    double spread = 0;
+    for (int b = 0; b < P.npairs; ++b) {
+        const int m = X.length(b), n = Y.length(b), W = window_eff(m, n, w), D = X.dimension(b);
+        if (use_rows(m, n, W, D, diag_max)) spread += rows_wave_cost(m, n, W, 4 * nch_pad(D));
+    }
+    spread /= 256.0;
     // class key: mapping kind (diag even, diag odd, rows) x dimension class x waves per pair
     int index[3][17][9];
     for (auto& r : index)
@@ -132,7 +159,7 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
         soff += words;
         const int kind = d.rows ? 2 : (d.W & 1);
         const int nch = nch_pad(d.D);
-        const int K = d.rows ? waves_for(d.m, d.n, 4 * nch, P.waves_per_pair) : 1;
+        const int K = d.rows ? waves_for(d.m, d.n, d.W, 4 * nch, spread, P.waves_per_pair) : 1;
         int& ci = index[kind][nch][K];
         if (ci < 0) {
             if ((int)P.classes.size() == TC_DTW_PLAN_MAX_CLASSES)
@@ -206,7 +233,64 @@ static void to_public(const PairsPlan& P, const std::vector<size_t>& off, void* 
         o.waves_per_pair = c.K;
         o.max_words = c.max_words;
         o.desc_off = (int64_t)off[k];
+        o.work = c.work;
     }
+    // classes to streams, heaviest first onto the least loaded stream
+    double load[TC_DTW_RUN_STREAMS] = {0};
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        int best = 0;
+        for (int i = 1; i < TC_DTW_RUN_STREAMS; ++i)
+            if (load[i] < load[best]) best = i;
+        out->cls[k].stream = best;
+        load[best] += P.classes[k].work;
+    }
+}
+
+// The streams a run forks to, created once per device, with the events of
+// the fork and the join.  One run at a time enqueues on them (mutex); the
+// work itself overlaps freely.
+struct RunStreams {
+    hipStream_t s[TC_DTW_RUN_STREAMS];
+    hipEvent_t fork;
+    hipEvent_t done[TC_DTW_RUN_STREAMS];
+    std::mutex mu;
+};
+
+static RunStreams* run_streams(hipError_t& err) {
+    int dev = 0;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess) return nullptr;
+    static std::mutex mu;
+    static std::map<int, RunStreams*> pools;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    RunStreams* r = new RunStreams();
+    for (int i = 0; i < TC_DTW_RUN_STREAMS && err == hipSuccess; ++i)
+        err = hipStreamCreateWithFlags(&r->s[i], hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&r->fork, hipEventDisableTiming);
+    for (int i = 0; i < TC_DTW_RUN_STREAMS && err == hipSuccess; ++i)
+        err = hipEventCreateWithFlags(&r->done[i], hipEventDisableTiming);
+    if (err != hipSuccess) return nullptr;   // kept nothing: the next call tries again
+    pools[dev] = r;
+    return r;
+}
+
+// Fork: the library streams wait for everything enqueued on `s` so far.
+static hipError_t fork_from(RunStreams* r, hipStream_t s) {
+    hipError_t e = hipEventRecord(r->fork, s);
+    for (int i = 0; i < TC_DTW_RUN_STREAMS && e == hipSuccess; ++i) e = hipStreamWaitEvent(r->s[i], r->fork, 0);
+    return e;
+}
+
+// Join: `s` waits for everything the run put on the library streams.
+static hipError_t join_into(RunStreams* r, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < TC_DTW_RUN_STREAMS && e == hipSuccess; ++i) {
+        e = hipEventRecord(r->done[i], r->s[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, r->done[i], 0);
+    }
+    return e;
 }
 
 static tc_dtw_status upload(const PairsPlan& P, const std::vector<size_t>& off, void* buf, hipStream_t s) {
@@ -235,14 +319,19 @@ static tc_dtw_status check_plan(const tc_dtw_pairs_plan* p) {
 }
 
 static tc_dtw_status run_fwd(const tc_dtw_pairs_plan* p, const float* x, const float* y, uint32_t flags,
-                             float* dist, void* saved, hipStream_t s) {
+                             float* dist, void* saved, hipStream_t s0) {
     const bool f64 = (flags & TC_DTW_F64) != 0;
     char* base = static_cast<char*>(p->buf);
     int32_t* counters = reinterpret_cast<int32_t*>(base);
-    hipError_t e = launch_zero_i32(counters, TC_DTW_PLAN_MAX_CLASSES, s);
+    hipError_t e = launch_zero_i32(counters, TC_DTW_PLAN_MAX_CLASSES, s0);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
     const size_t lim = lds_limit();
+    RunStreams* rs = run_streams(e);
+    if (!rs) return hip_fail(e, "run streams");
+    std::lock_guard<std::mutex> lk(rs->mu);
+    if ((e = fork_from(rs, s0)) != hipSuccess) return hip_fail(e, "stream fork");
     for (int k = 0; k < p->nclasses; ++k) {
+        hipStream_t s = rs->s[p->cls[k].stream % TC_DTW_RUN_STREAMS];
         const tc_dtw_plan_class& c = p->cls[k];
         DtwFwdArgs a;
         std::memset(&a, 0, sizeof a);
@@ -260,29 +349,35 @@ static tc_dtw_status run_fwd(const tc_dtw_pairs_plan* p, const float* x, const f
         const int K = c.rows ? c.waves_per_pair : 1;
         if (K > 1) {
             const size_t lds = pipe_lds_bytes(c.maxn, c.dim, K, f64);
-            if (lds > lim) return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
+            if (lds > lim) { (void)join_into(rs, s0); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair"); }
             const int per_cu = std::max(1, std::min(p->waves_per_cu / K, (int)(lim / lds)));
             const int grid = std::max(1, std::min(c.nitems, 256 * per_cu));
             e = launch_dtw_rows_pipe(a, f64, saved != nullptr, K, c.nitems, grid, s);
         } else {
             const size_t lds = fwd_lds_bytes(a, c.rows != 0, f64);
-            if (lds > lim) return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
+            if (lds > lim) { (void)join_into(rs, s0); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair"); }
             e = launch_dtw_fwd(a, f64, saved != nullptr, c.rows != 0, c.nitems,
                                persistent_grid(lds, p->waves_per_cu, c.nitems), s);
         }
-        if (e != hipSuccess) return hip_fail(e, "dtw forward launch");
+        if (e != hipSuccess) { (void)join_into(rs, s0); return hip_fail(e, "dtw forward launch"); }
     }
+    if ((e = join_into(rs, s0)) != hipSuccess) return hip_fail(e, "stream join");
     return ok();
 }
 
 static tc_dtw_status run_bwd(const tc_dtw_pairs_plan* p, const float* x, const float* y, const void* saved,
-                             const float* grad_dist, float* grad_x, float* grad_y, hipStream_t s) {
+                             const float* grad_dist, float* grad_x, float* grad_y, hipStream_t s0) {
     char* base = static_cast<char*>(p->buf);
     int32_t* counters = reinterpret_cast<int32_t*>(base);
-    hipError_t e = launch_zero_i32(counters, TC_DTW_PLAN_MAX_CLASSES, s);
+    hipError_t e = launch_zero_i32(counters, TC_DTW_PLAN_MAX_CLASSES, s0);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
     const size_t lim = lds_limit();
+    RunStreams* rs = run_streams(e);
+    if (!rs) return hip_fail(e, "run streams");
+    std::lock_guard<std::mutex> lk(rs->mu);
+    if ((e = fork_from(rs, s0)) != hipSuccess) return hip_fail(e, "stream fork");
     for (int k = 0; k < p->nclasses; ++k) {
+        hipStream_t s = rs->s[p->cls[k].stream % TC_DTW_RUN_STREAMS];
         const tc_dtw_plan_class& c = p->cls[k];
         DtwBwdArgs a;
         std::memset(&a, 0, sizeof a);
@@ -297,11 +392,12 @@ static tc_dtw_status run_bwd(const tc_dtw_pairs_plan* p, const float* x, const f
         a.grad_y = grad_y;
         a.counter = counters + k;
         const size_t lds = bwd_lds_bytes(c.maxm, c.maxn, c.max_words);
-        if (lds > lim) return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the backward's LDS");
+        if (lds > lim) { (void)join_into(rs, s0); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the backward's LDS"); }
         e = launch_dtw_bwd(a, c.maxm, c.maxn, c.max_words, c.nitems,
                            persistent_grid(lds, p->waves_per_cu, c.nitems), s);
-        if (e != hipSuccess) return hip_fail(e, "dtw backward launch");
+        if (e != hipSuccess) { (void)join_into(rs, s0); return hip_fail(e, "dtw backward launch"); }
     }
+    if ((e = join_into(rs, s0)) != hipSuccess) return hip_fail(e, "stream join");
     return ok();
 }
 

@@ -237,122 +237,186 @@ __device__ __forceinline__ void load_point(const float* src, int len, int D, int
     }
 }
 
-// Row-systolic mapping, one pair per wave: lane l owns row i0 + l of a
-// block of 64 rows and sweeps the block's band columns, lane l reading
-// column jlo - l + t at step t; up and diag come from lane l - 1 by a DPP
-// shift (lane 0 from the row buffer), left from the lane itself.
+// Row-systolic mapping: lane l owns row i0 + l of a block of 64 rows and
+// sweeps the block's band columns, lane l reading column jlo - l + t at
+// step t; up and diag come from lane l - 1 by a DPP shift (lane 0 from the
+// row buffer), left from the lane itself.
 //
-// LDS at float4 index sc: a ring of kRowRing = 128 candidate positions
-// ([k][128] float4, column j at slot (j + 64) mod 128), then the row buffer
-// (T[n + 2 kRowPad], column j at j + kRowPad) holding the last row of the
-// previous block.  At step t the wave reads columns jlo + t - 63 .. jlo + t,
-// so 128 positions hold everything live: at the start of a block columns
-// jlo - 63 .. jlo + 64 are loaded, and every 64 steps the next 64 columns
-// (prefetched into registers during the previous 64 steps) replace the 64
-// that no lane reads any more.  LDS therefore does not grow with the window
-// or the dimension count beyond 2 KB per float4 chunk.  Candidate positions
+// LDS at float4 index `ring`: a ring of 128 candidate positions plus 8
+// mirrored slots ([k][136] float4, column j at slot (j + 64) mod 128; slots
+// 0..7 are repeated at 128..135 so that up to 8 consecutive steps read at
+// fixed offsets from one base), and the row buffer (T[n + 2 kRowPad],
+// column j at j + kRowPad) holding the last row of the previous block.  At
+// step t the wave reads columns jlo + t - 63 .. jlo + t, so 128 positions
+// hold everything live: at the start of a block columns jlo - 63 .. jlo + 64
+// are loaded, and every 64 steps the next 64 columns (prefetched into
+// registers during the previous 64 steps) replace the 64 no lane reads any
+// more.  LDS therefore does not grow with the window.  Candidate positions
 // outside [0, n) hold -inf, query rows past m hold +inf, so cells outside
-// the matrix cost +inf.  xs: query rows, ys: candidate, in global memory.
-// Returns the DTW value in the lane (m - 1) mod 64 (others undefined).
+// the matrix cost +inf.  Steps run in groups of U (8 / chunks, at least 1):
+// the group's candidate points and row-buffer values are read first, then
+// the U cells are evaluated, then lane 63 stores its U values.  The last
+// block stops at the step that evaluates cell (m-1, n-1).
 constexpr int kRowRing = 2 * kRowBlock;
+constexpr int kRowMirror = 8;
+constexpr int kRowStride = kRowRing + kRowMirror;   // float4 per chunk of a ring
 
+template <int NCH>
+__device__ __forceinline__ void ring_put(int ring, int j, const float4 (&v)[NCH]) {
+    const int slot = (j + kRowBlock) & (kRowRing - 1);
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) lds4[ring + slot + k * kRowStride] = v[k];
+    if (slot < kRowMirror) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) lds4[ring + kRowRing + slot + k * kRowStride] = v[k];
+    }
+}
+
+// State of one wave in one row block.
+template <typename T, int NCH>
+struct RowBlock {
+    float4 qv[NCH];
+    int i0, jlo, jhi, T_b, T_end;   // T_end: steps actually run (the last block stops at the end cell)
+    int k0, cs0, rb, wb;
+    T cur, prevup;
+    uint32_t cw;
+    uint32_t* cp;
+};
+
+// Steps [ta, tb) of block B (tb - ta <= 64, no refill in between).
+template <typename T, int NCH, bool SAVE>
+__device__ __forceinline__ void rows_steps(int ring, const T* rowbuf, T* rowbuf_w, int W, int lane,
+                                           RowBlock<T, NCH>& B, int ta, int tb) {
+    constexpr int U = NCH >= 8 ? 1 : NCH >= 4 ? 2 : NCH >= 2 ? 4 : 8;
+    const T INF = inf_v<T>();
+    const unsigned W2 = (unsigned)(2 * W);
+    auto step = [&](int t, const float4 (&cv)[NCH], T upin) -> T {
+        const T up = wave_shr1(upin, B.cur);
+        const T diag = B.prevup;
+        B.prevup = up;
+        const T left = B.cur;
+        const T cost = point_cost<NCH>(B.qv, cv, T(0));
+        T best;
+        if (SAVE) {
+            uint32_t code = 0;
+            best = diag;
+            if (up < best) { best = up; code = 1; }
+            if (left < best) { best = left; code = 2; }
+            B.cw |= code << ((t & 15) * 2);
+            if ((t & 15) == 15 || t == B.T_end - 1) {
+                B.cp[(int64_t)(t >> 4) * kWave] = B.cw;
+                B.cw = 0;
+            }
+        } else {
+            best = vmin3(diag, up, left);
+        }
+        T v = add_cost(cost, best);
+        v = ((unsigned)(t + B.k0) <= W2) ? v : INF;
+        B.cur = v;
+        return v;
+    };
+    int t = ta;
+    for (; t + U <= tb; t += U) {
+        const int sb = ring + ((B.cs0 + t) & (kRowRing - 1));
+        float4 cv[U][NCH];
+        T upv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) cv[u][k] = lds4[sb + u + k * kRowStride];
+            upv[u] = rowbuf[B.rb + t + u];
+        }
+        T out[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) out[u] = step(t + u, cv[u], upv[u]);
+        if (lane == kRowBlock - 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) rowbuf_w[B.wb + t + u] = out[u];
+        }
+    }
+    for (; t < tb; ++t) {
+        const int sb = ring + ((B.cs0 + t) & (kRowRing - 1));
+        float4 cv[NCH];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) cv[k] = lds4[sb + k * kRowStride];
+        const T v = step(t, cv, rowbuf[B.rb + t]);
+        if (lane == kRowBlock - 1) rowbuf_w[B.wb + t] = v;
+    }
+}
+
+// Sets up block b: query rows into registers, the ring's first 128 columns.
+template <typename T, int NCH, bool SAVE>
+__device__ __forceinline__ void rows_block_begin(int ring, const T* rowbuf, const float* xs, const float* ys,
+                                                 int m, int n, int W, int D, int lane, int b, int nwb,
+                                                 uint32_t* codes, RowBlock<T, NCH>& B) {
+    const T INF = inf_v<T>();
+    B.i0 = b * kRowBlock;
+    const int i = B.i0 + lane;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int p = 4 * k + e;
+            v[e] = (i < m) ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
+        }
+        B.qv[k] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    B.jlo = max(0, B.i0 - W);
+    B.jhi = min(n - 1, B.i0 + kRowBlock - 1 + W);
+    {   // columns jlo - 63 .. jlo + 64
+        float4 v0[NCH], v1[NCH];
+        load_point<NCH>(ys, n, D, B.jlo - (kRowBlock - 1) + lane, -__builtin_inff(), v0);
+        load_point<NCH>(ys, n, D, B.jlo + 1 + lane, -__builtin_inff(), v1);
+        ring_put<NCH>(ring, B.jlo - (kRowBlock - 1) + lane, v0);
+        ring_put<NCH>(ring, B.jlo + 1 + lane, v1);
+    }
+    B.T_b = B.jhi - B.jlo + kRowBlock;
+    const int nb = (m + kRowBlock - 1) / kRowBlock;
+    // the last block stops after lane m-1-i0 has evaluated column n-1
+    B.T_end = (b == nb - 1) ? min(B.T_b, (n - 1) - B.jlo + (m - 1 - B.i0) + 1) : B.T_b;
+    B.k0 = B.jlo - B.i0 + W - 2 * lane;           // band offset k = t + k0 must lie in [0, 2W]
+    B.cs0 = B.jlo - lane + kRowBlock;              // ring slot of step t: (cs0 + t) mod 128
+    B.rb = B.jlo + kRowPad;                        // rowbuf index of lane 0's up value: rb + t
+    B.wb = B.jlo - (kRowBlock - 1) + kRowPad;      // lane 63 writes rowbuf[wb + t]
+    B.cur = INF;
+    B.prevup = INF;
+    B.cw = 0;
+    B.cp = SAVE ? codes + (int64_t)b * nwb * kWave + lane : nullptr;
+}
+
+// One wave per pair.  sc: LDS float4 index of the ring; the row buffer follows it.
+// Returns the DTW value in the lane (m - 1) mod 64 (others undefined).
 template <typename T, int NCH, bool SAVE, bool ABANDON>
 __device__ __forceinline__ T rows_core(int sc, const float* xs, const float* ys, int m,
                                        int n, int W, int D, int lane, uint32_t* codes,
                                        const Abandon& ab, bool& aband, int* blocks_done = nullptr) {
     const T INF = inf_v<T>();
-    const float NINF = -__builtin_inff();
-    constexpr int RS = kRowRing, mask = kRowRing - 1;
-    T* rowbuf = reinterpret_cast<T*>(lds4 + sc + RS * NCH);
+    T* rowbuf = reinterpret_cast<T*>(lds4 + sc + kRowStride * NCH);
     const int LB = n + 2 * kRowPad;
     for (int pos = lane; pos < LB; pos += kWave) rowbuf[pos] = (pos - kRowPad == -1) ? T(0) : INF;
-    auto put = [&](int j, const float4 (&v)[NCH]) {
-        const int slot = sc + ((j + kRowBlock) & mask);
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) lds4[slot + k * RS] = v[k];
-    };
     const int nb = (m + kRowBlock - 1) / kRowBlock;
     const int band = min(n, 2 * W + kRowBlock);
     const int nwb = (band + kRowBlock - 1 + 15) / 16;
     T result = INF;
     if (blocks_done) *blocks_done = nb;
     for (int b = 0; b < nb; ++b) {
-        const int i0 = b * kRowBlock;
-        const int i = i0 + lane;
-        float4 qv[NCH];
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int p = 4 * k + e;
-                v[e] = (i < m) ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
-            }
-            qv[k] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        const int jlo = max(0, i0 - W);
-        const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
-        {   // columns jlo - 63 .. jlo + 64
-            float4 v0[NCH], v1[NCH];
-            load_point<NCH>(ys, n, D, jlo - (kRowBlock - 1) + lane, NINF, v0);
-            load_point<NCH>(ys, n, D, jlo + 1 + lane, NINF, v1);
-            put(jlo - (kRowBlock - 1) + lane, v0);
-            put(jlo + 1 + lane, v1);
-        }
+        RowBlock<T, NCH> B;
+        rows_block_begin<T, NCH, SAVE>(sc, rowbuf, xs, ys, m, n, W, D, lane, b, nwb, codes, B);
         __syncthreads();
-        const int T_b = jhi - jlo + kRowBlock;
-        const int k0 = jlo - i0 + W - 2 * lane;          // band offset k = t + k0 must lie in [0, 2W]
-        const int cs0 = jlo - lane + kRowBlock;          // ring slot of step t: (cs0 + t) & mask
-        const int rb = jlo + kRowPad;                    // rowbuf index + t
-        const int wb = jlo - (kRowBlock - 1) + kRowPad;  // lane 63 writes rowbuf[wb + t]
-        T cur = INF;
-        T prevup = (lane == 0) ? rowbuf[jlo - 1 + kRowPad] : INF;
-        const bool last = (b == nb - 1);
-        const int tend = (n - 1) - jlo + (m - 1 - i0);
-        uint32_t cw = 0;
-        uint32_t* cp = SAVE ? codes + (int64_t)b * nwb * kWave + lane : nullptr;
-        for (int t0 = 0; t0 < T_b; t0 += kRowBlock) {
-            // columns for steps t0 + 64 .. t0 + 127, written after steps t0 .. t0 + 63
-            const bool refill = t0 + kRowBlock < T_b;
+        if (lane == 0) B.prevup = rowbuf[B.jlo - 1 + kRowPad];
+        for (int t0 = 0; t0 < B.T_end; t0 += kRowBlock) {
+            const bool refill = t0 + kRowBlock < B.T_end;
             float4 nx[NCH];
-            if (refill) load_point<NCH>(ys, n, D, jlo + t0 + kRowBlock + 1 + lane, NINF, nx);
-            const int t1 = min(T_b, t0 + kRowBlock);
-            for (int t = t0; t < t1; ++t) {
-                const int cl = sc + ((cs0 + t) & mask);
-                float4 cv[NCH];
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) cv[k] = lds4[cl + k * RS];
-                const T up = wave_shr1(rowbuf[rb + t], cur);
-                const T diag = prevup;
-                prevup = up;
-                const T left = cur;
-                const T cost = point_cost<NCH>(qv, cv, T(0));
-                T best;
-                if (SAVE) {
-                    uint32_t code = 0;
-                    best = diag;
-                    if (up < best) { best = up; code = 1; }
-                    if (left < best) { best = left; code = 2; }
-                    cw |= code << ((t & 15) * 2);
-                    if ((t & 15) == 15 || t == T_b - 1) {
-                        cp[(int64_t)(t >> 4) * kWave] = cw;
-                        cw = 0;
-                    }
-                } else {
-                    best = vmin3(diag, up, left);
-                }
-                T v = add_cost(cost, best);
-                const unsigned kb = (unsigned)(t + k0);
-                v = (kb <= (unsigned)(2 * W)) ? v : INF;
-                cur = v;
-                if (lane == kRowBlock - 1) rowbuf[wb + t] = v;
-                if (last && t == tend && lane == m - 1 - i0) result = v;
-            }
-            if (refill) put(jlo + t0 + kRowBlock + 1 + lane, nx);
+            if (refill) load_point<NCH>(ys, n, D, B.jlo + t0 + kRowBlock + 1 + lane, -__builtin_inff(), nx);
+            rows_steps<T, NCH, SAVE>(sc, rowbuf, rowbuf, W, lane, B, t0, min(B.T_end, t0 + kRowBlock));
+            if (refill) ring_put<NCH>(sc, B.jlo + t0 + kRowBlock + 1 + lane, nx);
         }
+        if (b == nb - 1) result = B.cur;
         __syncthreads();
         if (ABANDON && b + 1 < nb) {
             // every path crosses row i0+63: its minimum bounds the final value from below
+            const int i0 = B.i0;
             const int r0 = max(0, i0 + kRowBlock - 1 - W), r1 = min(n - 1, i0 + kRowBlock - 1 + W);
             T mn = INF;
             for (int j = r0 + lane; j <= r1; j += kWave) mn = vmin(mn, rowbuf[j + kRowPad]);
@@ -367,6 +431,11 @@ __device__ __forceinline__ T rows_core(int sc, const float* xs, const float* ys,
         }
     }
     return result;
+}
+
+// LDS bytes of rows_core for candidate length n (tbytes = sizeof(T)).
+__host__ __device__ inline size_t rows_core_lds(int n, int nch, int tbytes) {
+    return (size_t)kRowStride * nch * 16 + (size_t)(n + 2 * kRowPad) * tbytes;
 }
 
 // Row mapping with K waves per pair (one workgroup of 64 K threads): wave
@@ -390,60 +459,22 @@ __device__ __forceinline__ T rows_core_pipe(int ring, T* rowbuf, int* prog, int 
                                             const float* xs, const float* ys, int m, int n, int W,
                                             int D, int lane, uint32_t* codes, bool& late) {
     const T INF = inf_v<T>();
-    const float NINF = -__builtin_inff();
-    constexpr int RS = kRowRing, mask = kRowRing - 1;
-    auto put = [&](int j, const float4 (&v)[NCH]) {
-        const int slot = ring + ((j + kRowBlock) & mask);
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) lds4[slot + k * RS] = v[k];
-    };
     const int nb = (m + kRowBlock - 1) / kRowBlock;
     const int band = min(n, 2 * W + kRowBlock);
     const int nwb = (band + kRowBlock - 1 + 15) / 16;
     const int pw = wv == 0 ? K - 1 : wv - 1;   // wave of the previous block
     T result = INF;
     for (int b = wv; b < nb; b += K) {
-        const int i0 = b * kRowBlock;
-        const int i = i0 + lane;
-        float4 qv[NCH];
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int p = 4 * k + e;
-                v[e] = (i < m) ? (p < D ? xs[(int64_t)i * D + p] : 0.0f) : __builtin_inff();
-            }
-            qv[k] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        const int jlo = max(0, i0 - W);
-        const int jhi = min(n - 1, i0 + kRowBlock - 1 + W);
+        RowBlock<T, NCH> B;
+        rows_block_begin<T, NCH, SAVE>(ring, rowbuf, xs, ys, m, n, W, D, lane, b, nwb, codes, B);
         // the previous block: its first column and its step count
-        const int pjlo = max(0, i0 - kRowBlock - W);
-        const int pT = b > 0 ? min(n - 1, i0 - 1 + W) - pjlo + kRowBlock : 0;
-        {
-            float4 v0[NCH], v1[NCH];
-            load_point<NCH>(ys, n, D, jlo - (kRowBlock - 1) + lane, NINF, v0);
-            load_point<NCH>(ys, n, D, jlo + 1 + lane, NINF, v1);
-            put(jlo - (kRowBlock - 1) + lane, v0);
-            put(jlo + 1 + lane, v1);
-        }
-        const int T_b = jhi - jlo + kRowBlock;
-        const int k0 = jlo - i0 + W - 2 * lane;
-        const int cs0 = jlo - lane + kRowBlock;
-        const int rb = jlo + kRowPad;
-        const int wb = jlo - (kRowBlock - 1) + kRowPad;
-        T cur = INF;
-        T prevup = INF;
-        const bool last = (b == nb - 1);
-        const int tend = (n - 1) - jlo + (m - 1 - i0);
-        uint32_t cw = 0;
-        uint32_t* cp = SAVE ? codes + (int64_t)b * nwb * kWave + lane : nullptr;
-        for (int t0 = 0; t0 < T_b; t0 += kRowBlock) {
+        const int pjlo = max(0, B.i0 - kRowBlock - W);
+        const int pT = b > 0 ? min(n - 1, B.i0 - 1 + W) - pjlo + kRowBlock : 0;
+        for (int t0 = 0; t0 < B.T_end; t0 += kRowBlock) {
             if (b > 0 && K > 1 && !late) {
                 // columns up to jlo + t0 + 63 are written by the previous block's step
                 // (column - pjlo + 63); it must have completed that many steps
-                const int need = min(pT, jlo - pjlo + t0 + 2 * kRowBlock - 1);
+                const int need = min(pT, B.jlo - pjlo + t0 + 2 * kRowBlock - 1);
                 const int target = (b - 1) * kProgStride + need;
                 int spins = 0;
                 for (;;) {
@@ -457,47 +488,18 @@ __device__ __forceinline__ T rows_core_pipe(int ring, T* rowbuf, int* prog, int 
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
-            if (t0 == 0) prevup = (lane == 0) ? rowbuf[jlo - 1 + kRowPad] : INF;
-            const bool refill = t0 + kRowBlock < T_b;
+            if (t0 == 0 && lane == 0) B.prevup = rowbuf[B.jlo - 1 + kRowPad];
+            const bool refill = t0 + kRowBlock < B.T_end;
             float4 nx[NCH];
-            if (refill) load_point<NCH>(ys, n, D, jlo + t0 + kRowBlock + 1 + lane, NINF, nx);
-            const int t1 = min(T_b, t0 + kRowBlock);
-            for (int t = t0; t < t1; ++t) {
-                const int cl = ring + ((cs0 + t) & mask);
-                float4 cv[NCH];
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) cv[k] = lds4[cl + k * RS];
-                const T up = wave_shr1(rowbuf[rb + t], cur);
-                const T diag = prevup;
-                prevup = up;
-                const T left = cur;
-                const T cost = point_cost<NCH>(qv, cv, T(0));
-                T best;
-                if (SAVE) {
-                    uint32_t code = 0;
-                    best = diag;
-                    if (up < best) { best = up; code = 1; }
-                    if (left < best) { best = left; code = 2; }
-                    cw |= code << ((t & 15) * 2);
-                    if ((t & 15) == 15 || t == T_b - 1) {
-                        cp[(int64_t)(t >> 4) * kWave] = cw;
-                        cw = 0;
-                    }
-                } else {
-                    best = vmin3(diag, up, left);
-                }
-                T v = add_cost(cost, best);
-                const unsigned kb = (unsigned)(t + k0);
-                v = (kb <= (unsigned)(2 * W)) ? v : INF;
-                cur = v;
-                if (lane == kRowBlock - 1) rowbuf[wb + t] = v;
-                if (last && t == tend && lane == m - 1 - i0) result = v;
-            }
-            if (refill) put(jlo + t0 + kRowBlock + 1 + lane, nx);
+            if (refill) load_point<NCH>(ys, n, D, B.jlo + t0 + kRowBlock + 1 + lane, -__builtin_inff(), nx);
+            const int t1 = min(B.T_end, t0 + kRowBlock);
+            rows_steps<T, NCH, SAVE>(ring, rowbuf, rowbuf, W, lane, B, t0, t1);
+            if (refill) ring_put<NCH>(ring, B.jlo + t0 + kRowBlock + 1 + lane, nx);
             // this block has completed t1 steps, its row-buffer writes included
             if (K > 1 && lane == 0)
                 __hip_atomic_store(prog + wv, b * kProgStride + t1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        if (b == nb - 1) result = B.cur;
     }
     return result;
 }
@@ -505,14 +507,9 @@ __device__ __forceinline__ T rows_core_pipe(int ring, T* rowbuf, int* prog, int 
 // LDS bytes of the K-wave row kernel: K rings, the row buffer, K progress
 // counters, the work item and a status flag.
 __host__ __device__ inline size_t rows_pipe_lds(int n, int nch, int K, int tbytes) {
-    const size_t rings = (size_t)K * kRowRing * nch * 16;
+    const size_t rings = (size_t)K * kRowStride * nch * 16;
     const size_t rowbuf = ((size_t)(n + 2 * kRowPad) * tbytes + 15) & ~(size_t)15;
     return rings + rowbuf + (size_t)(K + 2) * 4;
-}
-
-// LDS bytes of rows_core for candidate length n (tbytes = sizeof(T)).
-__host__ __device__ inline size_t rows_core_lds(int n, int nch, int tbytes) {
-    return (size_t)kRowRing * nch * 16 + (size_t)(n + 2 * kRowPad) * tbytes;
 }
 
 }  // namespace tcdtw

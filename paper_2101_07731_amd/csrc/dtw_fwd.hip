@@ -187,7 +187,7 @@ __global__ __launch_bounds__(512) void dtw_rows_pipe_kernel(DtwFwdArgs a) {
     const int K = blockDim.x / kWave;
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const T INF = inf_v<T>();
-    T* rowbuf = reinterpret_cast<T*>(lds4 + K * kRowRing * NCH);
+    T* rowbuf = reinterpret_cast<T*>(lds4 + K * kRowStride * NCH);
     const size_t rb_bytes = ((size_t)(a.n + 2 * kRowPad) * sizeof(T) + 15) & ~(size_t)15;
     int* prog = reinterpret_cast<int*>(reinterpret_cast<char*>(rowbuf) + rb_bytes);
     int* sitem = prog + K;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(512) void dtw_rows_pipe_kernel(DtwFwdArgs a) {
         if (threadIdx.x == 0) *sflag = 0;
         __syncthreads();
         bool late = false;
-        const T v = rows_core_pipe<T, NCH, SAVE>(wv * kRowRing * NCH, rowbuf, prog, K, wv, a.x + d.xoff,
+        const T v = rows_core_pipe<T, NCH, SAVE>(wv * kRowStride * NCH, rowbuf, prog, K, wv, a.x + d.xoff,
                                                  a.y + d.yoff, m, n, W, D, lane,
                                                  SAVE ? a.codes + d.saved_off : nullptr, late);
         if (late) *sflag = 1;
