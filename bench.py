@@ -239,7 +239,7 @@ def main():
                                             "finalize", "total"])},
         "index_build_ms": round(index_ms, 3),
         "roofline": {
-            "kernel": "k_knn_dtw_diag" if W <= 63 else "k_knn_dtw_rows",
+            "kernel": "k_knn_dtw_ring" if W <= 63 else "k_knn_dtw_rows",
             "bound": "alu",
             "achieved": round(achieved_gcells, 2),
             "peak": round(peak_gcells, 2),

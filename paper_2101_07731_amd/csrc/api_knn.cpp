@@ -115,7 +115,7 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.o_prefix = at((size_t)(K.nq + 1) * 4);
     K.o_items = 0;   // placed after P is final (below)
     K.o_counters = at(kNumCounters * 4);
-    K.o_key = at((size_t)K.nq * 8);
+    K.o_key = at((size_t)K.nq * 8 * kKeyStride);
     K.o_stats = at(kNumStats * 8);
     const bool any_pc = K.pc || true;   // the dense bound matrix may ask for LB_PC / LB_TI too
     (void)any_pc;

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
         const int ref = live ? (a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e) : 0;
         float bsf = __builtin_inff();
         if (a.key) {
-            bsf = key_bsf(a.key + q);
+            bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
             // selective deployment: only pairs with LB_MV > e^2 bsf
             const float mv = live ? a.lb_mv[(int64_t)q * a.nc + ref] : 0.0f;
             if (live && !((double)mv > a.e2 * (double)bsf)) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         if (a.key) {
             // selective deployment: only pairs whose bound so far exceeds e^2 bsf
             const float cur = a.lb_in[(int64_t)q * a.cap + e];
-            const float bsf = key_bsf(a.key + q);
+            const float bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
             if (wave_uniform(!((double)cur > a.e2 * (double)bsf))) {
                 if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;
                 continue;
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void k_route(RouteArgs a) {
     const int lane = threadIdx.x & 63;
     const int cnt = a.in_cnt[q];
     const bool valid = e < cnt;
-    const double bsf = (double)key_bsf(a.key + q);
+    const double bsf = (double)key_bsf(a.key + (int64_t)q * kKeyStride);
     int ref = 0;
     float lb = 0.0f;
     if (valid) {

@@ -400,7 +400,11 @@ __device__ __forceinline__ T rows_core(int sc, const float* xs, const float* ys,
     const int nwb = (band + kRowBlock - 1 + 15) / 16;
     T result = INF;
     if (blocks_done) *blocks_done = nb;
+    unsigned long long pend = 0;
     for (int b = 0; b < nb; ++b) {
+        // the best-so-far for this block's check, loaded a block ahead of its use: the
+        // coherent load is slow, and the block's own loads would otherwise wait for it
+        if (ABANDON) pend = __hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         RowBlock<T, NCH> B;
         rows_block_begin<T, NCH, SAVE>(sc, rowbuf, xs, ys, m, n, W, D, lane, b, nwb, codes, B);
         __syncthreads();
@@ -420,8 +424,7 @@ __device__ __forceinline__ T rows_core(int sc, const float* xs, const float* ys,
             const int r0 = max(0, i0 + kRowBlock - 1 - W), r1 = min(n - 1, i0 + kRowBlock - 1 + W);
             T mn = INF;
             for (int j = r0 + lane; j <= r1; j += kWave) mn = vmin(mn, rowbuf[j + kRowPad]);
-            const float thr = abandon_threshold(
-                bsf_from_key(__hip_atomic_load(ab.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), ab.gamma);
+            const float thr = abandon_threshold(bsf_from_key(pend), ab.gamma);
             const bool over = (float)mn > thr;
             if (__ballot(over) == ~0ull) {
                 aband = true;

@@ -112,6 +112,10 @@ struct IndexBuildArgs {
 hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s);
 
 // ------------------------------------------------------------------- 1-NN
+// Best-so-far keys of the queries sit 128 bytes apart: every query's key
+// is its own cache line, so the atomic updates and coherent reads of
+// different queries do not queue on shared lines.
+constexpr int kKeyStride = 16;   // u64 words
 constexpr int kQT = 8;           // queries per LB_MV tile
 constexpr int kMaxSeeds = 8;
 constexpr int kNumCounters = 8;

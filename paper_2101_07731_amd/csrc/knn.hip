@@ -39,7 +39,7 @@ __global__ void k_knn_init(int nq, unsigned long long* key, int32_t* cnt, int32_
                            int32_t* c2) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int q = t; q < nq; q += gridDim.x * blockDim.x) {
-        key[q] = 0x7f800000ffffffffull;     // best-so-far +inf, no candidate yet
+        key[(int64_t)q * kKeyStride] = 0x7f800000ffffffffull;     // best-so-far +inf, no candidate yet
         cnt[q] = 0;
         if (gcnt) gcnt[q] = 0;
         if (c0) c0[q] = 0;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_compact(const float* __restrict__ lb, i
     const int q = blockIdx.y;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const double bsf = (double)bsf_from_key(key[q]);
+    const double bsf = (double)bsf_from_key(key[(int64_t)q * kKeyStride]);
     const bool valid = r < nc;
     bool seed = false;
     for (int k = 0; k < R; ++k) seed |= (seeds[(int64_t)q * R + k] == r);
@@ -253,7 +253,7 @@ __device__ __forceinline__ int find_query(const int32_t* prefix, int nq, int ite
 __device__ __forceinline__ void publish(const KnnDtwArgs& a, int q, int ref, float v, float gamma) {
     const float up = round_up_pos((double)v / (1.0 - (double)gamma));
     const unsigned long long k = ((unsigned long long)__float_as_uint(up) << 32) | (uint32_t)ref;
-    atomicMin(&a.key[q], k);
+    atomicMin(&a.key[(int64_t)q * kKeyStride], k);
 }
 
 template <int NCH, bool WODD>
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
         if (!spare && lg == h) vE = 0.0f;
         const uint64_t valid_mask = (np * G >= 64) ? ~0ull : ((1ull << (np * G)) - 1);
         const uint64_t gm = spare ? 0ull : (((G >= 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G));
-        Abandon ab{a.key + q, a.gamma, valid_mask};
+        Abandon ab{a.key + (int64_t)q * kKeyStride, a.gamma, valid_mask};
         bool aband = false;
         int rounds;
         if (a.abandon)
@@ -344,6 +344,9 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
 // round is W + 5 positions; every RF = RS / 4 rounds the RF positions that
 // fell behind are overwritten with the next ones, loaded into registers one
 // refill ahead.  Series 0 is the query, series 1 + g the candidate of group g.
+// Rounds between early-abandon checks (a multiple of both refill periods).
+constexpr int kCheckRounds = 32;
+
 template <int NCH, bool WODD, int RS>
 __global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
     constexpr int RF = RS / 4, MIR = 8, STR = RS + MIR;
@@ -415,12 +418,10 @@ __global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
         const uint64_t gm = spare ? 0ull : (((G >= 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G));
         bool aband = false;
         const bool abandon = a.abandon != 0;
-        float thr = __builtin_inff();
+        // the best-so-far is read by a coherent (slow) load whose value is first needed at
+        // the first check: nothing waits for it at the start of the item
         unsigned long long pend = 0;
-        if (abandon) {
-            thr = abandon_threshold(bsf_from_key(__hip_atomic_load(a.key + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), a.gamma);
-            pend = __hip_atomic_load(a.key + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (abandon) pend = __hip_atomic_load(a.key + (int64_t)q * kKeyStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         float4 cA[NCH], cB[NCH];
 #pragma unroll
         for (int k = 0; k < NCH; ++k) cA[k] = lds4[cbase + lg + k * STR];
@@ -429,6 +430,17 @@ __global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
         bool done = false;
         while (r < R) {
             if (r > 0 && (r & (RF - 1)) == 0) {
+                const bool check = abandon && (r & (kCheckRounds - 1)) == 0;
+                if (check) {
+                    // the key loaded at the start of the item (a best-so-far only
+                    // decreases, so an older value is a safe threshold)
+                    const float thr = abandon_threshold(bsf_from_key(pend), a.gamma);
+                    // every warping path crosses one of the anti-diagonals 2r-2, 2r-1
+                    const bool over = vmin(vE, vO) > thr;
+                    const uint64_t bal = __ballot(over);
+                    if ((bal & gm) == gm) aband = true;
+                    if ((bal & valid_mask) == valid_mask) { done = true; break; }
+                }
                 // refill: positions r-RF+RS .. r+RS-1 (prefetched), then prefetch the next refill
 #pragma unroll
                 for (int p = 0; p < MAXPASS; ++p) {
@@ -457,15 +469,6 @@ __global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
 #pragma unroll
                 for (int k = 0; k < NCH; ++k) cA[k] = cB[k];
                 r += 1;
-            }
-            if (abandon && (r & 15) == 0 && r < R) {
-                // every warping path crosses one of the anti-diagonals 2r-2, 2r-1
-                const bool over = vmin(vE, vO) > thr;
-                const uint64_t bal = __ballot(over);
-                if ((bal & gm) == gm) aband = true;
-                if ((bal & valid_mask) == valid_mask) { done = true; break; }
-                thr = abandon_threshold(bsf_from_key(pend), a.gamma);
-                pend = __hip_atomic_load(a.key + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         (void)done;
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
         const int ref = (int)a.list[(int64_t)q * a.cap + e];
         const float* cser = a.C + (int64_t)(ref < 0 ? 0 : ref) * a.n * a.D;
         __syncthreads();
-        Abandon ab{a.key + q, a.gamma, ~0ull};
+        Abandon ab{a.key + (int64_t)q * kKeyStride, a.gamma, ~0ull};
         bool aband = false;
         float v;
         int blocks = 0;
