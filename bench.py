@@ -131,6 +131,37 @@ def extra_fwd_bwd(dev, reps=5):
             "fwd_gcups": round(B * band_cells(T, T, T // 10) / (ms_f * 1e-3) / 1e9, 2)}
 
 
+def extra_ragged_banks(dev, reps=2):
+    """256 queries of uneven length and d searching one of five banks (d in
+    {2,4,8,16,32}, 4096 references of lengths U[64, 2048] each), window 10%
+    of the longer series: one search call per bank."""
+    import torch
+    from paper_2101_07731_amd import search, synth
+    banks, queries = synth.ragged_banks()
+    work = []
+    for D, refs in banks.items():
+        Q = [torch.from_numpy(q).to(dev) for d, q in queries if d == D]
+        if not Q:
+            continue
+        ix = search.Index([torch.from_numpy(c).to(dev) for c in refs])
+        work.append((D, ix, Q))
+    st_all = {}
+
+    def run():
+        for D, ix, Q in work:
+            st_all[D] = search.knn(ix, Q, frac=(1, 10), bounds="mv", stats=True)[2]
+
+    ms = _events_ms(run, reps)
+    pairs = sum(s["pairs"] for s in st_all.values())
+    started = sum(s["dtw_started"] for s in st_all.values())
+    cells = sum(s["cells"] for s in st_all.values())
+    return {"workload": "256 queries, 5 banks (d in {2,4,8,16,32}) of 4096 references, lengths U[64,2048], window 10%",
+            "queries_per_s": round(len(queries) / (ms * 1e-3), 2), "ms": round(ms, 3),
+            "pct_dtw_pruned": round(100.0 * (1 - started / pairs), 3),
+            "gcups_dtw": round(cells / (ms * 1e-3) / 1e9, 2),
+            "per_bank_ms": {str(D): round(st_all[D]["stage_ms"][7], 3) for D in st_all}}
+
+
 def extra_long_knn(dev, reps=3):
     """200 queries x 2000 references, length 1024, d = 16, window 10% (row mapping)."""
     import torch
@@ -267,6 +298,7 @@ def main():
         out["batched_pairs"] = extra_batched_pairs(dev)
         out["dtw_loss"] = extra_fwd_bwd(dev)
         out["long_knn"] = extra_long_knn(dev)
+        out["ragged_banks"] = extra_ragged_banks(dev)
         kwp = dict(frac=frac, bounds="plain")
         search.knn(ix, Qd, **kwp)
         torch.cuda.synchronize()

@@ -283,6 +283,218 @@ static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, b
     return a;
 }
 
+// ------------------------------------------------------------ ragged banks
+// Queries or candidates of uneven lengths (one D): LB_MV with per-pair
+// windows (query sparse tables), DTW on the row mapping, float64 finalize.
+struct RaggedPlan {
+    int nq = 0, nc = 0, D = 0, R = 0, maxm = 0, maxn = 0;
+    bool plain = false, abandon = true;
+    tc_dtw_window win{};
+    std::vector<int64_t> q_off, t_off;
+    std::vector<int32_t> q_len;
+    int64_t tab_floats = 0;
+    size_t o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_gcnt, o_prefix, o_items, o_counters,
+        o_key, o_stats, o_qoff, o_qlen, o_toff, o_tab, bytes;
+};
+
+static bool is_ragged_search(const tc_dtw_index* ix, const tc_dtw_batch* qb) {
+    if (!ix || !qb) return false;
+    return ix->uniform_len <= 0 || qb->len != nullptr || qb->offset != nullptr;
+}
+
+static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch* qb, const tc_dtw_knn_params* p,
+                                      RaggedPlan& K, HostSet& Qs) {
+    tc_dtw_status st;
+    if ((st = check_index(ix)) != TC_DTW_OK) return st;
+    if ((st = read_set(qb, "queries", Qs)) != TC_DTW_OK) return st;
+    if (Qs.mixed) return fail(TC_DTW_ERR_UNSUPPORTED, "a search needs one dim for all queries (dims must be NULL)");
+    if ((st = check_params(p)) != TC_DTW_OK) return st;
+    if (Qs.dim != ix->dim) return fail(TC_DTW_ERR_INVALID, "queries and index have different dims");
+    if (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI))
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI need uniform query and candidate lengths");
+    K = RaggedPlan();
+    K.nq = Qs.count;
+    K.nc = ix->count;
+    K.D = Qs.dim;
+    K.win = p->window;
+    K.plain = (p->bounds & TC_DTW_LB_MV) == 0;
+    K.abandon = p->early_abandon != 0;
+    K.R = K.plain ? 0 : std::min(std::min(p->seed_r > 0 ? p->seed_r : 4, kMaxSeeds), K.nc);
+    K.maxn = ix->max_len;
+    K.q_off.resize(K.nq);
+    K.q_len.resize(K.nq);
+    K.t_off.resize(K.nq);
+    for (int q = 0; q < K.nq; ++q) {
+        const int m = Qs.length(q);
+        K.q_off[q] = Qs.offset(q);
+        K.q_len[q] = m;
+        K.maxm = std::max(K.maxm, m);
+        K.t_off[q] = K.tab_floats;
+        int L = 0;
+        while ((1 << L) <= m) ++L;   // floor(log2 m) + 1
+        K.tab_floats += 2LL * L * m * K.D;
+    }
+    const size_t lim = 163840;
+    if (rknn_final_lds_bytes(K.maxn, K.D) > lim)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "candidates too long for the row buffer of one pair");
+    Carve c(nullptr, 0);
+    auto at = [&](size_t bytes) { c.used = (c.used + 255) & ~(size_t)255; size_t o = c.used; c.used += bytes; return o; };
+    const size_t pairs = (size_t)K.nq * K.nc;
+    K.o_lb = at(K.plain ? 0 : pairs * 4);
+    K.o_seeds = at((size_t)K.nq * std::max(K.R, 1) * 4);
+    K.o_seed_dist = at((size_t)K.nq * std::max(K.R, 1) * 4);
+    K.o_list = at(pairs * 4);
+    K.o_list_dist = at(pairs * 4);
+    K.o_cnt = at((size_t)K.nq * 4);
+    K.o_gcnt = at((size_t)K.nq * 4);
+    K.o_prefix = at((size_t)(K.nq + 1) * 4);
+    K.o_items = at(pairs * 4);
+    K.o_counters = at(kNumCounters * 4);
+    K.o_key = at((size_t)K.nq * 8 * kKeyStride);
+    K.o_stats = at(kNumStats * 8);
+    K.o_qoff = at((size_t)K.nq * 8);
+    K.o_qlen = at((size_t)K.nq * 4);
+    K.o_toff = at((size_t)K.nq * 8);
+    K.o_tab = at(K.plain ? 0 : (size_t)K.tab_floats * 4);
+    K.bytes = c.need();
+    return TC_DTW_OK;
+}
+
+static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* queries, const tc_dtw_knn_params* p,
+                                int32_t* nn_idx, float* nn_dist, tc_dtw_knn_stats* stats, void* ws, size_t ws_bytes,
+                                hipStream_t s) {
+    RaggedPlan K;
+    HostSet Qs;
+    tc_dtw_status st = make_ragged_plan(ix, queries, p, K, Qs);
+    if (st != TC_DTW_OK) return st;
+    if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
+    if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
+    if ((st = check_device()) != TC_DTW_OK) return st;
+    char* w = static_cast<char*>(ws);
+    char* base = static_cast<char*>(ix->buf);
+    const int64_t* c_off = reinterpret_cast<const int64_t*>(base + ix->off_meta);
+    const int32_t* c_len = reinterpret_cast<const int32_t*>(c_off + 2 * (int64_t)ix->count);
+
+    KnnPlanDev d;
+    std::memset(&d, 0, sizeof d);
+    d.Q = Qs.data;
+    d.C = reinterpret_cast<const float*>(base + ix->off_series);
+    d.nq = K.nq; d.nc = K.nc; d.D = K.D; d.R = K.R; d.cap = K.nc;
+    d.lb = K.plain ? nullptr : reinterpret_cast<float*>(w + K.o_lb);
+    d.seeds = reinterpret_cast<int32_t*>(w + K.o_seeds);
+    d.seed_dist = reinterpret_cast<float*>(w + K.o_seed_dist);
+    d.list = reinterpret_cast<uint32_t*>(w + K.o_list);
+    d.list_dist = reinterpret_cast<float*>(w + K.o_list_dist);
+    d.cnt = reinterpret_cast<int32_t*>(w + K.o_cnt);
+    d.gcnt = reinterpret_cast<int32_t*>(w + K.o_gcnt);
+    d.prefix = reinterpret_cast<int32_t*>(w + K.o_prefix);
+    d.item_query = reinterpret_cast<int32_t*>(w + K.o_items);
+    d.counters = reinterpret_cast<int32_t*>(w + K.o_counters);
+    d.key = reinterpret_cast<unsigned long long*>(w + K.o_key);
+    d.stats = reinterpret_cast<unsigned long long*>(w + K.o_stats);
+
+    RaggedKnnArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.Q = d.Q;
+    r.q_off = reinterpret_cast<const int64_t*>(w + K.o_qoff);
+    r.q_len = reinterpret_cast<const int32_t*>(w + K.o_qlen);
+    r.C = d.C;
+    r.c_off = c_off;
+    r.c_len = c_len;
+    r.nq = K.nq; r.nc = K.nc; r.D = K.D; r.maxm = K.maxm; r.maxn = K.maxn;
+    r.window = K.win.window; r.num = K.win.frac_num; r.den = K.win.frac_den;
+    r.tab = K.plain ? nullptr : reinterpret_cast<float*>(w + K.o_tab);
+    r.t_off = reinterpret_cast<const int64_t*>(w + K.o_toff);
+    r.lb = d.lb;
+    r.prefix = d.prefix; r.item_query = d.item_query; r.counter = d.counters + 1;
+    r.key = d.key; r.stats = d.stats;
+    r.seeds = d.seeds; r.seed_dist = d.seed_dist; r.R = K.R; r.list_cnt = d.cnt;
+    r.nn_idx = nn_idx; r.nn_dist = nn_dist;
+
+    hipEvent_t ev[8];
+    const bool timed = stats != nullptr;
+    if (timed)
+        for (auto& x : ev) (void)hipEventCreate(&x);
+    auto mark = [&](int i) { if (timed) (void)hipEventRecord(ev[i], s); };
+    hipError_t e;
+    // per-query metadata (pageable host memory: the copies are staged before the calls return)
+    if ((e = hipMemcpyAsync(w + K.o_qoff, K.q_off.data(), K.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(w + K.o_qlen, K.q_len.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(w + K.o_toff, K.t_off.data(), K.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "query metadata upload");
+    mark(0);
+    if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
+    if (!K.plain && (e = launch_rq_tables(r, s)) != hipSuccess) return hip_fail(e, "query tables");
+    mark(1);
+    if (!K.plain && (e = launch_rlb_mv(r, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+    mark(2);
+    const size_t lds = rknn_dtw_lds_bytes(K.maxn, K.D);
+    KnnDtwArgs scan;
+    std::memset(&scan, 0, sizeof scan);
+    scan.nq = K.nq; scan.P = 1; scan.prefix = d.prefix; scan.item_query = d.item_query; scan.counter = r.counter;
+    if (!K.plain && K.R > 0) {
+        if ((e = launch_topr(d, s)) != hipSuccess) return hip_fail(e, "seed selection");
+        scan.cnt = d.cnt; scan.cnt_uniform = K.R;
+        if ((e = launch_chunk_scan(scan, s)) != hipSuccess) return hip_fail(e, "seed scan");
+        RaggedKnnArgs a = r;
+        a.list = reinterpret_cast<const uint32_t*>(d.seeds);
+        a.list_dist = d.seed_dist;
+        a.cap = K.R;
+        a.abandon = 0;
+        if ((e = launch_rknn_dtw(a, persistent_blocks(lds, (int64_t)K.nq * K.R), s)) != hipSuccess)
+            return hip_fail(e, "seed dtw");
+    }
+    mark(3);
+    const double keep = 1.0 - (double)p->prune_margin;
+    if ((e = launch_compact(d, K.plain ? 0.0 : keep, 1e300, 0, s)) != hipSuccess) return hip_fail(e, "compaction");
+    mark(4);
+    {
+        scan.cnt = d.cnt; scan.cnt_uniform = 0;
+        if ((e = launch_chunk_scan(scan, s)) != hipSuccess) return hip_fail(e, "dtw scan");
+        mark(5);
+        RaggedKnnArgs a = r;
+        a.list = d.list;
+        a.list_dist = d.list_dist;
+        a.cap = K.nc;
+        a.abandon = K.abandon ? 1 : 0;
+        if ((e = launch_rknn_dtw(a, persistent_blocks(lds, (int64_t)K.nq * K.nc), s)) != hipSuccess)
+            return hip_fail(e, "dtw");
+    }
+    mark(6);
+    {
+        RaggedKnnArgs a = r;
+        a.list = d.list;
+        a.list_dist = d.list_dist;
+        a.cap = K.nc;
+        if ((e = launch_rknn_finalize(a, s)) != hipSuccess) return hip_fail(e, "finalize");
+    }
+    mark(7);
+    if (timed) {
+        unsigned long long h[kNumStats];
+        e = hipMemcpyAsync(h, d.stats, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "stats readback");
+        std::memset(stats, 0, sizeof *stats);
+        stats->pairs = (uint64_t)K.nq * K.nc;
+        stats->pruned_mv = h[kStPrunedMv];
+        stats->dtw_started = h[kStDtwStarted];
+        stats->dtw_abandoned = h[kStDtwAbandoned];
+        stats->dtw_completed = h[kStDtwStarted] - h[kStDtwAbandoned];
+        stats->cells = h[kStCells];
+        stats->rescored = h[kStRescored];
+        for (int i = 0; i < 7; ++i) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            stats->stage_ms[i] = ms;
+        }
+        float tot = 0.0f;
+        (void)hipEventElapsedTime(&tot, ev[0], ev[7]);
+        stats->stage_ms[7] = tot;
+        for (auto& x : ev) (void)hipEventDestroy(x);
+    }
+    return ok();
+}
+
 }  // namespace tcdtw
 
 using namespace tcdtw;
@@ -386,6 +598,11 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
 
 size_t tc_dtw_knn_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
                                   const tc_dtw_knn_params* p) {
+    if (is_ragged_search(ix, queries)) {
+        RaggedPlan R;
+        HostSet Qr;
+        return make_ragged_plan(ix, queries, p, R, Qr) == TC_DTW_OK ? R.bytes : 0;
+    }
     KnnPlan K;
     HostSet Q;
     if (make_knn_plan(ix, queries, p, K, Q) != TC_DTW_OK) return 0;
@@ -395,6 +612,8 @@ size_t tc_dtw_knn_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* qu
 tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, const tc_dtw_knn_params* p,
                          int32_t* nn_idx, float* nn_dist, tc_dtw_knn_stats* stats, void* ws,
                          size_t ws_bytes, tc_dtw_stream stream) {
+    if (is_ragged_search(ix, queries))
+        return knn_ragged(ix, queries, p, nn_idx, nn_dist, stats, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
     KnnPlan K;
     HostSet Qs;
     tc_dtw_status st = make_knn_plan(ix, queries, p, K, Qs);
@@ -402,6 +621,8 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
     if (K.ti && 2 * K.W + 1 > 128)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
+    if (K.ti && ti_lds_bytes(K.m, K.n, K.D) > 163840)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI stages a pair in LDS: series too long");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -449,7 +670,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     if (K.gate) {
         // Sec. 6: advanced bounds only for gated pairs; LB_PC first, then LB_TI
         if ((e = launch_copy_i32(d.cnt, x.cntmv, K.nq, s)) != hipSuccess) return hip_fail(e, "snapshot");
-        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * ((K.cap + 63) / 64));
+        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * K.cap);
         RouteArgs r;
         std::memset(&r, 0, sizeof r);
         r.nq = K.nq; r.nc = K.nc; r.cap = K.cap;
@@ -459,7 +680,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
             PcArgs a = pc_args(K, d, x, ix, p);
             a.in_list = d.glist; a.in_cnt = d.gcnt; a.in_uniform = 0;
             a.out_lb = x.glb; a.key = d.key;
-            if ((e = launch_list_items(d.gcnt, 0, K.nq, 64, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+            if ((e = launch_list_items(d.gcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
                 return hip_fail(e, "pc items");
             if ((e = launch_lb_pc(a, pc_blocks, s)) != hipSuccess) return hip_fail(e, "lb_pc");
             r.in_list = d.glist; r.in_cnt = d.gcnt; r.lb_prev = nullptr; r.lb_new = x.glb;
@@ -479,7 +700,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
             a.in_list = x.tlist; a.out_lb = x.tout; a.lb_in = x.tlb; a.key = d.key;
             if ((e = launch_list_items(x.tcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
                 return hip_fail(e, "ti items");
-            const int ti_blocks = persistent_blocks((size_t)K.m * 4 + 16, (int64_t)K.nq * K.cap);
+            const int ti_blocks = persistent_blocks(ti_lds_bytes(K.m, K.n, K.D), (int64_t)K.nq * K.cap);
             if ((e = launch_lb_ti(a, ti_blocks, s)) != hipSuccess) return hip_fail(e, "lb_ti");
             RouteArgs r2 = r;
             r2.in_list = x.tlist; r2.in_cnt = x.tcnt; r2.lb_prev = x.tlb; r2.lb_new = x.tout;
@@ -544,6 +765,14 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
 
 size_t tc_dtw_lower_bounds_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
                                            const tc_dtw_knn_params* p, uint32_t kind) {
+    if (is_ragged_search(ix, queries)) {
+        if (kind != TC_DTW_LB_MV) return 0;
+        RaggedPlan R;
+        HostSet Qr;
+        tc_dtw_knn_params pm = p ? *p : tc_dtw_knn_params{};
+        pm.bounds = TC_DTW_LB_MV;
+        return p && make_ragged_plan(ix, queries, &pm, R, Qr) == TC_DTW_OK ? R.bytes : 0;
+    }
     KnnPlan K;
     HostSet Q;
     if (make_knn_plan(ix, queries, p, K, Q) != TC_DTW_OK) return 0;
@@ -554,6 +783,44 @@ size_t tc_dtw_lower_bounds_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_
 tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* queries,
                                   const tc_dtw_knn_params* p, uint32_t kind, float* lb, void* ws,
                                   size_t ws_bytes, tc_dtw_stream stream) {
+    if (is_ragged_search(ix, queries)) {
+        if (kind != TC_DTW_LB_MV)
+            return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI need uniform query and candidate lengths");
+        if (!p) return fail(TC_DTW_ERR_INVALID, "null params");
+        tc_dtw_knn_params pm = *p;
+        pm.bounds = TC_DTW_LB_MV;
+        RaggedPlan R;
+        HostSet Qr;
+        tc_dtw_status st = make_ragged_plan(ix, queries, &pm, R, Qr);
+        if (st != TC_DTW_OK) return st;
+        if (!lb) return fail(TC_DTW_ERR_INVALID, "null lb pointer");
+        if (!ws || ws_bytes < R.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_lower_bounds_workspace_bytes()");
+        if ((st = check_device()) != TC_DTW_OK) return st;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        char* w = static_cast<char*>(ws);
+        char* base = static_cast<char*>(ix->buf);
+        RaggedKnnArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.Q = Qr.data;
+        a.q_off = reinterpret_cast<const int64_t*>(w + R.o_qoff);
+        a.q_len = reinterpret_cast<const int32_t*>(w + R.o_qlen);
+        a.C = reinterpret_cast<const float*>(base + ix->off_series);
+        a.c_off = reinterpret_cast<const int64_t*>(base + ix->off_meta);
+        a.c_len = reinterpret_cast<const int32_t*>(a.c_off + 2 * (int64_t)ix->count);
+        a.nq = R.nq; a.nc = R.nc; a.D = R.D; a.maxm = R.maxm; a.maxn = R.maxn;
+        a.window = R.win.window; a.num = R.win.frac_num; a.den = R.win.frac_den;
+        a.tab = reinterpret_cast<float*>(w + R.o_tab);
+        a.t_off = reinterpret_cast<const int64_t*>(w + R.o_toff);
+        a.lb = lb;
+        hipError_t e;
+        if ((e = hipMemcpyAsync(w + R.o_qoff, R.q_off.data(), R.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(w + R.o_qlen, R.q_len.data(), R.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(w + R.o_toff, R.t_off.data(), R.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "query metadata upload");
+        if ((e = launch_rq_tables(a, s)) != hipSuccess) return hip_fail(e, "query tables");
+        if ((e = launch_rlb_mv(a, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+        return ok();
+    }
     KnnPlan K;
     HostSet Qs;
     tc_dtw_status st = make_knn_plan(ix, queries, p, K, Qs);
@@ -563,6 +830,8 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         return fail(TC_DTW_ERR_INVALID, "kind must be one of TC_DTW_LB_MV, TC_DTW_LB_PC, TC_DTW_LB_TI");
     if (kind == TC_DTW_LB_TI && 2 * K.W + 1 > 128)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
+    if (kind == TC_DTW_LB_TI && ti_lds_bytes(K.m, K.n, K.D) > 163840)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI stages a pair in LDS: series too long");
     if (K.plain) return fail(TC_DTW_ERR_INVALID, "params.bounds must include TC_DTW_LB_MV");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_lower_bounds_workspace_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
@@ -577,9 +846,9 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         PcArgs a = pc_args(K, d, x, ix, p);
         if ((e = launch_pc_boxes(a, s)) != hipSuccess) return hip_fail(e, "boxes");
         a.in_list = nullptr; a.in_uniform = K.nc; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
-        if ((e = launch_list_items(nullptr, K.nc, K.nq, 64, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+        if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
             return hip_fail(e, "pc items");
-        if ((e = launch_lb_pc(a, persistent_blocks(0, (int64_t)K.nq * ((K.nc + 63) / 64)), s)) != hipSuccess)
+        if ((e = launch_lb_pc(a, persistent_blocks(0, (int64_t)K.nq * K.nc), s)) != hipSuccess)
             return hip_fail(e, "lb_pc");
     } else {
         if ((e = launch_query_steps(d.Q, K.nq, K.m, K.D, x.qstep, s)) != hipSuccess) return hip_fail(e, "query steps");
@@ -587,7 +856,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         a.in_list = nullptr; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
         if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
             return hip_fail(e, "ti items");
-        if ((e = launch_lb_ti(a, persistent_blocks((size_t)K.m * 4 + 16, (int64_t)K.nq * K.nc), s)) != hipSuccess)
+        if ((e = launch_lb_ti(a, persistent_blocks(ti_lds_bytes(K.m, K.n, K.D), (int64_t)K.nq * K.nc), s)) != hipSuccess)
             return hip_fail(e, "lb_ti");
     }
     return ok();

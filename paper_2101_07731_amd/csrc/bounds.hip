@@ -151,12 +151,13 @@ __global__ __launch_bounds__(64) void k_pc_boxes(PcArgs a) {
 }
 
 // ------------------------------------------------------------------- K5
-// LB_PC of a chunk of up to 64 listed candidates of one query (lanes over
-// candidates; the boxes of the current group are wave-uniform scalar loads):
-// per candidate point the smallest squared distance to a box of its group,
-// summed over points (Sec. 5, Fig. 4(a)).  In search mode a pair is only
-// evaluated when its LB_MV exceeds e^2 * bsf, and a chunk stops as soon as
-// every lane's partial sum already proves its pair prunable.
+// LB_PC of one listed pair per wave (Sec. 5, Fig. 4(a)): lanes over the
+// candidate's points (consecutive points, so the loads are coalesced); for
+// each point the smallest squared distance to a box of its group (the
+// query's boxes are a few KB, read through the caches), summed over points.
+// In search mode a pair is only evaluated when its LB_MV exceeds e^2 bsf,
+// and the evaluation stops once the partial sum already proves the pair
+// prunable.
 template <int DMAX>
 __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
     const int lane = threadIdx.x;
@@ -165,33 +166,30 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
     for (;;) {
         const int item = wave_next_item(a.counter);
         if (item >= a.prefix[a.nq]) break;
-        const int q = a.item_query[item];
-        const int e = (item - a.prefix[q]) * kWave + lane;
-        const int cnt = a.in_uniform > 0 ? a.in_uniform : a.in_cnt[q];
-        bool live = e < cnt;
-        const int ref = live ? (a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e) : 0;
+        const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
+        const int e = item - __builtin_amdgcn_readfirstlane(a.prefix[q]);
+        const int ref = a.in_list ? __builtin_amdgcn_readfirstlane((int)a.in_list[(int64_t)q * a.cap + e]) : e;
         float bsf = __builtin_inff();
         if (a.key) {
             bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
             // selective deployment: only pairs with LB_MV > e^2 bsf
-            const float mv = live ? a.lb_mv[(int64_t)q * a.nc + ref] : 0.0f;
-            if (live && !((double)mv > a.e2 * (double)bsf)) {
-                a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
-                live = false;
+            const float mv = a.lb_mv[(int64_t)q * a.nc + ref];
+            if (wave_uniform(!((double)mv > a.e2 * (double)bsf))) {
+                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
+                continue;
             }
         }
-        if (__ballot(live) == 0ull) continue;
         const float* c = a.C + (int64_t)ref * n * D;
         const float* bxq = a.boxes + (int64_t)q * a.ngroups * K * D * 2;
         const int32_t* nbq = a.nbox + (int64_t)q * a.ngroups;
         const double stop = a.key ? (double)bsf / a.keep : __builtin_inf();
         float acc = 0.0f;
-        for (int j0 = 0; j0 < n; j0 += w) {
-            const int g = j0 / w;
-            const int nb = nbq[g];
-            const float* bg = bxq + (int64_t)g * K * D * 2;
-            const int j1 = min(n, j0 + w);
-            for (int j = j0; j < j1; ++j) {
+        for (int j0 = 0; j0 < n; j0 += kWave) {
+            const int j = j0 + lane;
+            if (j < n) {
+                const int g = j / w;
+                const int nb = nbq[g];
+                const float* bg = bxq + (int64_t)g * K * D * 2;
                 float cv[DMAX];
 #pragma unroll
                 for (int p = 0; p < DMAX; ++p) cv[p] = p < D ? c[(int64_t)j * D + p] : 0.0f;
@@ -210,9 +208,16 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
                 }
                 acc += best;
             }
-            if (a.key && __ballot(live && !((double)acc * defl > stop)) == 0ull) break;
+            if (a.key && j0 + kWave < n) {
+                float tot = acc;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
+                if (wave_uniform((double)tot * defl > stop)) break;
+            }
         }
-        if (live) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
     }
 }
 
@@ -229,9 +234,13 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
 // neighbour with gamma_j = e(c_{j-1}, c_j) from the index.
 template <int SLOTS>
 __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
-    float* top = reinterpret_cast<float*>(lds4);       // [m] exact top distances (TOP)
     const int lane = threadIdx.x;
     const int m = a.m, n = a.n, D = a.D, W = a.W, P = a.P;
+    // LDS, staged per pair so that the row loop never waits on global memory:
+    float* top = reinterpret_cast<float*>(lds4);       // [m] exact top distances (TOP)
+    float* dqs = top + m;                              // [m] query steps
+    float* gcs = dqs + m;                              // [n] candidate steps
+    float* cst = gcs + n;                              // [n][D] candidate points
     const int KB = 2 * W + 1;                          // band offsets 0 .. 2W
     const float INF = __builtin_inff();
     const double u = 1.0 / 16777216.0;
@@ -258,9 +267,10 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         }
         const float* qs = a.Q + (int64_t)q * m * D;
         const float* cs = a.C + (int64_t)ref * n * D;
-        const float* dq = a.qstep + (int64_t)q * m;
-        const float* gc = a.gamma + (int64_t)ref * n;
         __syncthreads();
+        for (int i = lane; i < m; i += kWave) dqs[i] = a.qstep[(int64_t)q * m + i];
+        for (int j = lane; j < n; j += kWave) gcs[j] = a.gamma[(int64_t)ref * n + j];
+        for (int t = lane; t < n * D; t += kWave) cst[t] = cs[t];
         if (a.top) {
             for (int i = lane; i < m; i += kWave) {
                 const int j = i + W;
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         float acc = 0.0f;
         for (int i = 0; i < m; ++i) {
             const bool exact_row = (i == 0) || (P > 0 && i % P == 0);
-            const float di = dq[i];
+            const float di = dqs[i];
             // row i-1 values of the same column (offset k+1)
             float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
             if (SLOTS == 1) {
@@ -311,7 +321,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                     if (exact_row) {
                         float sacc = 0.0f;
                         for (int p = 0; p < D; ++p) {
-                            const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
+                            const float t = qs[(int64_t)i * D + p] - cst[j * D + p];
                             sacc = __builtin_fmaf(t, t, sacc);
                         }
                         lo = hi = __builtin_sqrtf(sacc);
@@ -336,13 +346,13 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 if (lane == (kt & 63) && j >= 0 && j < n) {
                     float lo, hi;
                     if (kt >= 1 && j >= 1) {
-                        const float gj = gc[j];
+                        const float gj = gcs[j];
                         lo = __builtin_fmaxf(Ll - gj, gj - Ul);          // Eq. 9
                         hi = Ul + gj;                                    // Eq. 10
                     } else {
                         float sacc = 0.0f;
                         for (int p = 0; p < D; ++p) {
-                            const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
+                            const float t = qs[(int64_t)i * D + p] - cst[j * D + p];
                             sacc = __builtin_fmaf(t, t, sacc);
                         }
                         lo = hi = __builtin_sqrtf(sacc);
@@ -445,8 +455,10 @@ hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
     return hipGetLastError();
 }
 
+size_t ti_lds_bytes(int m, int n, int D) { return ((size_t)2 * m + n + (size_t)n * D) * 4 + 16; }
+
 hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s) {
-    const size_t lds = (size_t)a.m * 4 + 16;
+    const size_t lds = ti_lds_bytes(a.m, a.n, a.D);
     if (2 * a.W + 1 <= 64) hipLaunchKernelGGL(k_lb_ti<1>, dim3(nblocks), dim3(64), lds, s, a);
     else hipLaunchKernelGGL(k_lb_ti<2>, dim3(nblocks), dim3(64), lds, s, a);
     return hipGetLastError();

@@ -188,6 +188,43 @@ struct KnnFinalArgs {
     unsigned long long* stats;
 };
 
+// 1-NN over a bank of uneven lengths (knn_ragged.hip).
+struct RaggedKnnArgs {
+    const float* Q;
+    const int64_t* q_off;      // [nq] float offsets of the queries
+    const int32_t* q_len;      // [nq]
+    const float* C;            // index series
+    const int64_t* c_off;      // [nc] float offsets inside the index series
+    const int32_t* c_len;      // [nc]
+    int32_t nq, nc, D, maxm, maxn;
+    int32_t window, num, den;  // window specification (per pair W_eff)
+    float* tab;                // query sparse tables
+    const int64_t* t_off;      // [nq] float offsets of each query's tables
+    float* lb;                 // [nq][nc]
+    const uint32_t* list;      // DTW list (seeds or survivors) [nq][cap]
+    float* list_dist;
+    int32_t cap;
+    const int32_t* prefix;
+    const int32_t* item_query;
+    int32_t* counter;
+    unsigned long long* key;
+    unsigned long long* stats;
+    int32_t abandon;
+    // finalize
+    const int32_t* seeds;
+    const float* seed_dist;
+    int32_t R;
+    const int32_t* list_cnt;
+    int32_t* nn_idx;
+    float* nn_dist;
+};
+hipError_t launch_rq_tables(const RaggedKnnArgs& a, hipStream_t s);
+hipError_t launch_rlb_mv(const RaggedKnnArgs& a, hipStream_t s);
+hipError_t launch_rknn_dtw(const RaggedKnnArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_rknn_finalize(const RaggedKnnArgs& a, hipStream_t s);
+size_t rknn_dtw_lds_bytes(int maxn, int D);
+size_t rknn_final_lds_bytes(int maxn, int D);
+
 hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s);
 hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s);
 hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s);
@@ -266,6 +303,7 @@ size_t pc_boxes_lds_bytes(int max_pts, int K, int D);
 hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s);
 hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s);
+size_t ti_lds_bytes(int m, int n, int D);
 hipError_t launch_route(const RouteArgs& a, int max_in, hipStream_t s);
 hipError_t launch_list_items(const int32_t* cnt, int cnt_uniform, int nq, int per, int32_t* prefix,
                              int32_t* item_query, int32_t* counter, hipStream_t s);
