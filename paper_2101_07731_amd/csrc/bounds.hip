@@ -288,12 +288,20 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         }
         __syncthreads();
         float L[SLOTS], U[SLOTS], cm[SLOTS];
+        int jrow[SLOTS];     // column of this lane's cell in the current row
+        bool ink[SLOTS];     // the lane holds a band offset (k <= 2W)
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) { L[s] = -INF; U[s] = INF; cm[s] = INF; }
+        for (int s = 0; s < SLOTS; ++s) {
+            L[s] = -INF; U[s] = INF; cm[s] = INF;
+            jrow[s] = lane + 64 * s - W;
+            ink[s] = lane + 64 * s < KB;
+        }
         float acc = 0.0f;
+        int since = 0;       // rows since the last exact row (exact rows: i = 0 and i mod P = 0)
         for (int i = 0; i < m; ++i) {
-            const bool exact_row = (i == 0) || (P > 0 && i % P == 0);
+            const bool exact_row = (i == 0) || (P > 0 && since == 0);
             const float di = dqs[i];
+            const float topv = a.top ? top[i] : INF;
             // row i-1 values of the same column (offset k+1)
             float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
             if (SLOTS == 1) {
@@ -311,29 +319,29 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
             // the column at offset 0 of row i-1 is not in row i's band: its minimum is final
             const float leaving = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cm[0])));
             if (i > 0 && leaving < INF) acc += leaving * leaving;
+            // Lanes that are not cells (columns outside [0, n), offsets past 2W) carry values
+            // that only ever reach other non-cells (the cell below keeps the column), so every
+            // lane evaluates the same arithmetic and only the column minimum is masked.
+            if (exact_row) {
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const int k = lane + 64 * s;
-                const int j = i - W + k;
-                const bool cell = (k < KB) && j >= 0 && j < n;
-                float lo = -INF, hi = INF;
-                if (cell) {
-                    if (exact_row) {
-                        float sacc = 0.0f;
-                        for (int p = 0; p < D; ++p) {
-                            const float t = qs[(int64_t)i * D + p] - cst[j * D + p];
-                            sacc = __builtin_fmaf(t, t, sacc);
-                        }
-                        lo = hi = __builtin_sqrtf(sacc);
-                    } else if (k < kt) {
-                        lo = __builtin_fmaxf(Ln[s] - di, di - Un[s]);   // Eq. 7
-                        hi = Un[s] + di;                                 // Eq. 8
-                    } else if (a.top) {
-                        lo = hi = top[i];
+                for (int s = 0; s < SLOTS; ++s) {
+                    const int jc = min(max(jrow[s], 0), n - 1);
+                    float sacc = 0.0f;
+                    for (int p = 0; p < D; ++p) {
+                        const float t = qs[(int64_t)i * D + p] - cst[jc * D + p];
+                        sacc = __builtin_fmaf(t, t, sacc);
                     }
+                    L[s] = U[s] = __builtin_sqrtf(sacc);
                 }
-                L[s] = lo;
-                U[s] = hi;
+            } else {
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    const bool istop = lane + 64 * s == kt;
+                    const float lo = __builtin_fmaxf(Ln[s] - di, di - Un[s]);   // Eq. 7
+                    const float hi = Un[s] + di;                                 // Eq. 8
+                    L[s] = (istop && a.top) ? topv : lo;
+                    U[s] = (istop && a.top) ? topv : hi;
+                }
             }
             if (!exact_row && !a.top) {
                 // top cell from (i, j-1), Eqs. 9-10 (exact when it has no left neighbour)
@@ -364,13 +372,13 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
             }
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
-                const int k = lane + 64 * s;
-                const int j = i - W + k;
-                const bool cell = (k < KB) && j >= 0 && j < n;
+                const bool cell = ink[s] && (unsigned)jrow[s] < (unsigned)n;
                 // a safe lower bound of the Euclidean point distance, clamped at 0
                 const float safe = __builtin_fmaxf(__builtin_fmaf(-slack, U[s], L[s]), 0.0f);
                 cm[s] = __builtin_fminf(cmn[s], cell ? safe : INF);
+                jrow[s] += 1;
             }
+            since = (since + 1 == P) ? 0 : since + 1;
         }
         // columns still in the band after the last row
         float tail = 0.0f;
