@@ -298,6 +298,10 @@ def main():
                                "pruned_pc": stf["pruned_pc"], "pruned_ti": stf["pruned_ti"],
                                "pct_dtw_pruned": round(100.0 * (1 - stf["dtw_started"] / stf["pairs"]), 3),
                                "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3)}
+        # setup-stage choice of bounds and triggers on a sample of 100 queries (Sec. 6)
+        best, times = search.tune_cascade(ix, Qd[:100], frac=frac)
+        out["cascade_setup"] = {"sample_queries": 100, "best": "%s e_pc=%s e_ti=%s" % best,
+                                "ms_per_choice": {"%s e_pc=%s e_ti=%s" % k: round(v, 3) for k, v in times.items()}}
         out["batched_pairs"] = extra_batched_pairs(dev)
         out["dtw_loss"] = extra_fwd_bwd(dev)
         out["long_knn"] = extra_long_knn(dev)

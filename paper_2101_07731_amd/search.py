@@ -90,3 +90,45 @@ def knn_workspace_bytes(index, queries, **kw):
     Q = SeriesSet(queries)
     p = params(**kw)
     return L.lib().tc_dtw_knn_workspace_bytes(C.byref(index.ix), C.byref(Q.batch), C.byref(p))
+
+
+# Bound combinations and triggering thresholds tried by tune_cascade: the
+# grids the paper evaluates (e_TI in {0.05, 0.1, 0.2}, e_PC in {0.1, 0.5}).
+CASCADE_CHOICES = (
+    ("mv", None, None),
+    ("mv+pc", 0.1, None), ("mv+pc", 0.5, None),
+    ("mv+ti", None, 0.05), ("mv+ti", None, 0.1), ("mv+ti", None, 0.2),
+    ("mv+pc+ti", 0.1, 0.1), ("mv+pc+ti", 0.5, 0.2),
+)
+
+
+def tune_cascade(index, queries, reps=2, choices=CASCADE_CHOICES, **kw):
+    """Setup-stage choice of the bounds and their triggering thresholds
+    (Sec. 6: e is chosen per dataset during setup): times the search of
+    `queries` (a sample) for every choice and returns (best, {choice: ms}).
+    Every choice returns the same neighbours; only the time differs.
+    Choices the library cannot run for these shapes (LB_TI beyond W_eff 63,
+    LB_PC / LB_TI on uneven lengths) are skipped."""
+    times = {}
+    for bounds, e_pc, e_ti in choices:
+        extra = dict(kw)
+        if e_pc is not None:
+            extra["trigger_pc"] = e_pc
+        if e_ti is not None:
+            extra["trigger_ti"] = e_ti
+        try:
+            knn(index, queries, bounds=bounds, **extra)
+        except L.TcDtwError as err:
+            if err.status == L.ERR_UNSUPPORTED:
+                continue
+            raise
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            knn(index, queries, bounds=bounds, **extra)
+        e1.record()
+        torch.cuda.synchronize()
+        times[(bounds, e_pc, e_ti)] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    return best, times

@@ -207,3 +207,20 @@ def test_full_size_sampled_full_cascade(dev):
     np.testing.assert_array_equal(idx[sample], ri)
     np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
     assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == 1000 * 10000
+
+
+def test_tune_cascade_picks_a_runnable_choice(dev):
+    """Setup-stage choice of bounds and triggers; LB_TI choices are skipped when W_eff > 63."""
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.cascade_knn(nq=20, nc=400, T=96, D=8, seed=31)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    best, times = search.tune_cascade(ix, Qd, reps=1, frac=(1, 10))
+    assert best in times and len(times) == len(search.CASCADE_CHOICES)
+    idx, dist = search.knn(ix, Qd, frac=(1, 10), bounds=best[0],
+                           **{k: v for k, v in (("trigger_pc", best[1]), ("trigger_ti", best[2])) if v is not None})
+    check_against_oracle(idx.cpu().numpy(), dist.cpu().numpy(), Q, Cs, 1, 10)
+    Ql, Cl = synth.long_knn(nq=3, nc=20, T=300, D=4)
+    ixl = search.Index(torch.from_numpy(Cl).to(dev))
+    _, tl = search.tune_cascade(ixl, torch.from_numpy(Ql).to(dev), reps=1, frac=(1, 2))   # W = 150
+    assert all("ti" not in k[0] for k in tl) and ("mv", None, None) in tl
