@@ -97,7 +97,15 @@ __global__ __launch_bounds__(256) void k_rq_tables(RaggedKnnArgs a) {
 // One wave per (query, candidate); blocks of 4 waves over candidates,
 // grid.y over queries.  Rounding as in the uniform LB_MV: the sum of
 // N = n D + 6 float32 terms (each lane's partial sum, then 6 shuffle
-// levels) is scaled by 1 - (N + 3) u and rounded down.
+// levels) is scaled by 1 - (N + 3) u and rounded down.  With D a multiple
+// of 4 (VEC) the table rows and the candidate point are read as float4
+// chunks (every row offset is then a multiple of 4 floats), NCH chunks
+// unrolled so that all loads of a point are in flight together.
+__device__ __forceinline__ float mv_term(float v, float U, float Lw) {
+    return v > U ? v - U : (v < Lw ? Lw - v : 0.0f);
+}
+
+template <int NCH, bool VEC>
 __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
     const int q = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -110,6 +118,7 @@ __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
     const float* mx = a.tab + a.t_off[q];
     const float* mn = mx + (int64_t)L * md;
     const float* cs = a.C + a.c_off[c];
+    const int D4 = D >> 2;
     float acc = 0.0f;
     for (int j = lane; j < n; j += kWave) {
         const int lo = max(0, j - W), hi = min(m - 1, j + W);
@@ -117,12 +126,39 @@ __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
         const int h2 = hi - (1 << k) + 1;
         const float* xk = mx + k * md;
         const float* nk = mn + k * md;
-        for (int p = 0; p < D; ++p) {
-            const float U = __builtin_fmaxf(xk[(int64_t)lo * D + p], xk[(int64_t)h2 * D + p]);
-            const float Lw = __builtin_fminf(nk[(int64_t)lo * D + p], nk[(int64_t)h2 * D + p]);
-            const float v = cs[(int64_t)j * D + p];
-            const float d = v > U ? v - U : (v < Lw ? Lw - v : 0.0f);
-            acc = __builtin_fmaf(d, d, acc);
+        if (VEC) {
+            float4 x1[NCH], x2[NCH], n1[NCH], n2[NCH], cv[NCH];
+#pragma unroll
+            for (int t = 0; t < NCH; ++t) {
+                if (t < D4) {
+                    x1[t] = *reinterpret_cast<const float4*>(xk + (int64_t)lo * D + 4 * t);
+                    x2[t] = *reinterpret_cast<const float4*>(xk + (int64_t)h2 * D + 4 * t);
+                    n1[t] = *reinterpret_cast<const float4*>(nk + (int64_t)lo * D + 4 * t);
+                    n2[t] = *reinterpret_cast<const float4*>(nk + (int64_t)h2 * D + 4 * t);
+                    cv[t] = *reinterpret_cast<const float4*>(cs + (int64_t)j * D + 4 * t);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NCH; ++t) {
+                if (t < D4) {
+                    float d;
+                    d = mv_term(cv[t].x, __builtin_fmaxf(x1[t].x, x2[t].x), __builtin_fminf(n1[t].x, n2[t].x));
+                    acc = __builtin_fmaf(d, d, acc);
+                    d = mv_term(cv[t].y, __builtin_fmaxf(x1[t].y, x2[t].y), __builtin_fminf(n1[t].y, n2[t].y));
+                    acc = __builtin_fmaf(d, d, acc);
+                    d = mv_term(cv[t].z, __builtin_fmaxf(x1[t].z, x2[t].z), __builtin_fminf(n1[t].z, n2[t].z));
+                    acc = __builtin_fmaf(d, d, acc);
+                    d = mv_term(cv[t].w, __builtin_fmaxf(x1[t].w, x2[t].w), __builtin_fminf(n1[t].w, n2[t].w));
+                    acc = __builtin_fmaf(d, d, acc);
+                }
+            }
+        } else {
+            for (int p = 0; p < D; ++p) {
+                const float U = __builtin_fmaxf(xk[(int64_t)lo * D + p], xk[(int64_t)h2 * D + p]);
+                const float Lw = __builtin_fminf(nk[(int64_t)lo * D + p], nk[(int64_t)h2 * D + p]);
+                const float d = mv_term(cs[(int64_t)j * D + p], U, Lw);
+                acc = __builtin_fmaf(d, d, acc);
+            }
         }
     }
 #pragma unroll
@@ -256,7 +292,21 @@ hipError_t launch_rq_tables(const RaggedKnnArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_rlb_mv(const RaggedKnnArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_rlb_mv, dim3((a.nc + 3) / 4, a.nq), dim3(256), 0, s, a);
+    const dim3 grid((a.nc + 3) / 4, a.nq);
+    if (a.D % 4 != 0) {
+        hipLaunchKernelGGL((k_rlb_mv<1, false>), grid, dim3(256), 0, s, a);
+    } else {
+        switch (nch_pad(a.D)) {
+            case 1: hipLaunchKernelGGL((k_rlb_mv<1, true>), grid, dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_rlb_mv<2, true>), grid, dim3(256), 0, s, a); break;
+            case 3: hipLaunchKernelGGL((k_rlb_mv<3, true>), grid, dim3(256), 0, s, a); break;
+            case 4: hipLaunchKernelGGL((k_rlb_mv<4, true>), grid, dim3(256), 0, s, a); break;
+            case 6: hipLaunchKernelGGL((k_rlb_mv<6, true>), grid, dim3(256), 0, s, a); break;
+            case 8: hipLaunchKernelGGL((k_rlb_mv<8, true>), grid, dim3(256), 0, s, a); break;
+            case 12: hipLaunchKernelGGL((k_rlb_mv<12, true>), grid, dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_rlb_mv<16, true>), grid, dim3(256), 0, s, a); break;
+        }
+    }
     return hipGetLastError();
 }
 

@@ -70,10 +70,10 @@ def test_uniform_queries_against_ragged_bank(dev):
     np.testing.assert_array_equal(dist, rd.astype(np.float32))
 
 
-def test_ragged_lb_mv_sound_and_tight(dev):
+@pytest.mark.parametrize("D", [5, 8])      # scalar and float4 paths
+def test_ragged_lb_mv_sound_and_tight(dev, D):
     from paper_2101_07731_amd import search
     rng = np.random.default_rng(8)
-    D = 5
     Cs = bank(rng, 40, 3, 150, D)
     Q = bank(rng, 7, 3, 150, D)
     ix = search.Index([torch.from_numpy(c).to(dev) for c in Cs])
