@@ -348,7 +348,7 @@ __global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
 constexpr int kCheckRounds = 32;
 
 template <int NCH, bool WODD, int RS>
-__global__ __launch_bounds__(64) void k_knn_dtw_ring(KnnDtwArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 ? 4 : 1))) void k_knn_dtw_ring(KnnDtwArgs a) {
     constexpr int RF = RS / 4, MIR = 8, STR = RS + MIR;
     constexpr int MAXPASS = NCH <= 4 ? 3 : 1;
     const int lane = threadIdx.x;
