@@ -6,7 +6,7 @@ enabled, DTW of the survivors with early abandoning, float64 re-scoring of
 near-tie finalists).  Inputs and the candidate index are resident in HBM
 before the timed region; the index build is timed separately.
 
-Prints one JSON line ("Measurement") with:
+Prints one JSON line with:
   value       queries/s of the whole batch,
   roofline    the DTW kernel (the step's dominant kernel) as useful band
               cells/s against the VALU bound of (2D + 2) lane-operations per
@@ -162,6 +162,26 @@ def extra_ragged_banks(dev, reps=2):
             "per_bank_ms": {str(D): round(st_all[D]["stage_ms"][7], 3) for D in st_all}}
 
 
+def extra_lb_mv_streaming(dev, reps=5):
+    """LB_MV in the streaming regime (queries arriving one at a time, Sec. 7.1):
+    1 and 8 queries against 40000 references of length 256, d = 8 (328 MB of
+    element-major candidate tiles, more than the 256 MB Infinity Cache), as
+    HBM bytes of the candidate tiles per second."""
+    import torch
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.cascade_knn(nq=8, nc=40000, T=256, D=8, seed=7)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    del Cs
+    out = {"workload": "LB_MV, 40000 references x 256 x 8 float32 (328 MB tiles), window 10%"}
+    tile_bytes = 40000 * 256 * 8 * 4
+    for nq in (1, 8):
+        Qd = torch.from_numpy(Q[:nq]).to(dev)
+        ms = _events_ms(lambda: search.lower_bounds(ix, Qd, kind="mv", frac=(1, 10)), reps)
+        out["queries_%d" % nq] = {"ms": round(ms, 4), "GB_per_s": round(tile_bytes / (ms * 1e-3) / 1e9, 1),
+                                  "frac_of_8TB_s": round(tile_bytes / (ms * 1e-3) / 8e12, 3)}
+    return out
+
+
 def extra_long_knn(dev, reps=3):
     """200 queries x 2000 references, length 1024, d = 16, window 10% (row mapping)."""
     import torch
@@ -194,8 +214,9 @@ def cpu_threads():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md, 'More than one GPU'); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the search has no multi-GPU path "
+              "(a query batch would be split across GPUs, each holding a full index copy); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -306,6 +327,7 @@ def main():
         out["dtw_loss"] = extra_fwd_bwd(dev)
         out["long_knn"] = extra_long_knn(dev)
         out["ragged_banks"] = extra_ragged_banks(dev)
+        out["lb_mv_streaming"] = extra_lb_mv_streaming(dev)
         kwp = dict(frac=frac, bounds="plain")
         search.knn(ix, Qd, **kwp)
         torch.cuda.synchronize()

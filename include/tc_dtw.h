@@ -227,7 +227,8 @@ tc_dtw_status tc_dtw_backward_run(const tc_dtw_pairs_plan* plan, const float* x,
 /* -------------------------------------------------------------- index ---
  * tc_dtw_build_index: prepares a candidate (reference) set for repeated
  * searches: a copy of the series, an element-major copy in tiles of 64
- * references (uniform lengths only) for the envelope bound, the candidate
+ * references (uniform lengths only; float[tile][e/4][64][e%4], elements
+ * padded with zeros to a multiple of 4) for the envelope bound, the candidate
  * neighbour distances d(c_{j-1}, c_j) of the basic triangle bound (Sec. 4.1,
  * Eqs. 9-10, computed ahead of time and reused by every query), and the
  * value range (min, max over all values) that sets LB_PC's smallest cell

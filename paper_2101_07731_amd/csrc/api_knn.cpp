@@ -30,7 +30,7 @@ static IndexLayout index_layout(const HostSet& R) {
     Carve c(nullptr, 0);
     auto at = [&](size_t bytes) { c.used = (c.used + 255) & ~(size_t)255; size_t o = c.used; c.used += bytes; return o; };
     L.off_series = at((size_t)L.total_len * R.dim * 4);
-    L.off_tiles = at(R.uniform ? (size_t)L.ntiles * R.ulen * R.dim * 64 * 4 : 0);
+    L.off_tiles = at(R.uniform ? (size_t)L.ntiles * (((size_t)R.ulen * R.dim + 3) / 4 * 4) * 64 * 4 : 0);
     L.off_gamma = at((size_t)L.total_len * 4);
     L.off_meta = at((size_t)R.count * (8 + 8 + 4 + 8) + 8);
     L.off_range = at(8);
@@ -68,7 +68,8 @@ struct KnnPlan {
     int ngroups, max_pts;
     size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
         o_items, o_counters, o_key, o_stats, o_boxes, o_nbox, o_qstep, o_glb, o_tlist, o_tlb, o_tout,
-        o_tcnt, o_ppc, o_pti, o_cntmv, bytes;
+        o_tcnt, o_ppc, o_pti, o_cntmv, o_part, bytes;
+    int nseg = 1;
 };
 
 
@@ -103,7 +104,7 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     Carve c(nullptr, 0);
     auto at = [&](size_t bytes) { c.used = (c.used + 255) & ~(size_t)255; size_t o = c.used; c.used += bytes; return o; };
     const size_t nqt = (size_t)(K.nq + kQT - 1) / kQT;
-    K.o_env = at(K.plain ? 0 : nqt * kQT * (size_t)K.n * K.D * 2 * 4);
+    K.o_env = at(K.plain ? 0 : nqt * kQT * (((size_t)K.n * K.D + 3) / 4 * 4) * 2 * 4);
     K.o_lb = at(K.plain ? 0 : (size_t)K.nq * K.nc * 4);
     K.o_seeds = at((size_t)K.nq * std::max(K.R, 1) * 4);
     K.o_seed_dist = at((size_t)K.nq * std::max(K.R, 1) * 4);
@@ -130,6 +131,8 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.o_ppc = at((size_t)K.nq * 4);
     K.o_pti = at((size_t)K.nq * 4);
     K.o_cntmv = at((size_t)K.nq * 4);
+    K.nseg = K.plain ? 1 : lb_mv_segments(K.ntiles, K.nq, K.n * K.D);
+    K.o_part = at(K.nseg > 1 ? (size_t)K.nseg * K.nq * K.nc * 4 : 0);
     K.bytes = c.need();
     {
         // the boxes of one expanded window are built in LDS; its cell keys need Lv^D < 2^63
@@ -175,6 +178,8 @@ static KnnPlanDev dev_plan(const KnnPlan& K, const tc_dtw_index* ix, const HostS
     d.counters = reinterpret_cast<int32_t*>(ws + K.o_counters);
     d.key = reinterpret_cast<unsigned long long*>(ws + K.o_key);
     d.stats = reinterpret_cast<unsigned long long*>(ws + K.o_stats);
+    d.nseg = K.nseg;
+    d.part = K.nseg > 1 ? reinterpret_cast<float*>(ws + K.o_part) : nullptr;
     return d;
 }
 
@@ -839,7 +844,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
     const KnnPlanDev d = dev_plan(K, ix, Qs, static_cast<char*>(ws));
     const KnnExtra x = extra_plan(K, static_cast<char*>(ws));
     hipError_t e;
-    if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
+    if ((e = launch_knn_prep(d, s, kind != TC_DTW_LB_MV)) != hipSuccess) return hip_fail(e, "prep");
     if (kind == TC_DTW_LB_MV) {
         if ((e = launch_lb_mv(d, lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
     } else if (kind == TC_DTW_LB_PC) {

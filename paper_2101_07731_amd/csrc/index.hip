@@ -68,16 +68,21 @@ __global__ void k_index_series(const float* src, const int64_t* src_off, const i
 
 // Element-major tiles: tiles[(tile * E + e) * 64 + lane] = series[(tile*64+lane) * E + e],
 // E = len * D; zero for candidates past the end.
+// Layout tiles[tile][e / 4][lane][e % 4]: a lane reads four consecutive
+// elements of its candidate with one 16-byte load, a wave 1 KB; elements
+// past E (padding to a multiple of 4) are 0.
 __global__ void k_index_tiles(const float* series, int count, int E, int ntiles, float* tiles) {
-    const int64_t total = (int64_t)ntiles * E * 64;
+    const int E4 = (E + 3) / 4;
+    const int64_t total = (int64_t)ntiles * E4 * 256;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int lane = (int)(idx & 63);
-        const int64_t te = idx >> 6;
-        const int tile = (int)(te / E);
-        const int e = (int)(te - (int64_t)tile * E);
+        const int comp = (int)(idx & 3);
+        const int lane = (int)((idx >> 2) & 63);
+        const int64_t te4 = idx >> 8;
+        const int tile = (int)(te4 / E4);
+        const int e = 4 * (int)(te4 - (int64_t)tile * E4) + comp;
         const int r = tile * 64 + lane;
-        tiles[idx] = r < count ? series[(int64_t)r * E + e] : 0.0f;
+        tiles[idx] = (r < count && e < E) ? series[(int64_t)r * E + e] : 0.0f;
     }
 }
 

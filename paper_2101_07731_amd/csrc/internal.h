@@ -146,7 +146,11 @@ struct KnnPlanDev {
     unsigned long long* key;
     unsigned long long* stats;
     int32_t* clear[3];    // optional extra per-query counters zeroed with the others
+    float* part;          // LB_MV partial sums [nseg][nq][nc] when nseg > 1, else null
+    int32_t nseg;
 };
+// Element segments of the LB_MV launch (more when few query tiles would leave HBM idle).
+int lb_mv_segments(int ntiles, int nq, int E);
 
 // Persistent DTW over per-query candidate lists.
 struct KnnDtwArgs {
@@ -225,7 +229,9 @@ hipError_t launch_rknn_finalize(const RaggedKnnArgs& a, hipStream_t s);
 size_t rknn_dtw_lds_bytes(int maxn, int D);
 size_t rknn_final_lds_bytes(int maxn, int D);
 
-hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s);
+// Query envelope; with init also the
+// per-query search state (best-so-far keys, list counts, counters, stats).
+hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s, bool init = true);
 hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s);
 hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s);
 hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int use_gate, hipStream_t s);

@@ -3,7 +3,7 @@
 // survivors with early abandoning (persistent work queue), float64
 // re-scoring of near-tie finalists.
 //
-// Soundness of every float32 decision (see DESIGN.md "Rounding"):
+// Soundness of every float32 decision:
 //   * a bound is a sum of N non-negative float32 terms accumulated by fused
 //     multiply-add; scaled by (1 - (N+3) u) and rounded down it never
 //     exceeds the exact bound (u = 2^-24);
@@ -57,62 +57,117 @@ __global__ void k_knn_init(int nq, unsigned long long* key, int32_t* cnt, int32_
 __global__ void k_envelope(const float* __restrict__ Q, int nq, int m, int n, int D, int W,
                            float* __restrict__ env) {
     const int E = n * D;
+    const int Ep = (E + 3) / 4 * 4;     // padded like the candidate tiles; padding gets (+inf, -inf)
     const int nqt = (nq + kQT - 1) / kQT;
-    const int64_t total = (int64_t)nqt * kQT * E;
+    const int64_t total = (int64_t)nqt * kQT * Ep;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int e = (int)(idx % E);
-        const int q = (int)(idx / E);
+        const int e = (int)(idx % Ep);
+        const int q = (int)(idx / Ep);
         const int j = e / D, p = e - j * D;
         float U = __builtin_inff(), L = -__builtin_inff();
-        if (q < nq) {
+        if (q < nq && e < E) {
             const int i0 = max(0, j - W), i1 = min(m - 1, j + W);
             const float* s = Q + (int64_t)q * m * D + p;
             U = s[(int64_t)i0 * D];
             L = U;
-            for (int i = i0 + 1; i <= i1; ++i) {
+#pragma unroll 8
+            for (int i = i0 + 1; i <= i1; ++i) {    // unrolled: eight loads in flight
                 const float v = s[(int64_t)i * D];
                 U = __builtin_fmaxf(U, v);
                 L = __builtin_fminf(L, v);
             }
         }
-        float* o = env + (((int64_t)(q / kQT) * E + e) * kQT + (q % kQT)) * 2;
+        float* o = env + (((int64_t)(q / kQT) * Ep + e) * kQT + (q % kQT)) * 2;
         o[0] = U;
         o[1] = L;
     }
 }
 
-// LB_MV (Sec. 3, squared form) of kQT queries against 64 candidates per
-// wave.  Candidates come from the element-major tiles (one coalesced
-// 256-byte load per element), the envelope from wave-uniform scalar loads;
-// per element and query: two subtractions, a max3 and an FMA.
+// LB_MV (Sec. 3, squared form) of up to kQT queries against 64 candidates
+// per wave.  Candidates come from the element-major tiles (a lane reads
+// four elements of its candidate with one 16-byte load), the envelope from
+// wave-uniform scalar loads.  The term of element e is t^2 with
+// t = c - med3(c, L, U): c - U above the envelope, -(L - c) below it, 0
+// inside -- the float32 values of max(c - U, L - c, 0), one operation fewer.
+// QT: query slots of the tile that are evaluated (kQT, or fewer when the
+// whole batch has fewer queries); LD: loads in flight per lane (deeper when
+// the arithmetic per element is light and HBM is the bound).
+// With few query tiles (queries arriving one at a time) a launch over
+// candidate tiles alone would hold too few waves to keep HBM busy, so the
+// elements are split into gridDim.z segments of seg4 groups of four: each
+// segment writes its raw partial sums to `part` ([z][nq][nc]) and k_lb_sum
+// adds them in segment order.  (A last-arriving block adding them instead
+// would need a device-scope release per block, which writes back the
+// XCD's whole L2.)  The deflation covers any summation order of the E
+// terms.
+template <int QT, int LD = (QT <= 2 ? 4 : 2)>
 __global__ __launch_bounds__(256) void k_lb_mv(const float* __restrict__ tiles, int ntiles, int E,
                                                const float* __restrict__ env, int nq, int nc,
-                                               double deflate, float* __restrict__ lb) {
+                                               double deflate, float* __restrict__ lb, int seg4,
+                                               float* __restrict__ part) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = blockIdx.x * 4 + wave;
     if (tile >= ntiles) return;
     const int qt = blockIdx.y;
-    const float* __restrict__ cp = tiles + (int64_t)tile * E * 64 + lane;
-    const float* __restrict__ ep = env + (int64_t)qt * E * kQT * 2;
-    float acc[kQT];
+    const int E4 = (E + 3) / 4, Ep = 4 * E4;
+    const int f0 = blockIdx.z * seg4, f1 = min(E4, f0 + seg4);
+    const float4* __restrict__ cp = reinterpret_cast<const float4*>(tiles) + (int64_t)tile * E4 * 64 + lane;
+    const float* __restrict__ ep = env + (int64_t)qt * Ep * kQT * 2;
+    float acc[QT];
 #pragma unroll
-    for (int k = 0; k < kQT; ++k) acc[k] = 0.0f;
-    for (int e = 0; e < E; ++e) {
-        const float c = cp[(int64_t)e * 64];
+    for (int k = 0; k < QT; ++k) acc[k] = 0.0f;
+    auto term = [&](float c, int e) {
         const float* __restrict__ u = ep + (int64_t)e * kQT * 2;
 #pragma unroll
-        for (int k = 0; k < kQT; ++k) {
-            const float d = __builtin_fmaxf(__builtin_fmaxf(c - u[2 * k], u[2 * k + 1] - c), 0.0f);
-            acc[k] = __builtin_fmaf(d, d, acc[k]);
+        for (int k = 0; k < QT; ++k) {
+            const float t = c - __builtin_amdgcn_fmed3f(c, u[2 * k + 1], u[2 * k]);
+            acc[k] = __builtin_fmaf(t, t, acc[k]);
         }
+    };
+    int f = f0;
+    for (; f + LD <= f1; f += LD) {   // LD 16-byte loads (4 LD elements) in flight per lane
+        float4 a[LD];
+#pragma unroll
+        for (int i = 0; i < LD; ++i) a[i] = cp[(int64_t)(f + i) * 64];
+#pragma unroll
+        for (int i = 0; i < LD; ++i) {
+            const int e = 4 * (f + i);
+            term(a[i].x, e); term(a[i].y, e + 1); term(a[i].z, e + 2); term(a[i].w, e + 3);
+        }
+    }
+    for (; f < f1; ++f) {
+        const float4 a = cp[(int64_t)f * 64];
+        const int e = 4 * f;
+        term(a.x, e); term(a.y, e + 1); term(a.z, e + 2); term(a.w, e + 3);
     }
     const int r = tile * 64 + lane;
     if (r >= nc) return;
 #pragma unroll
-    for (int k = 0; k < kQT; ++k) {
+    for (int k = 0; k < QT; ++k) {
         const int q = qt * kQT + k;
-        if (q < nq) lb[(int64_t)q * nc + r] = round_down_f((double)acc[k] * deflate);
+        if (q >= nq) continue;
+        if (gridDim.z == 1) lb[(int64_t)q * nc + r] = round_down_f((double)acc[k] * deflate);
+        else part[((int64_t)blockIdx.z * nq + q) * nc + r] = acc[k];
+    }
+}
+
+// Sum of the segment partials in segment order; the loads of eight
+// segments are issued together.
+__global__ __launch_bounds__(256) void k_lb_sum(const float* __restrict__ part, int nseg, int64_t n,
+                                                double deflate, float* __restrict__ lb) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        int z = 0;
+        for (; z + 8 <= nseg; z += 8) {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = part[(int64_t)(z + i) * n + t];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s += v[i];
+        }
+        for (; z < nseg; ++z) s += part[(int64_t)z * n + t];
+        lb[t] = round_down_f((double)s * deflate);
     }
 }
 
@@ -642,23 +697,43 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
 }
 
 // ------------------------------------------------------------------ launch
-hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_knn_init, dim3((p.nq + 255) / 256 + 1), dim3(256), 0, s, p.nq, p.key, p.cnt,
-                       p.gcnt, p.counters, p.stats, p.clear[0], p.clear[1], p.clear[2]);
+hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s, bool init) {
+    if (init)
+        hipLaunchKernelGGL(k_knn_init, dim3((p.nq + 255) / 256 + 1), dim3(256), 0, s, p.nq, p.key, p.cnt,
+                           p.gcnt, p.counters, p.stats, p.clear[0], p.clear[1], p.clear[2]);
     if (p.env) {
-        const int64_t total = (int64_t)((p.nq + kQT - 1) / kQT) * kQT * p.n * p.D;
+        const int64_t total = (int64_t)((p.nq + kQT - 1) / kQT) * kQT * (((int64_t)p.n * p.D + 3) / 4 * 4);
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
         hipLaunchKernelGGL(k_envelope, dim3(blocks), dim3(256), 0, s, p.Q, p.nq, p.m, p.n, p.D, p.W, p.env);
     }
     return hipGetLastError();
 }
 
+int lb_mv_segments(int ntiles, int nq, int E) {
+    const int64_t blocks = (int64_t)((ntiles + 3) / 4) * ((nq + kQT - 1) / kQT);
+    if (blocks >= 2048) return 1;   // eight waves per CU already
+    int64_t S = (8192 + blocks - 1) / blocks;
+    const int ld = nq <= 2 ? 4 : 2;   // loads in flight of the kernel that runs
+    S = std::min<int64_t>(S, std::max(1, (E + 3) / 4 / (8 * ld)));   // eight rounds of loads per segment
+    return (int)std::max<int64_t>(S, 1);
+}
+
 hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s) {
     const int E = p.n * p.D;
     const double u = 1.0 / 16777216.0;
     const double deflate = 1.0 - (double)(E + 3) * u * 1.001;
-    dim3 grid((p.ntiles + 3) / 4, (p.nq + kQT - 1) / kQT);
-    hipLaunchKernelGGL(k_lb_mv, grid, dim3(256), 0, s, p.tiles, p.ntiles, E, p.env, p.nq, p.nc, deflate, lb);
+    const int S = p.part ? p.nseg : 1;
+    const int E4 = (E + 3) / 4;
+    const int seg = (E4 + S - 1) / S;   // in groups of 4 elements
+    dim3 grid((p.ntiles + 3) / 4, (p.nq + kQT - 1) / kQT, S);
+    auto kern = p.nq > 4 ? k_lb_mv<kQT> : p.nq > 2 ? k_lb_mv<4> : p.nq > 1 ? k_lb_mv<2> : k_lb_mv<1>;
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, p.tiles, p.ntiles, E, p.env, p.nq, p.nc, deflate, lb, seg,
+                       p.part);
+    if (S > 1) {
+        const int64_t n = (int64_t)p.nq * p.nc;
+        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_lb_sum, dim3(blocks), dim3(256), 0, s, p.part, S, n, deflate, lb);
+    }
     return hipGetLastError();
 }
 

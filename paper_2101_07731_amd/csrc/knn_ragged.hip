@@ -101,8 +101,10 @@ __global__ __launch_bounds__(256) void k_rq_tables(RaggedKnnArgs a) {
 // of 4 (VEC) the table rows and the candidate point are read as float4
 // chunks (every row offset is then a multiple of 4 floats), NCH chunks
 // unrolled so that all loads of a point are in flight together.
+// Distance of v to [Lw, U] up to sign (v - U above, v - Lw below, 0 inside);
+// its square is the envelope term.
 __device__ __forceinline__ float mv_term(float v, float U, float Lw) {
-    return v > U ? v - U : (v < Lw ? Lw - v : 0.0f);
+    return v - __builtin_amdgcn_fmed3f(v, Lw, U);
 }
 
 template <int NCH, bool VEC>

@@ -106,17 +106,48 @@ def test_unequal_query_and_candidate_lengths(dev):
     np.testing.assert_array_equal(dist, rd.astype(np.float32))
 
 
-def test_lb_mv_dense_matrix(dev):
+@pytest.mark.parametrize("case", [
+    (19, 150, 80, 8),   # three query tiles, ten element segments
+    (1, 300, 64, 3),    # one query slot, three segments
+    (3, 200, 20, 3),    # four query slots, E = 60 (not a multiple of 4), one segment
+    (2, 130, 33, 5),    # two query slots, E = 165, two segments, ragged last tile
+], ids=lambda c: "nq%d_nc%d_T%d_D%d" % c)
+def test_lb_mv_dense_matrix(dev, case):
     from paper_2101_07731_amd import search, synth
-    Q, Cs = synth.cascade_knn(nq=19, nc=150, T=80, D=8, seed=25)
+    nq, nc, T, D = case
+    Q, Cs = synth.cascade_knn(nq=nq, nc=nc, T=T, D=D, seed=25)
+    say("lb_mv dense", case)
     ix = search.Index(torch.from_numpy(Cs).to(dev))
     lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="mv", frac=(1, 10)).cpu().numpy()
-    W = O.window_eff(80, 80, 0, 1, 10)
+    W = O.window_eff(T, T, 0, 1, 10)
     ref = np.array([[O.lb_mv(q, c, W) for c in Cs] for q in Q])
     assert np.all(lb.astype(np.float64) <= ref * (1 + 1e-12))
     # deflation (E+3) u plus the float32 accumulation error (at most E+2 roundings), E = n*D
-    slack = 2 * (80 * 8 + 4) * 2.0 ** -24 * 1.01 + 2e-7
+    slack = 2 * (T * D + 4) * 2.0 ** -24 * 1.01 + 2e-7
     assert np.all(lb.astype(np.float64) >= ref * (1 - slack) - 1e-30)
+    # the same matrix again: the segment sums are added in a fixed order
+    lb2 = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="mv", frac=(1, 10)).cpu().numpy()
+    np.testing.assert_array_equal(lb, lb2)
+
+
+def test_lb_mv_streaming_size_sampled(dev):
+    """LB_MV at the streaming size (40000 references of length 256, d = 8,
+    one and eight queries, the launch the streaming benchmark times):
+    sampled columns against the oracle."""
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.cascade_knn(nq=8, nc=40000, T=256, D=8, seed=7)
+    say("lb_mv streaming size", Cs.shape)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    W = O.window_eff(256, 256, 0, 1, 10)
+    cols = np.random.default_rng(5).choice(40000, 64, replace=False)
+    cols = np.concatenate([cols, [0, 63, 64, 39999]])
+    slack = 2 * (256 * 8 + 4) * 2.0 ** -24 * 1.01 + 2e-7
+    for nq in (1, 8):
+        lb = search.lower_bounds(ix, torch.from_numpy(Q[:nq]).to(dev), kind="mv", frac=(1, 10)).cpu().numpy()
+        ref = np.array([[O.lb_mv(q, Cs[c], W) for c in cols] for q in Q[:nq]])
+        got = lb[:, cols].astype(np.float64)
+        assert np.all(got <= ref * (1 + 1e-12))
+        assert np.all(got >= ref * (1 - slack) - 1e-30)
 
 
 def test_full_size_sampled(dev):
