@@ -37,6 +37,10 @@ WORKLOADS = {
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
+EXTRAS = ("full_cascade", "cascade_setup", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
+          "lb_mv_streaming", "plain_gpu")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,9 +51,9 @@ def parse():
     ap.add_argument("--frac", default=None, help="window fraction num/den, e.g. 1/10")
     ap.add_argument("--cpu-queries", type=int, default=24, help="queries in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extras", action="store_true",
-                    help="also time the plain GPU search, the full cascade, batched uneven pairs, "
-                         "forward+backward pairs and long-series 1-NN")
+    ap.add_argument("--extras", nargs="*", default=None, choices=EXTRAS, metavar="NAME",
+                    help="also time further workloads: all of them with no name, else the named ones "
+                         "(%s)" % ", ".join(EXTRAS))
     return ap.parse_args()
 
 
@@ -306,7 +310,8 @@ def main():
         },
     }
 
-    if args.extras:
+    extras = set() if args.extras is None else set(args.extras or EXTRAS)
+    if "full_cascade" in extras:
         kwf = dict(frac=frac, bounds="mv+pc+ti")
         search.knn(ix, Qd, **kwf)
         stf = {}
@@ -319,15 +324,17 @@ def main():
                                "pruned_pc": stf["pruned_pc"], "pruned_ti": stf["pruned_ti"],
                                "pct_dtw_pruned": round(100.0 * (1 - stf["dtw_started"] / stf["pairs"]), 3),
                                "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3)}
+    if "cascade_setup" in extras:
         # setup-stage choice of bounds and triggers on a sample of 100 queries (Sec. 6)
         best, times = search.tune_cascade(ix, Qd[:100], frac=frac)
         out["cascade_setup"] = {"sample_queries": 100, "best": "%s e_pc=%s e_ti=%s" % best,
                                 "ms_per_choice": {"%s e_pc=%s e_ti=%s" % k: round(v, 3) for k, v in times.items()}}
-        out["batched_pairs"] = extra_batched_pairs(dev)
-        out["dtw_loss"] = extra_fwd_bwd(dev)
-        out["long_knn"] = extra_long_knn(dev)
-        out["ragged_banks"] = extra_ragged_banks(dev)
-        out["lb_mv_streaming"] = extra_lb_mv_streaming(dev)
+    for name, fn in (("batched_pairs", extra_batched_pairs), ("dtw_loss", extra_fwd_bwd),
+                     ("long_knn", extra_long_knn), ("ragged_banks", extra_ragged_banks),
+                     ("lb_mv_streaming", extra_lb_mv_streaming)):
+        if name in extras:
+            out[name] = fn(dev)
+    if "plain_gpu" in extras:
         kwp = dict(frac=frac, bounds="plain")
         search.knn(ix, Qd, **kwp)
         torch.cuda.synchronize()
