@@ -33,9 +33,11 @@ WORKLOADS = {
               "plain 1-NN: 64 queries x 256 references, length 64, d=3, random walks, window 10% (W=6)"),
 }
 
-# MI355X fp32 vector peak, 157.3 TFLOP/s = 256 CUs x 128 lanes x 2.4 GHz x 2 flops per FMA:
-# 78.6e12 VALU lane-operations/s, an FMA counted as one operation like any other VALU op.
-VALU_LANE_OPS = 256 * 128 * 2.4e9
+# MI355X VALU rate for the plain (non-packed) fp32 instructions the kernels use: one wave64
+# instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12
+# lane-operations/s.  The published 157.3 TFLOP/s counts packed fp32 (two FMAs per lane per
+# instruction, 2 flops each), which the kernels do not use.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 EXTRAS = ("full_cascade", "cascade_setup", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",

@@ -263,7 +263,7 @@ static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, b
     KnnDtwArgs a;
     std::memset(&a, 0, sizeof a);
     a.Q = d.Q; a.C = d.C;
-    a.nq = K.nq; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W; a.P = K.P;
+    a.nq = K.nq; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W; a.P = K.P; a.gs = knn_lane_stride(K.W);
     if (seeds) {
         a.list = reinterpret_cast<const uint32_t*>(d.seeds);
         a.list_dist = d.seed_dist;

@@ -12,6 +12,33 @@ template <> __device__ __forceinline__ double inf_v<double>() { return __builtin
 // DPP control codes (GFX9 family): whole-wave shift by one lane.
 constexpr int kWaveShr1 = 0x138;  // lane l receives lane l-1
 constexpr int kWaveShl1 = 0x130;  // lane l receives lane l+1
+constexpr int kWaveRor1 = 0x13C;  // lane l receives lane l-1, lane 0 lane 63
+constexpr int kWaveRol1 = 0x134;  // lane l receives lane l+1, lane 63 lane 0
+
+__device__ __forceinline__ uint32_t wave_ror1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kWaveRor1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t wave_rol1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kWaveRol1, 0xF, 0xF, false);
+}
+// Directed roundings of a non-negative double to float.
+__device__ __forceinline__ float round_down_f(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);   // x > 0
+    return f;
+}
+__device__ __forceinline__ float round_up_pos(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
+    return f;
+}
+
+// Minimum of non-negative floats (or +inf) through their bit patterns, which
+// order like the values; no NaN handling is generated.
+__device__ __forceinline__ uint32_t umin3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t t = a < b ? a : b;
+    return t < c ? t : c;
+}
 
 // Lanes without a source lane keep `old`.
 __device__ __forceinline__ float wave_shr1(float old, float v) {

@@ -127,6 +127,47 @@ __device__ __forceinline__ void diag_round(const int (&qk)[NCH], const int (&ck)
     }
 }
 
+// The round of diag_round for float values without argmin codes, with the
+// neighbour values passed by whole-wave rotations and the minimum taken on
+// the bit patterns (every DP value is >= +0 or +inf, never NaN).  Rotations
+// give lane 0 the value of lane 63 and lane 63 that of lane 0, so they need
+// the caller's layout to hold +inf there: with WODD lane 0's even slot (its
+// E step is killed), otherwise lane 63's odd slot (lane 63 is a padding
+// lane or belongs to no pair, and its O step is killed).
+// The two steps of a round on points already in registers.
+template <int NCH, bool WODD>
+__device__ __forceinline__ void diag_steps_rot(const float4 (&qv)[NCH], const float4 (&cin)[NCH],
+                                               const float4 (&cout)[NCH], bool kill_e, bool kill_o,
+                                               float& vE, float& vO) {
+    {   // E step: up = own odd slot, left = lane-1's odd slot, diag = own even slot
+        const float cost = point_cost<NCH>(qv, cin, 0.0f);
+        const uint32_t o = __float_as_uint(vO);
+        float v = cost + __uint_as_float(umin3(__float_as_uint(vE), o, wave_ror1(o)));
+        if (WODD && kill_e) v = __builtin_inff();
+        vE = v;
+    }
+    {   // O step: up = lane+1's even slot, left = own even slot, diag = own odd slot
+        const float cost = point_cost<NCH>(qv, cout, 0.0f);
+        const uint32_t e = __float_as_uint(vE);
+        float v = cost + __uint_as_float(umin3(__float_as_uint(vO), wave_rol1(e), e));
+        if (!WODD && kill_o) v = __builtin_inff();
+        vO = v;
+    }
+}
+
+template <int NCH, bool WODD>
+__device__ __forceinline__ void diag_round_rot(const int (&qk)[NCH], const int (&ck)[NCH], int off,
+                                               const float4 (&cin)[NCH], float4 (&cout)[NCH],
+                                               bool kill_e, bool kill_o, float& vE, float& vO) {
+    float4 qv[NCH];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        qv[k] = lds4[qk[k] + off];
+        cout[k] = lds4[ck[k] + off + 1];
+    }
+    diag_steps_rot<NCH, WODD>(qv, cin, cout, kill_e, kill_o, vE, vO);
+}
+
 // One wave, groups of G lanes each evaluating one pair.  qb / cb: this
 // lane's LDS float4 indices (position offsets already applied, see
 // dtw_fwd.hip); chunk k of the query lies LQ float4 further, of the

@@ -157,6 +157,7 @@ struct KnnDtwArgs {
     const float* Q;
     const float* C;
     int32_t nq, m, n, D, W, P;
+    int32_t gs;                // lanes per pair group (knn_lane_stride)
     const uint32_t* list;      // [nq][cap] candidate indices (negative: none)
     float* list_dist;          // [nq][cap] float32 DTW, +inf when abandoned
     const int32_t* cnt;        // [nq] list lengths (unless cnt_uniform > 0)
@@ -240,10 +241,22 @@ hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s);
 int64_t band_cells(int m, int n, int W);
 hipError_t launch_knn_finalize(const KnnFinalArgs& a, hipStream_t s);
 size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P);
+int knn_ring_max_passes(int nch);
 int knn_dtw_max_pairs(int W, int D);
 // Ring size of the diagonal 1-NN kernel: the live window W + 5 plus one
 // refill of RS / 4 positions must fit.
 inline int ring_size(int W) { return W <= 27 ? 64 : 128; }
+// Lanes per pair in the 1-NN diagonal kernel: the W + 1 band offsets of a
+// pair, padded to a power of two when that keeps as many pairs per wave.
+// Each 16-lane quarter of the wave then reads 16 consecutive positions of
+// one series, which the LDS serves without bank conflicts; two pairs in
+// one quarter read positions 16 apart, which share banks.
+inline int knn_lane_stride(int W) {
+    const int G = W + 1;
+    int p2 = 1;
+    while (p2 < G) p2 <<= 1;
+    return (64 / p2 >= 64 / G) ? p2 : G;
+}
 size_t knn_final_lds_bytes(int m, int n, int W, int D);
 
 // --------------------------------------------------------- advanced bounds

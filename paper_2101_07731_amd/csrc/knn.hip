@@ -22,17 +22,6 @@
 
 namespace tcdtw {
 
-__device__ __forceinline__ float round_down_f(double x) {
-    float f = (float)x;
-    if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);   // x > 0
-    return f;
-}
-__device__ __forceinline__ float round_up_pos(double x) {
-    float f = (float)x;
-    if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
-    return f;
-}
-
 // ------------------------------------------------------------------ setup
 __global__ void k_knn_init(int nq, unsigned long long* key, int32_t* cnt, int32_t* gcnt,
                            int32_t* counters, unsigned long long* stats, int32_t* c0, int32_t* c1,
@@ -311,108 +300,29 @@ __device__ __forceinline__ void publish(const KnnDtwArgs& a, int q, int ref, flo
     atomicMin(&a.key[(int64_t)q * kKeyStride], k);
 }
 
-template <int NCH, bool WODD>
-__global__ __launch_bounds__(64) void k_knn_dtw_diag(KnnDtwArgs a) {
-    const int lane = threadIdx.x;
-    DiagGeom g;
-    g.init(a.m, a.n, a.W);
-    const int G = g.G, h = g.h, R = g.R, LQ = g.LQ, LC = g.LC, P = a.P;
-    const int sq = 0;
-    const int scs = LQ * NCH;
-    const int grp = lane / G;
-    const int lg = lane - grp * G;
-    const int total = a.prefix[a.nq];
-    int staged_q = -1;
-    unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
-    for (;;) {
-        const int item = wave_next_item(a.counter);
-        if (item >= total) break;
-        const int q = find_query(a.prefix, a.nq, item);
-        const int chunk = item - a.prefix[q];
-        const int base = chunk * P;
-        const int np = min(P, a.cnt_uniform > 0 ? a.cnt_uniform - base : a.cnt[q] - base);
-        __syncthreads();
-        if (q != staged_q) {
-            stage_series<NCH>(sq, LQ, g.qfirst(), a.Q + (int64_t)q * a.m * a.D, a.m, a.D,
-                              __builtin_inff(), lane, kWave);
-            staged_q = q;
-        }
-        for (int gg = 0; gg < np; ++gg) {
-            const int ref = (int)a.list[(int64_t)q * a.cap + base + gg];
-            stage_series<NCH>(scs + gg * LC * NCH, LC, g.cfirst(),
-                              a.C + (int64_t)(ref < 0 ? 0 : ref) * a.n * a.D, a.n, a.D,
-                              -__builtin_inff(), lane, kWave);
-        }
-        __syncthreads();
-        const bool spare = grp >= np;
-        const int gsrc = spare ? 0 : grp;
-        const bool kill_e = WODD && (lg == 0 || spare);
-        const bool kill_o = !WODD && (lg == G - 1);
-        const int qb = sq + (a.W - lg);
-        const int cb = scs + gsrc * LC * NCH + lg;
-        float vE = __builtin_inff(), vO = __builtin_inff();
-        if (!spare && lg == h) vE = 0.0f;
-        const uint64_t valid_mask = (np * G >= 64) ? ~0ull : ((1ull << (np * G)) - 1);
-        const uint64_t gm = spare ? 0ull : (((G >= 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G));
-        Abandon ab{a.key + (int64_t)q * kKeyStride, a.gamma, valid_mask};
-        bool aband = false;
-        int rounds;
-        if (a.abandon)
-            rounds = diag_core<float, NCH, false, WODD, true>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE,
-                                                              vO, nullptr, ab, aband, gm);
-        else
-            rounds = diag_core<float, NCH, false, WODD, false>(qb, LQ, cb, LC, R, G, lg, kill_e, kill_o, vE,
-                                                               vO, nullptr, ab, aband, gm);
-        const int sigma = (a.n - a.m) + 2 * h;
-        const int myref = spare ? -1 : (int)a.list[(int64_t)q * a.cap + base + grp];
-        if (!spare && lg == (sigma >> 1)) {
-            const float v = (sigma & 1) ? vO : vE;
-            float out = __builtin_inff();
-            if (!aband && myref >= 0) {
-                out = v;
-                publish(a, q, myref, v, a.gamma);
-            }
-            a.list_dist[(int64_t)q * a.cap + base + grp] = out;
-        }
-        const uint64_t bstart = __ballot(!spare && lg == 0 && myref >= 0);
-        const uint64_t bab = __ballot(aband && !spare && lg == 0 && myref >= 0);
-        {
-            const int ns = __popcll(bstart), na = __popcll(bab);
-            w_started += ns;
-            w_aband += na;
-            // cells: completed pairs count their band, abandoned ones the share of rounds they ran
-            const double part = (double)a.band_cells * (double)rounds / (double)R;
-            w_cells += (unsigned long long)(ns - na) * (unsigned long long)a.band_cells +
-                       (unsigned long long)((double)na * part);
-        }
-    }
-    if (lane == 0 && w_started) {
-        atomicAdd(&a.stats[kStDtwStarted], w_started);
-        atomicAdd(&a.stats[kStDtwAbandoned], w_aband);
-        atomicAdd(&a.stats[kStCells], w_cells);
-    }
-}
-
 // Diagonal mapping with ring buffers: each staged series keeps only RS
-// consecutive positions (slot = position mod RS, slots 0..7 mirrored after
-// RS so that four consecutive positions never wrap).  The live window of a
-// round is W + 5 positions; every RF = RS / 4 rounds the RF positions that
-// fell behind are overwritten with the next ones, loaded into registers one
-// refill ahead.  Series 0 is the query, series 1 + g the candidate of group g.
-// Rounds between early-abandon checks (a multiple of both refill periods).
+// consecutive positions (slot = position mod RS).  The live window of a
+// round is about W + 2 positions; every RF = RS / 4 rounds the RF positions
+// that fell behind are overwritten with the next ones, loaded into
+// registers one refill ahead.  Series 0 is the query, series 1 + g the
+// candidate of group g.
+// Rounds between early-abandon checks.
 constexpr int kCheckRounds = 32;
 
-template <int NCH, bool WODD, int RS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 ? 4 : 1))) void k_knn_dtw_ring(KnnDtwArgs a) {
-    constexpr int RF = RS / 4, MIR = 8, STR = RS + MIR;
-    constexpr int MAXPASS = NCH <= 4 ? 3 : 1;
+// NPASS: 64-lane passes of one refill ((1 + P) * RF positions), so that the
+// prefetch registers are only as many as the launch needs.
+template <int NCH, bool WODD, int RS, int NPASS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && NPASS <= 2 ? 4 : 1))) void k_knn_dtw_ring(KnnDtwArgs a) {
+    constexpr int RF = RS / 4, STR = RS;
+    constexpr int MAXPASS = NPASS;
     const int lane = threadIdx.x;
     DiagGeom g;
     g.init(a.m, a.n, a.W);
-    const int G = g.G, h = g.h, R = g.R, P = a.P, W = a.W;
+    const int G = g.G, h = g.h, R = g.R, P = a.P, W = a.W, GS = a.gs;
     const int per_series = NCH * STR;
-    const int grp = lane / G;
-    const int lg = lane - grp * G;
+    const int grp = lane / GS;
+    const int lg = lane - grp * GS;
+    const bool pad = lg >= G;   // padding lane of a group (see knn_lane_stride)
     const int total = a.prefix[a.nq];
     unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
@@ -424,25 +334,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 ? 4
         const int np = min(P, a.cnt_uniform > 0 ? a.cnt_uniform - base : a.cnt[q] - base);
         const int nser = 1 + np;
         const float* qsrc = a.Q + (int64_t)q * a.m * a.D;
-        auto series_src = [&](int s) -> const float* {
+        auto series_src = [&](int s) __attribute__((always_inline)) -> const float* {
             if (s == 0) return qsrc;
             const int ref = (int)a.list[(int64_t)q * a.cap + base + s - 1];
             return a.C + (int64_t)(ref < 0 ? 0 : ref) * a.n * a.D;
         };
-        // ring slot writer: position pos of series s
-        auto put = [&](int s, int pos, const float4 (&v)[NCH]) {
-            const int slot = pos & (RS - 1);
-            const int b0 = s * per_series + slot;
-#pragma unroll
-            for (int k = 0; k < NCH; ++k) lds4[b0 + k * STR] = v[k];
-            if (slot < MIR) {
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) lds4[b0 + RS + k * STR] = v[k];
-            }
-        };
-        auto fetch = [&](int s, int pos, float4 (&v)[NCH]) {
+        // point of position pos of series s (outside the series: +inf for the
+        // query, -inf for a candidate, so that those cells cost +inf)
+        auto fetch = [&](int s, int pos, float4 (&v)[NCH]) __attribute__((always_inline)) {
             if (s == 0) load_point<NCH>(qsrc, a.m, a.D, pos + g.qfirst(), __builtin_inff(), v);
             else load_point<NCH>(series_src(s), a.n, a.D, pos + g.cfirst(), -__builtin_inff(), v);
+        };
+        auto put = [&](int s, int pos, const float4 (&v)[NCH]) __attribute__((always_inline)) {
+            const int slot = pos & (RS - 1);
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) lds4[s * per_series + k * STR + slot] = v[k];
         };
         __syncthreads();
         // initial positions 0 .. RS-1 of every series
@@ -463,68 +369,119 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 ? 4
 
         const bool spare = grp >= np;
         const int gsrc = spare ? 0 : grp;
-        const bool kill_e = WODD && (lg == 0 || spare);
-        const bool kill_o = !WODD && (lg == G - 1);
+        // Band-edge kills (one per parity) also isolate neighbouring groups;
+        // padding lanes and lanes of absent pairs hold +inf on the killed
+        // diagonal, which is the only one their neighbours read.
+        const bool kill_e = WODD && (lg == 0 || spare || pad);
+        const bool kill_o = !WODD && (lg == G - 1 || spare || pad);
         const int qbase = 0;
         const int cbase = (1 + gsrc) * per_series;
         float vE = __builtin_inff(), vO = __builtin_inff();
         if (!spare && lg == h) vE = 0.0f;
-        const uint64_t valid_mask = (np * G >= 64) ? ~0ull : ((1ull << (np * G)) - 1);
-        const uint64_t gm = spare ? 0ull : (((G >= 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G));
+        const uint64_t gbits = (G >= 64) ? ~0ull : ((1ull << G) - 1);
+        uint64_t valid_mask = 0;
+        for (int gg = 0; gg < np; ++gg) valid_mask |= gbits << (gg * GS);
+        const uint64_t gm = spare ? 0ull : gbits << (grp * GS);
         bool aband = false;
         const bool abandon = a.abandon != 0;
         // the best-so-far is read by a coherent (slow) load whose value is first needed at
         // the first check: nothing waits for it at the start of the item
         unsigned long long pend = 0;
         if (abandon) pend = __hip_atomic_load(a.key + (int64_t)q * kKeyStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        float4 cA[NCH], cB[NCH];
+        // Round r reads query position r + W - lg and candidate positions
+        // r + lg (cin, the previous round's cout) and r + lg + 1 (cout).
+        auto ldq = [&](int rr, float4 (&v)[NCH]) __attribute__((always_inline)) {
+            const int sl = (rr + W - lg) & (RS - 1);
 #pragma unroll
-        for (int k = 0; k < NCH; ++k) cA[k] = lds4[cbase + lg + k * STR];
-        uint32_t cw = 0;
-        int r = 0;
+            for (int k = 0; k < NCH; ++k) v[k] = lds4[qbase + sl + k * STR];
+        };
+        auto ldc = [&](int pos, float4 (&v)[NCH]) __attribute__((always_inline)) {
+            const int sl = (pos + lg) & (RS - 1);
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) v[k] = lds4[cbase + sl + k * STR];
+        };
+        // Refills and early-abandon checks run at the first loop boundary at
+        // or past their round: a refill at boundary b overwrites positions
+        // below b (read only before round b) with positions from b + RS - RF
+        // on (first read after round b + RS - RF - W - 2, more than six
+        // rounds later), and a check is valid after any round.
+        int next_refill = RF, next_check = kCheckRounds;
         bool done = false;
-        while (r < R) {
-            if (r > 0 && (r & (RF - 1)) == 0) {
-                const bool check = abandon && (r & (kCheckRounds - 1)) == 0;
-                if (check) {
-                    // the key loaded at the start of the item (a best-so-far only
-                    // decreases, so an older value is a safe threshold)
-                    const float thr = abandon_threshold(bsf_from_key(pend), a.gamma);
-                    // every warping path crosses one of the anti-diagonals 2r-2, 2r-1
-                    const bool over = vmin(vE, vO) > thr;
-                    const uint64_t bal = __ballot(over);
-                    if ((bal & gm) == gm) aband = true;
-                    if ((bal & valid_mask) == valid_mask) { done = true; break; }
-                }
-                // refill: positions r-RF+RS .. r+RS-1 (prefetched), then prefetch the next refill
+        auto boundary = [&](int r) __attribute__((always_inline)) -> bool {
+            if (abandon && r >= next_check) {
+                next_check += kCheckRounds;
+                // the key loaded at the start of the item (a best-so-far only
+                // decreases, so an older value is a safe threshold)
+                const float thr = abandon_threshold(bsf_from_key(pend), a.gamma);
+                // every warping path crosses one of the anti-diagonals 2r-2, 2r-1
+                const bool over = vmin(vE, vO) > thr;
+                const uint64_t bal = __ballot(over);
+                if ((bal & gm) == gm) aband = true;
+                if ((bal & valid_mask) == valid_mask) return true;
+            }
+            if (r >= next_refill) {
+                const int b = next_refill;
+                next_refill += RF;
+                // positions b-RF+RS .. b+RS-1 (prefetched), then prefetch the next refill
 #pragma unroll
                 for (int p = 0; p < MAXPASS; ++p) {
                     const int x = p * kWave + lane;
-                    if (x < nser * RF) put(x / RF, r - RF + RS + (x % RF), pf[p]);
+                    if (x < nser * RF) put(x / RF, b - RF + RS + (x % RF), pf[p]);
                 }
 #pragma unroll
                 for (int p = 0; p < MAXPASS; ++p) {
                     const int x = p * kWave + lane;
-                    if (x < nser * RF) fetch(x / RF, r + RS + (x % RF), pf[p]);
+                    if (x < nser * RF) fetch(x / RF, b + RS + (x % RF), pf[p]);
                 }
             }
-            const int qs = qbase + ((r + W - lg) & (RS - 1));
-            const int cs = cbase + ((r + lg + 1) & (RS - 1));
-            int qk[NCH], ck[NCH];
-#pragma unroll
-            for (int k = 0; k < NCH; ++k) { qk[k] = qs + k * STR; ck[k] = cs - 1 + k * STR; }
-            if (r + 4 <= R) {
-                diag_round<float, NCH, false, WODD>(qk, ck, 0, cA, cB, kill_e, kill_o, vE, vO, cw, 0);
-                diag_round<float, NCH, false, WODD>(qk, ck, 1, cB, cA, kill_e, kill_o, vE, vO, cw, 0);
-                diag_round<float, NCH, false, WODD>(qk, ck, 2, cA, cB, kill_e, kill_o, vE, vO, cw, 0);
-                diag_round<float, NCH, false, WODD>(qk, ck, 3, cB, cA, kill_e, kill_o, vE, vO, cw, 0);
-                r += 4;
-            } else {
-                diag_round<float, NCH, false, WODD>(qk, ck, 0, cA, cB, kill_e, kill_o, vE, vO, cw, 0);
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) cA[k] = cB[k];
-                r += 1;
+            return false;
+        };
+        // Six rounds per iteration, software-pipelined: each round loads the
+        // next round's query point and new candidate point before computing,
+        // so the LDS latency overlaps a round of arithmetic.  Two query and
+        // three candidate register sets rotate with period 6.  (Five sets of
+        // d > 16 dimensions do not fit: those launches run two rounds per
+        // iteration without prefetching.)
+        float4 Q0[NCH], Q1[NCH], C0[NCH], C1[NCH], C2[NCH];
+        ldc(0, C0);
+        ldq(0, Q0);
+        ldc(1, C1);
+        int r = 0;
+        if constexpr (NCH > 4) {
+            while (r + 2 <= R) {
+                if (boundary(r)) { done = true; break; }
+                ldq(r, Q0); ldc(r + 1, C1);
+                diag_steps_rot<NCH, WODD>(Q0, C0, C1, kill_e, kill_o, vE, vO);
+                ldq(r + 1, Q0); ldc(r + 2, C0);
+                diag_steps_rot<NCH, WODD>(Q0, C1, C0, kill_e, kill_o, vE, vO);
+                r += 2;
             }
+        }
+        while (NCH <= 4 && r + 6 <= R) {
+            if (boundary(r)) { done = true; break; }
+            ldq(r + 1, Q1); ldc(r + 2, C2);
+            diag_steps_rot<NCH, WODD>(Q0, C0, C1, kill_e, kill_o, vE, vO);
+            ldq(r + 2, Q0); ldc(r + 3, C0);
+            diag_steps_rot<NCH, WODD>(Q1, C1, C2, kill_e, kill_o, vE, vO);
+            ldq(r + 3, Q1); ldc(r + 4, C1);
+            diag_steps_rot<NCH, WODD>(Q0, C2, C0, kill_e, kill_o, vE, vO);
+            ldq(r + 4, Q0); ldc(r + 5, C2);
+            diag_steps_rot<NCH, WODD>(Q1, C0, C1, kill_e, kill_o, vE, vO);
+            ldq(r + 5, Q1); ldc(r + 6, C0);
+            diag_steps_rot<NCH, WODD>(Q0, C1, C2, kill_e, kill_o, vE, vO);
+            ldq(r + 6, Q0); ldc(r + 7, C1);
+            diag_steps_rot<NCH, WODD>(Q1, C2, C0, kill_e, kill_o, vE, vO);
+            r += 6;
+        }
+        // the remaining rounds one at a time (C0 holds round r's cin)
+        while (!done && r < R) {
+            if (boundary(r)) { done = true; break; }
+            ldq(r, Q0);
+            ldc(r + 1, C1);
+            diag_steps_rot<NCH, WODD>(Q0, C0, C1, kill_e, kill_o, vE, vO);
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) C0[k] = C1[k];
+            ++r;
         }
         (void)done;
         const int rounds = r;
@@ -701,6 +658,7 @@ hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s, bool init) {
     if (init)
         hipLaunchKernelGGL(k_knn_init, dim3((p.nq + 255) / 256 + 1), dim3(256), 0, s, p.nq, p.key, p.cnt,
                            p.gcnt, p.counters, p.stats, p.clear[0], p.clear[1], p.clear[2]);
+
     if (p.env) {
         const int64_t total = (int64_t)((p.nq + kQT - 1) / kQT) * kQT * (((int64_t)p.n * p.D + 3) / 4 * 4);
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
@@ -749,17 +707,30 @@ hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int 
     return hipGetLastError();
 }
 
+template <int NCH, int RS, int NPASS>
+static void launch_ring_w(const KnnDtwArgs& a, int nblocks, size_t lds, hipStream_t s) {
+    if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, RS, NPASS>), dim3(nblocks), dim3(64), lds, s, a);
+    else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, RS, NPASS>), dim3(nblocks), dim3(64), lds, s, a);
+}
+
+template <int NCH, int RS>
+static void launch_ring(const KnnDtwArgs& a, int npass, int nblocks, size_t lds, hipStream_t s) {
+    if (npass <= 1) launch_ring_w<NCH, RS, 1>(a, nblocks, lds, s);
+    else if (NCH <= 4 && npass == 2) launch_ring_w<NCH, RS, (NCH <= 4 ? 2 : 1)>(a, nblocks, lds, s);
+    else if (NCH <= 4) launch_ring_w<NCH, RS, (NCH <= 4 ? 3 : 1)>(a, nblocks, lds, s);
+}
+
 template <int NCH>
 static hipError_t launch_dtw_lists_nch(const KnnDtwArgs& a, bool rows, int nblocks, size_t lds,
                                        hipStream_t s) {
     if (rows) {
         hipLaunchKernelGGL(k_knn_dtw_rows<NCH>, dim3(nblocks), dim3(64), lds, s, a);
-    } else if (ring_size(a.W) == 64) {
-        if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, 64>), dim3(nblocks), dim3(64), lds, s, a);
-        else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, 64>), dim3(nblocks), dim3(64), lds, s, a);
     } else {
-        if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, 128>), dim3(nblocks), dim3(64), lds, s, a);
-        else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, 128>), dim3(nblocks), dim3(64), lds, s, a);
+        const int RS = ring_size(a.W);
+        const int npass = ((1 + a.P) * (RS / 4) + kWave - 1) / kWave;
+        if (npass > knn_ring_max_passes(NCH)) return hipErrorInvalidValue;
+        if (RS == 64) launch_ring<NCH, 64>(a, npass, nblocks, lds, s);
+        else launch_ring<NCH, 128>(a, npass, nblocks, lds, s);
     }
     return hipGetLastError();
 }
@@ -793,14 +764,16 @@ hipError_t launch_dtw_lists(const KnnDtwArgs& a, int nblocks, hipStream_t s) {
 size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P) {
     (void)m;
     if (W > kDiagMaxW) return rows_core_lds(n, nch_pad(D), 4);
-    return (size_t)(1 + P) * nch_pad(D) * (ring_size(W) + 8) * 16;
+    return (size_t)(1 + P) * ring_size(W) * nch_pad(D) * 16;
 }
+
+int knn_ring_max_passes(int nch) { return nch <= 4 ? 3 : 1; }
 
 int knn_dtw_max_pairs(int W, int D) {
     if (W > kDiagMaxW) return 1;
-    int P = kWave / (W + 1);
+    int P = kWave / knn_lane_stride(W);
     const int RF = ring_size(W) / 4;
-    const int maxpass = nch_pad(D) <= 4 ? 3 : 1;
+    const int maxpass = knn_ring_max_passes(nch_pad(D));
     while (P > 1 && (1 + P) * RF > maxpass * kWave) --P;
     return P;
 }

@@ -74,6 +74,19 @@ def test_cascade_prototypes_with_ties(dev, frac):
     assert idx[-3] == 3 and dist[-3] == 0.0
 
 
+@pytest.mark.parametrize("D", [20, 33, 64])
+def test_wide_dimensions(dev, D):
+    """d > 16: the diagonal kernel runs two rounds per iteration without
+    prefetching (six chunks and more); both window parities."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn(nq=6, nc=90, T=48, D=D, seed=27)
+    say("knn wide", D)
+    for frac in ((1, 10), (1, 9)):     # W = 4 and 5 at length 48
+        idx, dist, st = run_knn(dev, Q, Cs, frac=frac, bounds="mv")
+        check_against_oracle(idx, dist, Q, Cs, *frac)
+        assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
+
+
 def test_cascade_repeatable(dev):
     from paper_2101_07731_amd import synth
     Q, Cs = synth.cascade_knn(nq=30, nc=500, T=64, D=4, seed=22)
