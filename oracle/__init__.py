@@ -229,6 +229,29 @@ def knn_exhaustive(Q, Cs, window=0, num=0, den=0, threads=None):
     return idx, dist
 
 
+def knn_exhaustive_k(Q, Cs, k, window=0, num=0, den=0, threads=None):
+    """Plain k-NN (the 1-NN definition of Sec. 2 extended to the k nearest):
+    the float64 banded DTW of every (query, reference) pair, then per query
+    the k references with the smallest distance, ordered by (distance,
+    index) so that ties go to the lower index.
+    -> (idx int32 [nq, k], dist float64 [nq, k])."""
+    Qs = [np.asarray(q) for q in Q]
+    Rs = [np.asarray(c) for c in Cs]
+    nq, nc = len(Qs), len(Rs)
+    assert 1 <= k <= nc
+    xs = [q for q in Qs for _ in range(nc)]
+    ys = [c for _ in range(nq) for c in Rs]
+    d = dtw_pairs(xs, ys, window=window, num=num, den=den, threads=threads).reshape(nq, nc)
+    idx = np.zeros((nq, k), dtype=np.int32)
+    dist = np.zeros((nq, k), dtype=np.float64)
+    refs = np.arange(nc)
+    for i in range(nq):
+        order = np.lexsort((refs, d[i]))[:k]     # primary key: distance; then index
+        idx[i] = order
+        dist[i] = d[i, order]
+    return idx, dist
+
+
 def knn_cascade(Q, Cs, window=0, num=0, den=0, bounds=6, ti_P=5, ti_top=1, pc_Lv=2, pc_K=6,
                 pc_w=6, pc_floor=1e-5, e_ti=0.1, e_pc=0.1, threads=None):
     """The paper's sequential cascade -> (nn_idx, nn_dist, per-query stats dict of arrays)."""

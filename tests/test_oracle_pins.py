@@ -339,6 +339,31 @@ def test_knn_exhaustive_matches_brute_force():
     assert idx[-1] == 3 and dist[-1] == 0.0
 
 
+def test_knn_exhaustive_k_matches_brute_force():
+    """k nearest by brute-force path enumeration, ordered by (distance, index);
+    duplicated references make ties that must go to the lower index."""
+    rng = np.random.default_rng(23)
+    Q = [walk(rng, int(rng.integers(2, 6)), 2) for _ in range(4)]
+    Cs = [walk(rng, int(rng.integers(2, 6)), 2) for _ in range(10)]
+    Cs += [Cs[2].copy(), Cs[7].copy(), Cs[2].copy()]
+    Q.append(Cs[7] + 0.0)
+    for k in (1, 3, len(Cs)):
+        idx, dist = O.knn_exhaustive_k(Q, Cs, k, window=1)
+        assert idx.shape == (len(Q), k)
+        for a, q in enumerate(Q):
+            vals = [brute_force_dtw(q, c, max(1, abs(len(q) - len(c)))) for c in Cs]
+            want = sorted(range(len(Cs)), key=lambda r: (vals[r], r))[:k]
+            assert list(idx[a]) == want
+            np.testing.assert_allclose(dist[a], [vals[r] for r in want], rtol=1e-12, atol=1e-12)
+    idx1, dist1 = O.knn_exhaustive_k(Q, Cs, 1, window=1)
+    r1, d1 = O.knn_exhaustive(Q, Cs, window=1)
+    np.testing.assert_array_equal(idx1[:, 0], r1)
+    np.testing.assert_array_equal(dist1[:, 0], d1)
+    # the query equal to reference 7 (and to its copy, 11): 7 first, then 11, both at distance 0
+    idx3, dist3 = O.knn_exhaustive_k(Q, Cs, 3, window=1)
+    assert list(idx3[-1][:2]) == [7, 11] and dist3[-1][0] == 0.0 and dist3[-1][1] == 0.0
+
+
 @pytest.mark.parametrize("bounds", [0, 2, 4, 6])
 def test_cascade_equals_exhaustive(bounds):
     """The filtering cascade returns exactly the plain 1-NN (Sec. 7.2, soundness)."""
