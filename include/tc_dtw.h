@@ -290,7 +290,7 @@ typedef struct {
     float trigger_pc;       /* triggering threshold e of LB_PC */
     float prune_margin;     /* extra relative margin of every prune test (>= 0) */
     int32_t seed_r;         /* smallest-LB_MV candidates per query whose DTW seeds the best-so-far; 0: 4 */
-    int32_t k;              /* neighbours per query; must be 1 */
+    int32_t k;              /* neighbours per query, 1..32 (k > 1: uniform lengths only) */
 } tc_dtw_knn_params;
 
 void tc_dtw_knn_params_default(tc_dtw_knn_params* p);
@@ -308,19 +308,21 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
                                   const tc_dtw_knn_params* p, uint32_t kind, float* lb,
                                   void* ws, size_t ws_bytes, tc_dtw_stream stream);
 
-/* ---------------------------------------------------------------- 1-NN ---
- * tc_dtw_knn: for every query, the index of the candidate with the smallest
- * banded DTW (ties go to the lowest index) and that distance (Sec. 2
- * DTW-NN; Sec. 3 Definition 1).  The result equals an exhaustive float64
- * search: pruning and abandoning use rigorous float32 error bounds, and
- * every candidate whose float32 DTW lies within those bounds of the best is
- * re-scored in float64.
- *   nn_idx   DEVICE int32[queries->count]
- *   nn_dist  DEVICE float[queries->count] (the float64 DTW rounded to float32)
+/* ---------------------------------------------------------------- k-NN ---
+ * tc_dtw_knn: for every query, the indices of the p->k candidates with the
+ * smallest banded DTW, ordered by (distance, index) so that ties go to the
+ * lower index, and those distances (Sec. 2 DTW-NN; Sec. 3 Definition 1;
+ * k = 1 is the paper's nearest neighbour).  The result equals an exhaustive
+ * float64 search: pruning and abandoning compare against an upper bound of
+ * the k-th smallest distance with rigorous float32 error bounds, and every
+ * candidate whose float32 DTW lies within those bounds of the k-th smallest
+ * is re-scored in float64.
+ *   nn_idx   DEVICE int32[queries->count * k], row-major by query
+ *   nn_dist  DEVICE float[queries->count * k] (float64 DTW rounded to float32)
  *   stats    HOST or NULL.  When given, the call waits for the stream and
  *            fills the counters and per-stage times.
- * Errors: INVALID (dims differ, bad parameters), UNSUPPORTED (k != 1),
- * WORKSPACE, DEVICE. */
+ * Errors: INVALID (dims differ, k < 1 or k > candidates, bad parameters),
+ * UNSUPPORTED (k > 32; k > 1 with uneven lengths), WORKSPACE, DEVICE. */
 typedef struct {
     uint64_t pairs;          /* query-candidate pairs */
     uint64_t pruned_mv;      /* pairs skipped by LB_MV */

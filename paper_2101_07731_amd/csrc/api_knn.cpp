@@ -48,7 +48,8 @@ static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
     if (!p) return fail(TC_DTW_ERR_INVALID, "null params");
     tc_dtw_status st = check_window(p->window);
     if (st != TC_DTW_OK) return st;
-    if (p->k != 1) return fail(TC_DTW_ERR_UNSUPPORTED, "only k = 1 is supported");
+    if (p->k < 1) return fail(TC_DTW_ERR_INVALID, "k must be >= 1");
+    if (p->k > kMaxK) return fail(TC_DTW_ERR_UNSUPPORTED, "k is limited to 32");
     if (p->bounds & ~(TC_DTW_LB_MV | TC_DTW_LB_PC | TC_DTW_LB_TI))
         return fail(TC_DTW_ERR_INVALID, "unknown bound bits");
     if ((p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)) && !(p->bounds & TC_DTW_LB_MV))
@@ -63,12 +64,12 @@ static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
 
 // Everything a uniform search needs, with workspace offsets.
 struct KnnPlan {
-    int nq, nc, m, n, D, W, R, P, cap, ntiles;
+    int nq, nc, m, n, D, W, R, P, cap, ntiles, k;
     bool plain, abandon, gate, pc, ti;
     int ngroups, max_pts;
     size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
         o_items, o_counters, o_key, o_stats, o_boxes, o_nbox, o_qstep, o_glb, o_tlist, o_tlb, o_tout,
-        o_tcnt, o_ppc, o_pti, o_cntmv, o_part, bytes;
+        o_tcnt, o_ppc, o_pti, o_cntmv, o_part, o_topk, bytes;
     int nseg = 1;
 };
 
@@ -97,7 +98,10 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.ti = (p->bounds & TC_DTW_LB_TI) != 0;
     K.ngroups = (K.n + p->pc_group - 1) / p->pc_group;
     K.max_pts = std::min(K.m, p->pc_group + 2 * K.W);
-    K.R = K.plain ? 0 : std::min(std::min(p->seed_r > 0 ? p->seed_r : 4, kMaxSeeds), K.nc);
+    K.k = p->k;
+    if (K.k > K.nc) return fail(TC_DTW_ERR_INVALID, "k exceeds the number of candidates");
+    // at least k seeds, so that the k-th best is finite before the compaction
+    K.R = K.plain ? 0 : std::min(std::min(std::max(p->seed_r > 0 ? p->seed_r : 4, K.k), kMaxSeeds), K.nc);
     K.P = knn_dtw_max_pairs(K.W, K.D);
     K.cap = K.nc;
     K.ntiles = ix->ntiles;
@@ -133,6 +137,7 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.o_cntmv = at((size_t)K.nq * 4);
     K.nseg = K.plain ? 1 : lb_mv_segments(K.ntiles, K.nq, K.n * K.D);
     K.o_part = at(K.nseg > 1 ? (size_t)K.nseg * K.nq * K.nc * 4 : 0);
+    K.o_topk = at(K.k > 1 ? (size_t)K.nq * K.k * 8 : 0);
     K.bytes = c.need();
     {
         // the boxes of one expanded window are built in LDS; its cell keys need Lv^D < 2^63
@@ -180,6 +185,8 @@ static KnnPlanDev dev_plan(const KnnPlan& K, const tc_dtw_index* ix, const HostS
     d.stats = reinterpret_cast<unsigned long long*>(ws + K.o_stats);
     d.nseg = K.nseg;
     d.part = K.nseg > 1 ? reinterpret_cast<float*>(ws + K.o_part) : nullptr;
+    d.k = K.k;
+    d.topk = K.k > 1 ? reinterpret_cast<unsigned long long*>(ws + K.o_topk) : nullptr;
     return d;
 }
 
@@ -264,6 +271,7 @@ static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, b
     std::memset(&a, 0, sizeof a);
     a.Q = d.Q; a.C = d.C;
     a.nq = K.nq; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W; a.P = K.P; a.gs = knn_lane_stride(K.W);
+    a.k = K.k; a.topk = d.topk;
     if (seeds) {
         a.list = reinterpret_cast<const uint32_t*>(d.seeds);
         a.list_dist = d.seed_dist;
@@ -317,6 +325,7 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     if (Qs.dim != ix->dim) return fail(TC_DTW_ERR_INVALID, "queries and index have different dims");
     if (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI))
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI need uniform query and candidate lengths");
+    if (p->k > 1) return fail(TC_DTW_ERR_UNSUPPORTED, "k > 1 needs uniform query and candidate lengths");
     K = RaggedPlan();
     K.nq = Qs.count;
     K.nc = ix->count;
@@ -735,6 +744,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         f.nc = K.nc;
         const double g = dp_gamma(K.m, K.n, K.D);
         f.ratio = (1.0 + g) / (1.0 - g) * (1.0 + 1e-9);
+        f.k = K.k;
         f.nn_idx = nn_idx; f.nn_dist = nn_dist;
         f.stats = d.stats;
         if ((e = launch_knn_finalize(f, s)) != hipSuccess) return hip_fail(e, "finalize");

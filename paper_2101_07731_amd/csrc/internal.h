@@ -117,7 +117,8 @@ hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s);
 // different queries do not queue on shared lines.
 constexpr int kKeyStride = 16;   // u64 words
 constexpr int kQT = 8;           // queries per LB_MV tile
-constexpr int kMaxSeeds = 8;
+constexpr int kMaxSeeds = 32;
+constexpr int kMaxK = 32;           // largest k of a k-nearest-neighbour search
 constexpr int kNumCounters = 8;
 constexpr int kNumStats = 16;
 enum {
@@ -148,6 +149,8 @@ struct KnnPlanDev {
     int32_t* clear[3];    // optional extra per-query counters zeroed with the others
     float* part;          // LB_MV partial sums [nseg][nq][nc] when nseg > 1, else null
     int32_t nseg;
+    unsigned long long* topk;   // [nq][k] keys of the k best candidates so far (k > 1), else null
+    int32_t k;
 };
 // Element segments of the LB_MV launch (more when few query tiles would leave HBM idle).
 int lb_mv_segments(int ntiles, int nq, int E);
@@ -158,6 +161,8 @@ struct KnnDtwArgs {
     const float* C;
     int32_t nq, m, n, D, W, P;
     int32_t gs;                // lanes per pair group (knn_lane_stride)
+    unsigned long long* topk;  // [nq][k] keys of the k best so far (k > 1); key[] then holds their largest
+    int32_t k;
     const uint32_t* list;      // [nq][cap] candidate indices (negative: none)
     float* list_dist;          // [nq][cap] float32 DTW, +inf when abandoned
     const int32_t* cnt;        // [nq] list lengths (unless cnt_uniform > 0)
@@ -187,7 +192,8 @@ struct KnnFinalArgs {
     const int32_t* pruned_pc;  // [nq] or null
     const int32_t* pruned_ti;  // [nq] or null
     int32_t nc;
-    double ratio;              // finalists: float32 DTW <= smallest * ratio
+    double ratio;              // finalists: float32 DTW <= k-th smallest * ratio
+    int32_t k;                 // neighbours per query; nn_idx / nn_dist are [nq][k]
     int32_t* nn_idx;
     float* nn_dist;
     unsigned long long* stats;

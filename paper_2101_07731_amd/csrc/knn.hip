@@ -25,8 +25,11 @@ namespace tcdtw {
 // ------------------------------------------------------------------ setup
 __global__ void k_knn_init(int nq, unsigned long long* key, int32_t* cnt, int32_t* gcnt,
                            int32_t* counters, unsigned long long* stats, int32_t* c0, int32_t* c1,
-                           int32_t* c2) {
+                           int32_t* c2, unsigned long long* topk, int k) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (topk)
+        for (int64_t x = t; x < (int64_t)nq * k; x += (int64_t)gridDim.x * blockDim.x)
+            topk[x] = 0x7f800000ffffffffull;
     for (int q = t; q < nq; q += gridDim.x * blockDim.x) {
         key[(int64_t)q * kKeyStride] = 0x7f800000ffffffffull;     // best-so-far +inf, no candidate yet
         cnt[q] = 0;
@@ -294,10 +297,52 @@ __device__ __forceinline__ int find_query(const int32_t* prefix, int nq, int ite
     return lo;
 }
 
-__device__ __forceinline__ void publish(const KnnDtwArgs& a, int q, int ref, float v, float gamma) {
+// k > 1: the query's k slots hold the packed keys of k distinct computed
+// candidates (initially +inf); a new key replaces the largest slot when it
+// is smaller (compare-and-swap, retried while other inserts change the
+// slots: every failure is another insert's success, so the loop ends).
+// The query's threshold key then drops to the largest slot: an upper bound
+// of the k-th smallest exact distance, since every slot bounds a distinct
+// candidate's distance from above.  Wave-cooperative (the whole wave calls
+// it with the same arguments): lane i reads slot i, so a pass over the
+// slots is one round trip of coherent loads.
+__device__ __forceinline__ void topk_insert_wave(unsigned long long* slots, int K, unsigned long long x,
+                                                 unsigned long long* thr) {
+    const int lane = threadIdx.x & 63;
+    auto wave_max = [&](unsigned long long& v, int& at) __attribute__((always_inline)) {
+        v = lane < K ? __hip_atomic_load(slots + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+        at = lane;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const unsigned long long ov = __shfl_xor(v, o);
+            const int oa = __shfl_xor(at, o);
+            if (ov > v || (ov == v && oa < at)) { v = ov; at = oa; }
+        }
+    };
+    for (;;) {
+        unsigned long long mx;
+        int mi;
+        wave_max(mx, mi);
+        if (x >= mx) return;
+        unsigned long long old = 0;
+        if (lane == 0) old = atomicCAS(slots + mi, mx, x);
+        if (__shfl(old, 0) == mx) break;
+    }
+    unsigned long long m2;
+    int at;
+    wave_max(m2, at);
+    if (lane == 0) atomicMin(thr, m2);
+}
+
+// Publishes an upper bound of the exact DTW of (q, ref), D <= v / (1 - gamma),
+// as the query's best-so-far key (1-NN; one lane) or into its k best (k-NN;
+// the whole wave with the same arguments).
+__device__ __forceinline__ unsigned long long dist_key(float v, float gamma, int ref) {
     const float up = round_up_pos((double)v / (1.0 - (double)gamma));
-    const unsigned long long k = ((unsigned long long)__float_as_uint(up) << 32) | (uint32_t)ref;
-    atomicMin(&a.key[(int64_t)q * kKeyStride], k);
+    return ((unsigned long long)__float_as_uint(up) << 32) | (uint32_t)ref;
+}
+__device__ __forceinline__ void publish(const KnnDtwArgs& a, int q, int ref, float v, float gamma) {
+    atomicMin(&a.key[(int64_t)q * kKeyStride], dist_key(v, gamma, ref));
 }
 
 // Diagonal mapping with ring buffers: each staged series keeps only RS
@@ -487,14 +532,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && 
         const int rounds = r;
         const int sigma = (a.n - a.m) + 2 * h;
         const int myref = spare ? -1 : (int)a.list[(int64_t)q * a.cap + base + grp];
-        if (!spare && lg == (sigma >> 1)) {
-            const float v = (sigma & 1) ? vO : vE;
+        const bool res_lane = !spare && lg == (sigma >> 1);
+        const float res = (sigma & 1) ? vO : vE;
+        if (res_lane) {
             float out = __builtin_inff();
             if (!aband && myref >= 0) {
-                out = v;
-                publish(a, q, myref, v, a.gamma);
+                out = res;
+                if (a.k <= 1) publish(a, q, myref, res, a.gamma);
             }
             a.list_dist[(int64_t)q * a.cap + base + grp] = out;
+        }
+        if (a.k > 1) {   // k-NN: one wave-cooperative insert per finished pair
+            uint64_t pend_groups = __ballot(res_lane && !aband && myref >= 0);
+            while (pend_groups) {
+                const int src = __builtin_ctzll(pend_groups);
+                pend_groups &= pend_groups - 1;
+                const unsigned long long key = __shfl(dist_key(res, a.gamma, myref), src);
+                topk_insert_wave(a.topk + (int64_t)q * a.k, a.k, key, &a.key[(int64_t)q * kKeyStride]);
+            }
         }
         const uint64_t bstart = __ballot(!spare && lg == 0 && myref >= 0);
         const uint64_t bab = __ballot(aband && !spare && lg == 0 && myref >= 0);
@@ -538,13 +593,18 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
         else
             v = rows_core<float, NCH, false, false>(sc, a.Q + (int64_t)q * a.m * a.D, cser, a.m,
                                                     a.n, a.W, a.D, lane, nullptr, ab, aband, &blocks);
-        if (lane == (a.m - 1) % kRowBlock) {
+        const int rl = (a.m - 1) % kRowBlock;
+        if (lane == rl) {
             float out = __builtin_inff();
             if (!aband && ref >= 0) {
                 out = v;
-                publish(a, q, ref, v, a.gamma);
+                if (a.k <= 1) publish(a, q, ref, v, a.gamma);
             }
             a.list_dist[(int64_t)q * a.cap + e] = out;
+        }
+        if (a.k > 1 && __shfl((int)(!aband && ref >= 0), rl)) {   // k-NN: wave-cooperative insert
+            const unsigned long long key = __shfl(dist_key(v, a.gamma, ref), rl);
+            topk_insert_wave(a.topk + (int64_t)q * a.k, a.k, key, &a.key[(int64_t)q * kKeyStride]);
         }
         if (ref >= 0) {
             const int nb = (a.m + kRowBlock - 1) / kRowBlock;
@@ -562,21 +622,51 @@ __global__ __launch_bounds__(64) void k_knn_dtw_rows(KnnDtwArgs a) {
 }
 
 // ---------------------------------------------------------------- finalize
-// One wave per query: the smallest float32 DTW over the seeds and the
-// survivors, then a float64 re-scoring of every candidate within
-// (1 + g) / (1 - g) of it; the smallest float64 value wins, ties to the
-// lowest candidate index.
+// One wave per query: the k-th smallest float32 DTW over the seeds and the
+// survivors (k = 1: the smallest), then a float64 re-scoring of every
+// candidate within (1 + g) / (1 - g) of it; the k smallest float64 values
+// win, ties to the lowest candidate index.  (A candidate among the exact k
+// nearest has exact DTW at most the k-th exact distance, which is at most
+// the k-th smallest v / (1 - g); so its float value is at most that times
+// (1 + g).  Pruned and abandoned candidates exceed the k-th exact distance.)
 template <int NCH, bool WODD, bool ROWS>
 __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
     const int q = blockIdx.x, lane = threadIdx.x;
-    float mn = __builtin_inff();
-    const int ns = a.R, nl = a.cnt[q];
-    for (int k = lane; k < ns; k += kWave)
-        if (a.seeds[(int64_t)q * ns + k] >= 0) mn = __builtin_fminf(mn, a.seed_dist[(int64_t)q * ns + k]);
-    for (int k = lane; k < nl; k += kWave) mn = __builtin_fminf(mn, a.list_dist[(int64_t)q * a.cap + k]);
+    const int ns = a.R, nl = a.cnt[q], K = a.k;
+    // the k-th smallest float32 value over the seeds and the list: K rounds,
+    // each taking the smallest (value, slot) after the previous one
+    float kth = __builtin_inff();
+    {
+        float pv = -__builtin_inff();
+        int ps = -1, found = 0;
+        for (int t = 0; t < K; ++t) {
+            float bv = __builtin_inff();
+            int bs = 0x7fffffff;
+            for (int x = lane; x < ns + nl; x += kWave) {
+                const bool ok = x < ns ? a.seeds[(int64_t)q * ns + x] >= 0 : true;
+                const float v = x < ns ? a.seed_dist[(int64_t)q * ns + x] : a.list_dist[(int64_t)q * a.cap + x - ns];
+                if (ok && v < __builtin_inff() && (v > pv || (v == pv && x > ps)) && (v < bv || (v == bv && x < bs))) {
+                    bv = v;
+                    bs = x;
+                }
+            }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fminf(mn, __shfl_xor(mn, o));
-    const double thr = (double)mn * a.ratio;
+            for (int o = 32; o >= 1; o >>= 1) {
+                const float ov = __shfl_xor(bv, o);
+                const int os = __shfl_xor(bs, o);
+                if (ov < bv || (ov == bv && os < bs)) { bv = ov; bs = os; }
+            }
+            if (bs == 0x7fffffff) break;
+            pv = bv; ps = bs;
+            ++found;
+        }
+        if (found == K) kth = pv;
+    }
+    const double thr = (double)kth * a.ratio;
+    // the k best (float64 value, index) so far, ascending; kept by lane 0
+    __shared__ double tk_v[kMaxK];
+    __shared__ int tk_i[kMaxK];
+    int tk_n = 0;
 
     double best = __builtin_inf();
     int bestidx = 0x7fffffff;
@@ -635,12 +725,31 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
                 }
                 ++rescored;
                 if (v < best || (v == best && r < bestidx)) { best = v; bestidx = r; }
+                if (K > 1 && lane == 0 &&
+                    (tk_n < K || v < tk_v[K - 1] || (v == tk_v[K - 1] && r < tk_i[K - 1]))) {
+                    int pos = tk_n < K ? tk_n : K - 1;
+                    while (pos > 0 && (tk_v[pos - 1] > v || (tk_v[pos - 1] == v && tk_i[pos - 1] > r))) {
+                        tk_v[pos] = tk_v[pos - 1];
+                        tk_i[pos] = tk_i[pos - 1];
+                        --pos;
+                    }
+                    tk_v[pos] = v;
+                    tk_i[pos] = r;
+                    if (tk_n < K) ++tk_n;
+                }
             }
         }
     }
     if (lane == 0) {
-        a.nn_idx[q] = bestidx == 0x7fffffff ? -1 : bestidx;
-        a.nn_dist[q] = (float)best;
+        if (K == 1) {
+            a.nn_idx[q] = bestidx == 0x7fffffff ? -1 : bestidx;
+            a.nn_dist[q] = (float)best;
+        } else {
+            for (int t = 0; t < K; ++t) {
+                a.nn_idx[(int64_t)q * K + t] = t < tk_n ? tk_i[t] : -1;
+                a.nn_dist[(int64_t)q * K + t] = t < tk_n ? (float)tk_v[t] : __builtin_inff();
+            }
+        }
         atomicAdd(&a.stats[kStRescored], (unsigned long long)rescored);
         int nseeds = 0;
         for (int k = 0; k < ns; ++k) nseeds += a.seeds[(int64_t)q * ns + k] >= 0;
@@ -657,7 +766,7 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
 hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s, bool init) {
     if (init)
         hipLaunchKernelGGL(k_knn_init, dim3((p.nq + 255) / 256 + 1), dim3(256), 0, s, p.nq, p.key, p.cnt,
-                           p.gcnt, p.counters, p.stats, p.clear[0], p.clear[1], p.clear[2]);
+                           p.gcnt, p.counters, p.stats, p.clear[0], p.clear[1], p.clear[2], p.topk, p.k);
 
     if (p.env) {
         const int64_t total = (int64_t)((p.nq + kQT - 1) / kQT) * kQT * (((int64_t)p.n * p.D + 3) / 4 * 4);
@@ -696,7 +805,8 @@ hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s) {
 }
 
 hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_topr<kMaxSeeds>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.seeds);
+    if (p.R <= 8) hipLaunchKernelGGL(k_topr<8>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.seeds);
+    else hipLaunchKernelGGL(k_topr<kMaxSeeds>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.seeds);
     return hipGetLastError();
 }
 

@@ -62,14 +62,17 @@ def lower_bounds(index, queries, kind="mv", **kw):
     return lb
 
 
-def knn(index, queries, stats=False, workspace=None, **kw):
-    """1-NN of every query: (nn_idx int32 [nq], nn_dist float32 [nq][, stats dict])."""
+def knn(index, queries, stats=False, workspace=None, k=1, **kw):
+    """k nearest neighbours of every query: (nn_idx int32, nn_dist float32
+    [, stats dict]), shaped [nq] for k = 1 and [nq, k] otherwise (ascending
+    distance, ties to the lower index)."""
     Q = SeriesSet(queries)
-    p = params(**kw)
+    p = params(k=k, **kw)
     lib = L.lib()
     dev = Q.flat.device
-    idx = torch.empty(Q.count, dtype=torch.int32, device=dev)
-    dist = torch.empty(Q.count, dtype=torch.float32, device=dev)
+    shape = (Q.count,) if k == 1 else (Q.count, k)
+    idx = torch.empty(shape, dtype=torch.int32, device=dev)
+    dist = torch.empty(shape, dtype=torch.float32, device=dev)
     wsb = lib.tc_dtw_knn_workspace_bytes(C.byref(index.ix), C.byref(Q.batch), C.byref(p))
     if wsb == 0:
         L.check(lib.tc_dtw_knn(C.byref(index.ix), C.byref(Q.batch), C.byref(p), None, None, None, None, 0,

@@ -130,3 +130,41 @@ def test_search_calls_need_one_dim():
     assert lib.tc_dtw_index_bytes(C.byref(refs)) == 0
     st = lib.tc_dtw_build_index(C.byref(refs), C.c_void_p(0x2000), 1 << 20, C.byref(L.Index()), None)
     assert st == L.ERR_UNSUPPORTED
+
+
+def test_k_validated_on_the_host():
+    """k-NN: k in 1..32 and at most the number of candidates; k > 1 needs
+    uniform lengths.  Checked from the index description and the query
+    shape alone (no device memory is touched)."""
+    lib = L.lib()
+    ix = L.Index()
+    ix.buf = C.c_void_p(0x4000)
+    ix.bytes = 1 << 20
+    ix.count = 10
+    ix.dim = 2
+    ix.uniform_len = 8
+    ix.max_len = 8
+    ix.ntiles = 1
+    Q = L.Batch(0x1000, None, None, 3, 2, 8, None)     # 3 queries of length 8, dim 2
+    def ws(k):
+        p = L.KnnParams()
+        lib.tc_dtw_knn_params_default(C.byref(p))
+        p.k = k
+        return lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q), C.byref(p)), p
+    assert ws(1)[0] > 0 and ws(5)[0] > ws(1)[0] and ws(10)[0] > 0
+    for bad in (0, -1, 11, 33):
+        assert ws(bad)[0] == 0
+    _, p = ws(33)
+    st = lib.tc_dtw_knn(C.byref(ix), C.byref(Q), C.byref(p), C.c_void_p(0x100), C.c_void_p(0x200), None,
+                        C.c_void_p(0x300), 1 << 20, None)
+    assert st == L.ERR_UNSUPPORTED
+    _, p = ws(11)
+    st = lib.tc_dtw_knn(C.byref(ix), C.byref(Q), C.byref(p), C.c_void_p(0x100), C.c_void_p(0x200), None,
+                        C.c_void_p(0x300), 1 << 20, None)
+    assert st == L.ERR_INVALID
+    # uneven query lengths (a ragged search) with k > 1
+    lens = (C.c_int32 * 3)(8, 6, 7)
+    offs = (C.c_int64 * 3)(0, 16, 28)
+    Qr = L.Batch(0x1000, offs, lens, 3, 2, 0, None)
+    _, p = ws(2)
+    assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Qr), C.byref(p)) == 0

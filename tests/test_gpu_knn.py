@@ -87,6 +87,50 @@ def test_wide_dimensions(dev, D):
         assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
 
 
+@pytest.mark.parametrize("k", [2, 5, 16, 32])
+def test_k_nearest_against_oracle(dev, k):
+    """k > 1: the k nearest in (distance, index) order, with duplicate
+    references (ties) and queries equal to a reference, for the plain
+    method, LB_MV and the full cascade."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn(nq=10, nc=280, T=64, D=4, seed=28)
+    Cs = np.concatenate([Cs, Cs[::9]])
+    Q = np.concatenate([Q, Cs[[5, 250]]])
+    ri, rd = O.knn_exhaustive_k(Q, Cs, k, num=1, den=10)
+    for bounds in ("plain", "mv", "mv+pc+ti"):
+        say("knn k", k, bounds)
+        idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds=bounds, k=k)
+        assert idx.shape == (len(Q), k)
+        np.testing.assert_array_equal(idx, ri)
+        np.testing.assert_array_equal(dist, rd.astype(np.float32))
+        assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == st["pairs"]
+    assert idx[-2][0] == 5 and dist[-2][0] == 0.0
+
+
+def test_k_nearest_row_mapping(dev):
+    """k > 1 with a band wider than 63 (row-systolic DTW)."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.long_knn(nq=3, nc=40, T=700, D=3, seed=29)
+    ri, rd = O.knn_exhaustive_k(Q, Cs, 4, num=1, den=10)
+    idx, dist, _ = run_knn(dev, Q, Cs, frac=(1, 10), bounds="mv", k=4)
+    np.testing.assert_array_equal(idx, ri)
+    np.testing.assert_array_equal(dist, rd.astype(np.float32))
+
+
+def test_k_nearest_full_size_sampled(dev):
+    """k = 10 on the benchmark's workload (1000 x 10000, length 256, d = 8,
+    window 10%), sampled queries against the oracle."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn()
+    idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds="mv", k=10)
+    say("knn k=10 full size", st)
+    sample = np.array([0, 421, 999])
+    ri, rd = O.knn_exhaustive_k(Q[sample], Cs, 10, num=1, den=10)
+    np.testing.assert_array_equal(idx[sample], ri)
+    np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
+    assert np.all(np.diff(dist, axis=1) >= 0)
+
+
 def test_cascade_repeatable(dev):
     from paper_2101_07731_amd import synth
     Q, Cs = synth.cascade_knn(nq=30, nc=500, T=64, D=4, seed=22)
