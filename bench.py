@@ -42,7 +42,7 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "total")
 
-EXTRAS = ("full_cascade", "cascade_setup", "knn_k10", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
+EXTRAS = ("full_cascade", "cascade_setup", "knn_k10", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
           "lb_mv_streaming", "plain_gpu")
 
 
@@ -341,6 +341,33 @@ def main():
                           "pct_dtw_pruned": round(100.0 * (1 - st10["dtw_started"] / st10["pairs"]), 3),
                           "rescored": st10["rescored"],
                           "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, st10["stage_ms"])}}
+    if "single_query_latency" in extras:
+        # queries arriving one at a time (Sec. 7.1): one tc_dtw_knn call per query against the
+        # same index; GPU time from events around each call, wall time including the host side
+        ws1 = torch.empty(search.knn_workspace_bytes(ix, Qd[:1], **kw), dtype=torch.uint8, device=dev)
+        for i in range(5):
+            search.knn(ix, Qd[i:i + 1], workspace=ws1, **kw)
+        torch.cuda.synchronize()
+        gpu_ms, wall_ms = [], []
+        for i in range(100):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            search.knn(ix, Qd[i:i + 1], workspace=ws1, **kw)
+            e1.record()
+            e1.synchronize()
+            wall_ms.append((time.perf_counter() - t0) * 1e3)
+            gpu_ms.append(e0.elapsed_time(e1))
+        stg = []
+        for i in range(20):
+            stg.append(search.knn(ix, Qd[i:i + 1], workspace=ws1, stats=True, **kw)[2]["stage_ms"])
+        out["single_query_latency"] = {
+            "queries": 100, "references": int(ix.count),
+            "stage_ms_mean": {n: round(float(np.mean([x[j] for x in stg])), 4) for j, n in enumerate(STAGES)},
+            "gpu_ms_p50": round(float(np.percentile(gpu_ms, 50)), 4),
+            "gpu_ms_p99": round(float(np.percentile(gpu_ms, 99)), 4),
+            "wall_ms_p50": round(float(np.percentile(wall_ms, 50)), 4),
+            "wall_ms_p99": round(float(np.percentile(wall_ms, 99)), 4)}
     if "cascade_setup" in extras:
         # setup-stage choice of bounds and triggers on a sample of 100 queries (Sec. 6)
         best, times = search.tune_cascade(ix, Qd[:100], frac=frac)
