@@ -229,19 +229,39 @@ def knn_exhaustive(Q, Cs, window=0, num=0, den=0, threads=None):
     return idx, dist
 
 
-def knn_exhaustive_k(Q, Cs, k, window=0, num=0, den=0, threads=None):
+def dtw_indep(q, c, weff):
+    """Independent multivariate DTW (Sec. 2: DTW_I): the univariate banded
+    DTW of every dimension with its own warping path, summed over the
+    dimensions in increasing order."""
+    q, c = _series(q), _series(c)
+    total = 0.0
+    for p in range(q.shape[1]):
+        total = total + dtw(q[:, p:p + 1], c[:, p:p + 1], weff)
+    return total
+
+
+def knn_exhaustive_k(Q, Cs, k, window=0, num=0, den=0, threads=None, independent=False):
     """Plain k-NN (the 1-NN definition of Sec. 2 extended to the k nearest):
-    the float64 banded DTW of every (query, reference) pair, then per query
-    the k references with the smallest distance, ordered by (distance,
-    index) so that ties go to the lower index.
-    -> (idx int32 [nq, k], dist float64 [nq, k])."""
+    the float64 banded DTW of every (query, reference) pair -- dependent
+    (one warping path for all dimensions) or, with `independent`, DTW_I as
+    in dtw_indep -- then per query the k references with the smallest
+    distance, ordered by (distance, index) so that ties go to the lower
+    index.  -> (idx int32 [nq, k], dist float64 [nq, k])."""
     Qs = [np.asarray(q) for q in Q]
     Rs = [np.asarray(c) for c in Cs]
     nq, nc = len(Qs), len(Rs)
     assert 1 <= k <= nc
     xs = [q for q in Qs for _ in range(nc)]
     ys = [c for _ in range(nq) for c in Rs]
-    d = dtw_pairs(xs, ys, window=window, num=num, den=den, threads=threads).reshape(nq, nc)
+    if independent:
+        D = Qs[0].shape[1]
+        d = np.zeros(nq * nc)
+        for p in range(D):   # per-dimension DTWs added in increasing dimension order
+            d = d + dtw_pairs([x[:, p:p + 1] for x in xs], [y[:, p:p + 1] for y in ys], window=window,
+                              num=num, den=den, threads=threads)
+        d = d.reshape(nq, nc)
+    else:
+        d = dtw_pairs(xs, ys, window=window, num=num, den=den, threads=threads).reshape(nq, nc)
     idx = np.zeros((nq, k), dtype=np.int32)
     dist = np.zeros((nq, k), dtype=np.float64)
     refs = np.arange(nc)

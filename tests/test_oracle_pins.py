@@ -364,6 +364,42 @@ def test_knn_exhaustive_k_matches_brute_force():
     assert list(idx3[-1][:2]) == [7, 11] and dist3[-1][0] == 0.0 and dist3[-1][1] == 0.0
 
 
+def test_dtw_indep_pins():
+    """DTW_I (Sec. 2): brute force per dimension summed; d = 1 is plain DTW;
+    DTW_I <= DTW_D (each dimension may take its own path) and LB_MV <= DTW_I
+    (LB_MV is a sum of per-dimension envelope bounds)."""
+    rng = np.random.default_rng(31)
+    for m, n in ((4, 5), (6, 6), (3, 6)):
+        for D in (1, 2, 3):
+            q, c = walk(rng, m, D), walk(rng, n, D)
+            for W in (0, 1, 3):
+                weff = O.window_eff(m, n, W)
+                bf = sum(brute_force_dtw(q[:, p:p + 1], c[:, p:p + 1], weff) for p in range(D))
+                got = O.dtw_indep(q, c, weff)
+                assert got == pytest.approx(bf, rel=1e-12, abs=1e-12)
+                if D == 1:
+                    assert got == O.dtw(q, c, weff)
+                assert got <= O.dtw(q, c, weff) * (1 + 1e-12) + 1e-12
+                assert O.lb_mv(q, c, weff) <= got * (1 + 1e-12) + 1e-12
+    # a case where the dimensions prefer different alignments: DTW_I < DTW_D strictly
+    q = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    c = np.array([[0.0, 0.0], [0.0, 1.0], [1.0, 0.0]])
+    assert O.dtw_indep(q, c, 2) < O.dtw(q, c, 2)
+
+
+def test_knn_exhaustive_k_independent():
+    rng = np.random.default_rng(37)
+    Q = [walk(rng, 5, 3) for _ in range(3)]
+    Cs = [walk(rng, 5, 3) for _ in range(8)]
+    Cs.append(Cs[4].copy())
+    idx, dist = O.knn_exhaustive_k(Q, Cs, 3, window=1, independent=True)
+    for a, q in enumerate(Q):
+        vals = [O.dtw_indep(q, c, 1) for c in Cs]
+        want = sorted(range(len(Cs)), key=lambda r: (vals[r], r))[:3]
+        assert list(idx[a]) == want
+        np.testing.assert_array_equal(dist[a], [vals[r] for r in want])
+
+
 @pytest.mark.parametrize("bounds", [0, 2, 4, 6])
 def test_cascade_equals_exhaustive(bounds):
     """The filtering cascade returns exactly the plain 1-NN (Sec. 7.2, soundness)."""
