@@ -42,7 +42,7 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "total")
 
-EXTRAS = ("full_cascade", "cascade_setup", "knn_k10", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
+EXTRAS = ("full_cascade", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
           "lb_mv_streaming", "plain_gpu")
 
 
@@ -341,6 +341,18 @@ def main():
                           "pct_dtw_pruned": round(100.0 * (1 - st10["dtw_started"] / st10["pairs"]), 3),
                           "rescored": st10["rescored"],
                           "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, st10["stage_ms"])}}
+    if "knn_independent" in extras:
+        # independent DTW (Sec. 2 DTW_I) on the same workload, LB_MV bounds
+        sti = {}
+
+        def indep():
+            sti.update(search.knn(ix, Qd, stats=True, independent=1, **kw)[2])
+
+        msi = _events_ms(indep, 3)
+        out["knn_independent"] = {"queries_per_s": round(nq / (msi * 1e-3), 2), "ms": round(msi, 3),
+                                  "pct_dtw_pruned": round(100.0 * (1 - sti["dtw_started"] / sti["pairs"]), 3),
+                                  "dtw_gcups": round(sti["cells"] / (sti["stage_ms"][5] * 1e-3) / 1e9, 2),
+                                  "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, sti["stage_ms"])}}
     if "single_query_latency" in extras:
         # queries arriving one at a time (Sec. 7.1): one tc_dtw_knn call per query against the
         # same index; GPU time from events around each call, wall time including the host side

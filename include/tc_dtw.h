@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define TC_DTW_ABI_VERSION 2
+#define TC_DTW_ABI_VERSION 3
 
 typedef struct ihipStream_t* tc_dtw_stream; /* same type as hipStream_t; NULL = default stream */
 
@@ -291,6 +291,10 @@ typedef struct {
     float prune_margin;     /* extra relative margin of every prune test (>= 0) */
     int32_t seed_r;         /* smallest-LB_MV candidates per query whose DTW seeds the best-so-far; 0: 4 */
     int32_t k;              /* neighbours per query, 1..32 (k > 1: uniform lengths only) */
+    int32_t independent;    /* 0: dependent DTW (one warping path for all dimensions, Sec. 2 DTW_D,
+                               the paper's subject); 1: independent DTW (Sec. 2 DTW_I, the sum of
+                               the dimensions' univariate DTWs), with LB_MV or no bounds, uniform
+                               lengths, W_eff <= 63 and up to 16 dimensions */
 } tc_dtw_knn_params;
 
 void tc_dtw_knn_params_default(tc_dtw_knn_params* p);
@@ -310,7 +314,9 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
 
 /* ---------------------------------------------------------------- k-NN ---
  * tc_dtw_knn: for every query, the indices of the p->k candidates with the
- * smallest banded DTW, ordered by (distance, index) so that ties go to the
+ * smallest banded DTW (dependent, or independent with p->independent; LB_MV
+ * bounds both, being a sum of per-dimension envelope bounds, Sec. 3),
+ * ordered by (distance, index) so that ties go to the
  * lower index, and those distances (Sec. 2 DTW-NN; Sec. 3 Definition 1;
  * k = 1 is the paper's nearest neighbour).  The result equals an exhaustive
  * float64 search: pruning and abandoning compare against an upper bound of
@@ -322,7 +328,8 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
  *   stats    HOST or NULL.  When given, the call waits for the stream and
  *            fills the counters and per-stage times.
  * Errors: INVALID (dims differ, k < 1 or k > candidates, bad parameters),
- * UNSUPPORTED (k > 32; k > 1 with uneven lengths), WORKSPACE, DEVICE. */
+ * UNSUPPORTED (k > 32; k > 1 with uneven lengths; independent DTW outside
+ * its limits or with LB_PC / LB_TI), WORKSPACE, DEVICE. */
 typedef struct {
     uint64_t pairs;          /* query-candidate pairs */
     uint64_t pruned_mv;      /* pairs skipped by LB_MV */

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcdtw.so")
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
 F64 = 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class TcDtwError(RuntimeError):
@@ -66,7 +66,7 @@ class KnnParams(C.Structure):
                 ("ti_period", C.c_int32), ("ti_top", C.c_int32), ("pc_levels", C.c_int32),
                 ("pc_clusters", C.c_int32), ("pc_group", C.c_int32), ("pc_min_cell", C.c_float),
                 ("trigger_ti", C.c_float), ("trigger_pc", C.c_float), ("prune_margin", C.c_float),
-                ("seed_r", C.c_int32), ("k", C.c_int32)]
+                ("seed_r", C.c_int32), ("k", C.c_int32), ("independent", C.c_int32)]
 
 
 class KnnStats(C.Structure):

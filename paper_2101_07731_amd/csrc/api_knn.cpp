@@ -50,6 +50,9 @@ static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
     if (st != TC_DTW_OK) return st;
     if (p->k < 1) return fail(TC_DTW_ERR_INVALID, "k must be >= 1");
     if (p->k > kMaxK) return fail(TC_DTW_ERR_UNSUPPORTED, "k is limited to 32");
+    if (p->independent != 0 && p->independent != 1) return fail(TC_DTW_ERR_INVALID, "independent must be 0 or 1");
+    if (p->independent && (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)))
+        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI bound the dependent DTW only (independent DTW: LB_MV)");
     if (p->bounds & ~(TC_DTW_LB_MV | TC_DTW_LB_PC | TC_DTW_LB_TI))
         return fail(TC_DTW_ERR_INVALID, "unknown bound bits");
     if ((p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)) && !(p->bounds & TC_DTW_LB_MV))
@@ -65,6 +68,7 @@ static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
 // Everything a uniform search needs, with workspace offsets.
 struct KnnPlan {
     int nq, nc, m, n, D, W, R, P, cap, ntiles, k;
+    bool indep;
     bool plain, abandon, gate, pc, ti;
     int ngroups, max_pts;
     size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
@@ -102,7 +106,10 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     if (K.k > K.nc) return fail(TC_DTW_ERR_INVALID, "k exceeds the number of candidates");
     // at least k seeds, so that the k-th best is finite before the compaction
     K.R = K.plain ? 0 : std::min(std::min(std::max(p->seed_r > 0 ? p->seed_r : 4, K.k), kMaxSeeds), K.nc);
-    K.P = knn_dtw_max_pairs(K.W, K.D);
+    K.indep = p->independent != 0;
+    if (K.indep && (K.W > kDiagMaxW || nch_pad(K.D) > 4))
+        return fail(TC_DTW_ERR_UNSUPPORTED, "independent DTW: band half-width up to 63 and up to 16 dimensions");
+    K.P = knn_dtw_max_pairs(K.W, K.D, K.indep);
     K.cap = K.nc;
     K.ntiles = ix->ntiles;
     Carve c(nullptr, 0);
@@ -270,8 +277,8 @@ static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, b
     KnnDtwArgs a;
     std::memset(&a, 0, sizeof a);
     a.Q = d.Q; a.C = d.C;
-    a.nq = K.nq; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W; a.P = K.P; a.gs = knn_lane_stride(K.W);
-    a.k = K.k; a.topk = d.topk;
+    a.nq = K.nq; a.m = K.m; a.n = K.n; a.D = K.D; a.W = K.W; a.P = K.P; a.gs = knn_lane_stride(K.W, K.indep);
+    a.k = K.k; a.topk = d.topk; a.indep = K.indep ? 1 : 0;
     if (seeds) {
         a.list = reinterpret_cast<const uint32_t*>(d.seeds);
         a.list_dist = d.seed_dist;
@@ -326,6 +333,7 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     if (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI))
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI need uniform query and candidate lengths");
     if (p->k > 1) return fail(TC_DTW_ERR_UNSUPPORTED, "k > 1 needs uniform query and candidate lengths");
+    if (p->independent) return fail(TC_DTW_ERR_UNSUPPORTED, "independent DTW needs uniform query and candidate lengths");
     K = RaggedPlan();
     K.nq = Qs.count;
     K.nc = ix->count;
@@ -533,6 +541,7 @@ void tc_dtw_knn_params_default(tc_dtw_knn_params* p) {
     p->prune_margin = 1e-6f;
     p->seed_r = 4;
     p->k = 1;
+    p->independent = 0;
 }
 
 size_t tc_dtw_index_bytes(const tc_dtw_batch* refs) {
@@ -745,6 +754,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         const double g = dp_gamma(K.m, K.n, K.D);
         f.ratio = (1.0 + g) / (1.0 - g) * (1.0 + 1e-9);
         f.k = K.k;
+        f.indep = K.indep ? 1 : 0;
         f.nn_idx = nn_idx; f.nn_dist = nn_dist;
         f.stats = d.stats;
         if ((e = launch_knn_finalize(f, s)) != hipSuccess) return hip_fail(e, "finalize");

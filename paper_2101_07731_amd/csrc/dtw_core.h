@@ -37,6 +37,18 @@ __device__ __forceinline__ void stage_series(int dst, int L, int first, const fl
     }
 }
 
+// Dimension p of series `src` ([len][D]) as single-chunk points (v, 0, 0, 0)
+// at positions pos = 0..L-1 (t = pos + first); `sentinel` outside [0, len).
+__device__ __forceinline__ void stage_dim(int dst, int L, int first, const float* src, int len, int D,
+                                          int p, float sentinel, int lane, int nlanes) {
+    for (int pos = lane; pos < L; pos += nlanes) {
+        const int t = pos + first;
+        const bool in = (t >= 0 && t < len);
+        lds4[dst + pos] = in ? make_float4(src[(int64_t)t * D + p], 0.0f, 0.0f, 0.0f)
+                             : make_float4(sentinel, sentinel, sentinel, sentinel);
+    }
+}
+
 // ---------------------------------------------------------- diagonal pairs
 struct DiagGeom {
     int m, n, W, G, h, R, LQ, LC;
@@ -152,6 +164,39 @@ __device__ __forceinline__ void diag_steps_rot(const float4 (&qv)[NCH], const fl
         float v = cost + __uint_as_float(umin3(__float_as_uint(vO), wave_rol1(e), e));
         if (!WODD && kill_o) v = __builtin_inff();
         vO = v;
+    }
+}
+
+// Component p (0 .. 4 NCH - 1) of a point held as NCH float4 chunks.
+template <int NCH>
+__device__ __forceinline__ float comp(const float4 (&v)[NCH], int p) {
+    const float4 x = v[p >> 2];
+    return (p & 3) == 0 ? x.x : (p & 3) == 1 ? x.y : (p & 3) == 2 ? x.z : x.w;
+}
+
+// Independent DTW (DTW_I): the steps of diag_steps_rot for every dimension
+// p with its own DP values vE[p], vO[p] and the univariate cost
+// (q_p - c_p)^2; the kills and neighbour exchanges are those of the
+// dependent case, per dimension.
+template <int NCH, bool WODD>
+__device__ __forceinline__ void diag_steps_indep(const float4 (&qv)[NCH], const float4 (&cin)[NCH],
+                                                 const float4 (&cout)[NCH], bool kill_e, bool kill_o,
+                                                 float (&vE)[4 * NCH], float (&vO)[4 * NCH]) {
+#pragma unroll
+    for (int p = 0; p < 4 * NCH; ++p) {
+        const float d = comp<NCH>(qv, p) - comp<NCH>(cin, p);
+        const uint32_t o = __float_as_uint(vO[p]);
+        float v = d * d + __uint_as_float(umin3(__float_as_uint(vE[p]), o, wave_ror1(o)));
+        if (WODD && kill_e) v = __builtin_inff();
+        vE[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < 4 * NCH; ++p) {
+        const float d = comp<NCH>(qv, p) - comp<NCH>(cout, p);
+        const uint32_t e = __float_as_uint(vE[p]);
+        float v = d * d + __uint_as_float(umin3(__float_as_uint(vO[p]), wave_rol1(e), e));
+        if (!WODD && kill_o) v = __builtin_inff();
+        vO[p] = v;
     }
 }
 

@@ -163,6 +163,7 @@ struct KnnDtwArgs {
     int32_t gs;                // lanes per pair group (knn_lane_stride)
     unsigned long long* topk;  // [nq][k] keys of the k best so far (k > 1); key[] then holds their largest
     int32_t k;
+    int32_t indep;             // 1: independent DTW (sum of per-dimension DTWs)
     const uint32_t* list;      // [nq][cap] candidate indices (negative: none)
     float* list_dist;          // [nq][cap] float32 DTW, +inf when abandoned
     const int32_t* cnt;        // [nq] list lengths (unless cnt_uniform > 0)
@@ -194,6 +195,7 @@ struct KnnFinalArgs {
     int32_t nc;
     double ratio;              // finalists: float32 DTW <= k-th smallest * ratio
     int32_t k;                 // neighbours per query; nn_idx / nn_dist are [nq][k]
+    int32_t indep;             // 1: independent DTW
     int32_t* nn_idx;
     float* nn_dist;
     unsigned long long* stats;
@@ -248,7 +250,7 @@ int64_t band_cells(int m, int n, int W);
 hipError_t launch_knn_finalize(const KnnFinalArgs& a, hipStream_t s);
 size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P);
 int knn_ring_max_passes(int nch);
-int knn_dtw_max_pairs(int W, int D);
+int knn_dtw_max_pairs(int W, int D, bool indep);
 // Ring size of the diagonal 1-NN kernel: the live window W + 5 plus one
 // refill of RS / 4 positions must fit.
 inline int ring_size(int W) { return W <= 27 ? 64 : 128; }
@@ -257,11 +259,11 @@ inline int ring_size(int W) { return W <= 27 ? 64 : 128; }
 // Each 16-lane quarter of the wave then reads 16 consecutive positions of
 // one series, which the LDS serves without bank conflicts; two pairs in
 // one quarter read positions 16 apart, which share banks.
-inline int knn_lane_stride(int W) {
+inline int knn_lane_stride(int W, bool pow2 = false) {
     const int G = W + 1;
     int p2 = 1;
     while (p2 < G) p2 <<= 1;
-    return (64 / p2 >= 64 / G) ? p2 : G;
+    return (pow2 || 64 / p2 >= 64 / G) ? p2 : G;
 }
 size_t knn_final_lds_bytes(int m, int n, int W, int D);
 

@@ -356,8 +356,12 @@ constexpr int kCheckRounds = 32;
 
 // NPASS: 64-lane passes of one refill ((1 + P) * RF positions), so that the
 // prefetch registers are only as many as the launch needs.
-template <int NCH, bool WODD, int RS, int NPASS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && NPASS <= 2 ? 4 : 1))) void k_knn_dtw_ring(KnnDtwArgs a) {
+// INDEP: independent DTW (DTW_I): one DP value per dimension and lane, the
+// pair's distance the sum over the dimensions; groups are a power of two
+// wide (the abandon test reduces within a group by xor shuffles).
+template <int NCH, bool WODD, int RS, int NPASS, bool INDEP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && NPASS <= 2 && !INDEP ? 4 : 1))) void k_knn_dtw_ring(KnnDtwArgs a) {
+    constexpr int NV = INDEP ? 4 * NCH : 1;   // DP values per lane and slot
     constexpr int RF = RS / 4, STR = RS;
     constexpr int MAXPASS = NPASS;
     const int lane = threadIdx.x;
@@ -421,8 +425,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && 
         const bool kill_o = !WODD && (lg == G - 1 || spare || pad);
         const int qbase = 0;
         const int cbase = (1 + gsrc) * per_series;
-        float vE = __builtin_inff(), vO = __builtin_inff();
-        if (!spare && lg == h) vE = 0.0f;
+        float vE[NV], vO[NV];
+#pragma unroll
+        for (int p = 0; p < NV; ++p) {
+            vE[p] = (!spare && lg == h) ? 0.0f : __builtin_inff();
+            vO[p] = __builtin_inff();
+        }
+        auto step = [&](const float4 (&qv)[NCH], const float4 (&ci)[NCH], const float4 (&co)[NCH])
+                        __attribute__((always_inline)) {
+            if constexpr (INDEP) diag_steps_indep<NCH, WODD>(qv, ci, co, kill_e, kill_o, vE, vO);
+            else diag_steps_rot<NCH, WODD>(qv, ci, co, kill_e, kill_o, vE[0], vO[0]);
+        };
         const uint64_t gbits = (G >= 64) ? ~0ull : ((1ull << G) - 1);
         uint64_t valid_mask = 0;
         for (int gg = 0; gg < np; ++gg) valid_mask |= gbits << (gg * GS);
@@ -459,7 +472,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && 
                 // decreases, so an older value is a safe threshold)
                 const float thr = abandon_threshold(bsf_from_key(pend), a.gamma);
                 // every warping path crosses one of the anti-diagonals 2r-2, 2r-1
-                const bool over = vmin(vE, vO) > thr;
+                bool over;
+                if constexpr (INDEP) {
+                    // the distance is at least the sum over dimensions of each
+                    // dimension's smallest value on those anti-diagonals (in the group)
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int p = 0; p < NV; ++p) {
+                        float mp = (pad || spare) ? __builtin_inff() : vmin(vE[p], vO[p]);
+                        for (int o = GS >> 1; o >= 1; o >>= 1) mp = vmin(mp, __shfl_xor(mp, o));
+                        sum += mp;
+                    }
+                    over = sum > thr;
+                } else {
+                    over = vmin(vE[0], vO[0]) > thr;
+                }
                 const uint64_t bal = __ballot(over);
                 if ((bal & gm) == gm) aband = true;
                 if ((bal & valid_mask) == valid_mask) return true;
@@ -496,26 +523,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && 
             while (r + 2 <= R) {
                 if (boundary(r)) { done = true; break; }
                 ldq(r, Q0); ldc(r + 1, C1);
-                diag_steps_rot<NCH, WODD>(Q0, C0, C1, kill_e, kill_o, vE, vO);
+                step(Q0, C0, C1);
                 ldq(r + 1, Q0); ldc(r + 2, C0);
-                diag_steps_rot<NCH, WODD>(Q0, C1, C0, kill_e, kill_o, vE, vO);
+                step(Q0, C1, C0);
                 r += 2;
             }
         }
         while (NCH <= 4 && r + 6 <= R) {
             if (boundary(r)) { done = true; break; }
             ldq(r + 1, Q1); ldc(r + 2, C2);
-            diag_steps_rot<NCH, WODD>(Q0, C0, C1, kill_e, kill_o, vE, vO);
+            step(Q0, C0, C1);
             ldq(r + 2, Q0); ldc(r + 3, C0);
-            diag_steps_rot<NCH, WODD>(Q1, C1, C2, kill_e, kill_o, vE, vO);
+            step(Q1, C1, C2);
             ldq(r + 3, Q1); ldc(r + 4, C1);
-            diag_steps_rot<NCH, WODD>(Q0, C2, C0, kill_e, kill_o, vE, vO);
+            step(Q0, C2, C0);
             ldq(r + 4, Q0); ldc(r + 5, C2);
-            diag_steps_rot<NCH, WODD>(Q1, C0, C1, kill_e, kill_o, vE, vO);
+            step(Q1, C0, C1);
             ldq(r + 5, Q1); ldc(r + 6, C0);
-            diag_steps_rot<NCH, WODD>(Q0, C1, C2, kill_e, kill_o, vE, vO);
+            step(Q0, C1, C2);
             ldq(r + 6, Q0); ldc(r + 7, C1);
-            diag_steps_rot<NCH, WODD>(Q1, C2, C0, kill_e, kill_o, vE, vO);
+            step(Q1, C2, C0);
             r += 6;
         }
         // the remaining rounds one at a time (C0 holds round r's cin)
@@ -523,7 +550,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && 
             if (boundary(r)) { done = true; break; }
             ldq(r, Q0);
             ldc(r + 1, C1);
-            diag_steps_rot<NCH, WODD>(Q0, C0, C1, kill_e, kill_o, vE, vO);
+            step(Q0, C0, C1);
 #pragma unroll
             for (int k = 0; k < NCH; ++k) C0[k] = C1[k];
             ++r;
@@ -533,7 +560,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NCH <= 2 && 
         const int sigma = (a.n - a.m) + 2 * h;
         const int myref = spare ? -1 : (int)a.list[(int64_t)q * a.cap + base + grp];
         const bool res_lane = !spare && lg == (sigma >> 1);
-        const float res = (sigma & 1) ? vO : vE;
+        float res = 0.0f;
+        if constexpr (INDEP) {
+#pragma unroll
+            for (int p = 0; p < NV; ++p)   // the dimensions' distances in increasing order
+                if (p < a.D) res += (sigma & 1) ? vO[p] : vE[p];
+        } else {
+            res = (sigma & 1) ? vO[0] : vE[0];
+        }
         if (res_lane) {
             float out = __builtin_inff();
             if (!aband && myref >= 0) {
@@ -676,7 +710,8 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
     const int LQ = g.LQ, LC = g.LC;
     const int sq = 0;
     const int sc = ROWS ? 0 : LQ * NCH;
-    if (!ROWS)
+    const int sc1 = LQ;    // candidate of the single-dimension staging (independent DTW)
+    if (!ROWS && !a.indep)
         stage_series<NCH>(sq, LQ, g.qfirst(), a.Q + (int64_t)q * a.m * a.D, a.m, a.D, __builtin_inff(),
                           lane, kWave);
     for (int pass = 0; pass < 2; ++pass) {
@@ -703,6 +738,33 @@ __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
                                                              a.C + (int64_t)r * a.n * a.D, a.m, a.n, a.W,
                                                              a.D, lane, nullptr, ab, aband);
                     v = __shfl(v, (a.m - 1) % kRowBlock);
+                } else if (a.indep) {
+                    // independent DTW: the univariate DTW of every dimension, summed in
+                    // increasing dimension order
+                    v = 0.0;
+                    const int G = g.G, lg = lane;
+                    const bool spare = lane >= G;
+                    const bool kill_e = WODD && (lg == 0 || spare);
+                    const bool kill_o = !WODD && (lg == G - 1);
+                    const int qb = sq + (a.W - (spare ? 0 : lg));
+                    const int cb = sc1 + (spare ? 0 : lg);
+                    const int sigma = (a.n - a.m) + 2 * g.h;
+                    for (int p = 0; p < a.D; ++p) {
+                        __syncthreads();
+                        stage_dim(sq, LQ, g.qfirst(), a.Q + (int64_t)q * a.m * a.D, a.m, a.D, p,
+                                  __builtin_inff(), lane, kWave);
+                        stage_dim(sc1, LC, g.cfirst(), a.C + (int64_t)r * a.n * a.D, a.n, a.D, p,
+                                  -__builtin_inff(), lane, kWave);
+                        __syncthreads();
+                        double vE = __builtin_inf(), vO = __builtin_inf();
+                        if (lg == g.h) vE = 0.0;
+                        Abandon ab{nullptr, 0.0f, 0};
+                        bool aband = false;
+                        diag_core<double, 1, false, WODD, false>(qb, LQ, cb, LC, g.R, G, lg, kill_e, kill_o,
+                                                                 vE, vO, nullptr, ab, aband, 0);
+                        const double mine = (sigma & 1) ? vO : vE;
+                        v = v + __shfl(mine, sigma >> 1);
+                    }
                 } else {
                     stage_series<NCH>(sc, LC, g.cfirst(), a.C + (int64_t)r * a.n * a.D, a.n, a.D,
                                       -__builtin_inff(), lane, kWave);
@@ -819,8 +881,14 @@ hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int 
 
 template <int NCH, int RS, int NPASS>
 static void launch_ring_w(const KnnDtwArgs& a, int nblocks, size_t lds, hipStream_t s) {
-    if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, RS, NPASS>), dim3(nblocks), dim3(64), lds, s, a);
-    else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, RS, NPASS>), dim3(nblocks), dim3(64), lds, s, a);
+    constexpr bool kIndep = NCH <= 4;   // independent DTW is built for up to 16 dimensions
+    if (a.indep && kIndep) {
+        if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, RS, NPASS, kIndep>), dim3(nblocks), dim3(64), lds, s, a);
+        else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, RS, NPASS, kIndep>), dim3(nblocks), dim3(64), lds, s, a);
+        return;
+    }
+    if (a.W & 1) hipLaunchKernelGGL((k_knn_dtw_ring<NCH, true, RS, NPASS, false>), dim3(nblocks), dim3(64), lds, s, a);
+    else hipLaunchKernelGGL((k_knn_dtw_ring<NCH, false, RS, NPASS, false>), dim3(nblocks), dim3(64), lds, s, a);
 }
 
 template <int NCH, int RS>
@@ -879,9 +947,9 @@ size_t knn_dtw_lds_bytes(int m, int n, int W, int D, int P) {
 
 int knn_ring_max_passes(int nch) { return nch <= 4 ? 3 : 1; }
 
-int knn_dtw_max_pairs(int W, int D) {
+int knn_dtw_max_pairs(int W, int D, bool indep) {
     if (W > kDiagMaxW) return 1;
-    int P = kWave / knn_lane_stride(W);
+    int P = kWave / knn_lane_stride(W, indep);
     const int RF = ring_size(W) / 4;
     const int maxpass = knn_ring_max_passes(nch_pad(D));
     while (P > 1 && (1 + P) * RF > maxpass * kWave) --P;

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     lib = L.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.tc_dtw_abi_version() == 2
+    assert lib.tc_dtw_abi_version() == 3
 
 
 def _batch(count=2, dim=3, ulen=8, data=0x1000):
@@ -168,3 +168,45 @@ def test_k_validated_on_the_host():
     Qr = L.Batch(0x1000, offs, lens, 3, 2, 0, None)
     _, p = ws(2)
     assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Qr), C.byref(p)) == 0
+
+
+def test_independent_dtw_validated_on_the_host():
+    """Independent DTW: LB_MV or no bounds, W_eff <= 63, up to 16 dimensions,
+    uniform lengths; the flag is 0 or 1."""
+    lib = L.lib()
+
+    def index(dim, length):
+        ix = L.Index()
+        ix.buf = C.c_void_p(0x4000)
+        ix.bytes = 1 << 20
+        ix.count = 10
+        ix.dim = dim
+        ix.uniform_len = length
+        ix.max_len = length
+        ix.ntiles = 1
+        return ix
+
+    def ws(ix, Q, **kw):
+        p = L.KnnParams()
+        lib.tc_dtw_knn_params_default(C.byref(p))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q), C.byref(p))
+
+    ix = index(8, 64)
+    Q = L.Batch(0x1000, None, None, 3, 8, 64, None)
+    assert ws(ix, Q, independent=1) > 0
+    assert ws(ix, Q, independent=1, bounds=0) > 0
+    assert ws(ix, Q, independent=2) == 0
+    assert ws(ix, Q, independent=1, bounds=L.LB_MV | L.LB_PC) == 0
+    assert ws(ix, Q, independent=1, bounds=L.LB_MV | L.LB_TI) == 0
+    ixw = index(20, 64)
+    Qw = L.Batch(0x1000, None, None, 3, 20, 64, None)
+    assert ws(ixw, Qw) > 0 and ws(ixw, Qw, independent=1) == 0          # 20 dimensions
+    ixl = index(8, 1000)
+    Ql = L.Batch(0x1000, None, None, 3, 8, 1000, None)
+    assert ws(ixl, Ql) > 0 and ws(ixl, Ql, independent=1) == 0          # W = 100
+    lens = (C.c_int32 * 3)(64, 60, 62)
+    offs = (C.c_int64 * 3)(0, 512, 992)
+    Qr = L.Batch(0x1000, offs, lens, 3, 8, 0, None)
+    assert ws(ix, Qr) > 0 and ws(ix, Qr, independent=1) == 0            # uneven lengths

@@ -131,6 +131,41 @@ def test_k_nearest_full_size_sampled(dev):
     assert np.all(np.diff(dist, axis=1) >= 0)
 
 
+@pytest.mark.parametrize("case", [(1, (1, 10)), (3, (1, 9)), (8, (1, 10)), (13, (1, 9))],
+                         ids=["d1_W6", "d3_W7", "d8_W6", "d13_W7"])
+def test_independent_dtw_against_oracle(dev, case):
+    """Independent DTW (DTW_I, Sec. 2): 1 and 3 nearest against the oracle's
+    exhaustive DTW_I, plain and with LB_MV, with duplicate references."""
+    from paper_2101_07731_amd import synth
+    D, frac = case
+    Q, Cs = synth.cascade_knn(nq=8, nc=200, T=64, D=D, seed=32)
+    Cs = np.concatenate([Cs, Cs[::11]])
+    Q = np.concatenate([Q, Cs[[17]]])
+    for k in (1, 3):
+        ri, rd = O.knn_exhaustive_k(Q, Cs, k, num=frac[0], den=frac[1], independent=True)
+        for bounds in ("plain", "mv"):
+            say("knn independent", case, k, bounds)
+            idx, dist, st = run_knn(dev, Q, Cs, frac=frac, bounds=bounds, k=k, independent=1)
+            if k == 1:
+                idx, dist = idx[:, None], dist[:, None]
+            np.testing.assert_array_equal(idx, ri)
+            np.testing.assert_array_equal(dist, rd.astype(np.float32))
+            assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
+
+
+def test_independent_dtw_full_size_sampled(dev):
+    """DTW_I on the benchmark's workload (1000 x 10000, length 256, d = 8,
+    W = 25), sampled queries against the oracle."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.cascade_knn()
+    idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds="mv", independent=1)
+    say("knn independent full size", st)
+    sample = np.array([3, 500])
+    ri, rd = O.knn_exhaustive_k(Q[sample], Cs, 1, num=1, den=10, independent=True)
+    np.testing.assert_array_equal(idx[sample], ri[:, 0])
+    np.testing.assert_array_equal(dist[sample], rd[:, 0].astype(np.float32))
+
+
 def test_cascade_repeatable(dev):
     from paper_2101_07731_amd import synth
     Q, Cs = synth.cascade_knn(nq=30, nc=500, T=64, D=4, seed=22)
