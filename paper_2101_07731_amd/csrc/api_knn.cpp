@@ -644,7 +644,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
     if (K.ti && 2 * K.W + 1 > 128)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
-    if (K.ti && ti_lds_bytes(K.m, K.n, K.D) > 163840)
+    if (K.ti && ti_lds_bytes(K.m, K.n, K.D, p->ti_period) > 163840)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI stages a pair in LDS: series too long");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
@@ -723,7 +723,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
             a.in_list = x.tlist; a.out_lb = x.tout; a.lb_in = x.tlb; a.key = d.key;
             if ((e = launch_list_items(x.tcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
                 return hip_fail(e, "ti items");
-            const int ti_blocks = persistent_blocks(ti_lds_bytes(K.m, K.n, K.D), (int64_t)K.nq * K.cap);
+            const int ti_blocks = persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period), (int64_t)K.nq * K.cap);
             if ((e = launch_lb_ti(a, ti_blocks, s)) != hipSuccess) return hip_fail(e, "lb_ti");
             RouteArgs r2 = r;
             r2.in_list = x.tlist; r2.in_cnt = x.tcnt; r2.lb_prev = x.tlb; r2.lb_new = x.tout;
@@ -855,7 +855,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         return fail(TC_DTW_ERR_INVALID, "kind must be one of TC_DTW_LB_MV, TC_DTW_LB_PC, TC_DTW_LB_TI");
     if (kind == TC_DTW_LB_TI && 2 * K.W + 1 > 128)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
-    if (kind == TC_DTW_LB_TI && ti_lds_bytes(K.m, K.n, K.D) > 163840)
+    if (kind == TC_DTW_LB_TI && ti_lds_bytes(K.m, K.n, K.D, p->ti_period) > 163840)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI stages a pair in LDS: series too long");
     if (K.plain) return fail(TC_DTW_ERR_INVALID, "params.bounds must include TC_DTW_LB_MV");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_lower_bounds_workspace_bytes()");
@@ -881,7 +881,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         a.in_list = nullptr; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
         if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
             return hip_fail(e, "ti items");
-        if ((e = launch_lb_ti(a, persistent_blocks(ti_lds_bytes(K.m, K.n, K.D), (int64_t)K.nq * K.nc), s)) != hipSuccess)
+        if ((e = launch_lb_ti(a, persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period), (int64_t)K.nq * K.nc), s)) != hipSuccess)
             return hip_fail(e, "lb_ti");
     }
     return ok();

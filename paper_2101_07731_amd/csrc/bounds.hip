@@ -241,6 +241,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     float* dqs = top + m;                              // [m] query steps
     float* gcs = dqs + m;                              // [n] candidate steps
     float* cst = gcs + n;                              // [n][D] candidate points
+    float* qex = cst + (int64_t)n * D;                 // [exact rows][D] query points of the exact rows
     const int KB = 2 * W + 1;                          // band offsets 0 .. 2W
     const float INF = __builtin_inff();
     const double u = 1.0 / 16777216.0;
@@ -271,6 +272,11 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         for (int i = lane; i < m; i += kWave) dqs[i] = a.qstep[(int64_t)q * m + i];
         for (int j = lane; j < n; j += kWave) gcs[j] = a.gamma[(int64_t)ref * n + j];
         for (int t = lane; t < n * D; t += kWave) cst[t] = cs[t];
+        // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[(i / P) D]
+        for (int t = lane; t < ti_exact_rows(m, P) * D; t += kWave) {
+            const int r = t / D;
+            qex[t] = qs[(int64_t)(P > 0 ? r * P : 0) * D + (t - r * D)];
+        }
         if (a.top) {
             for (int i = lane; i < m; i += kWave) {
                 const int j = i + W;
@@ -317,8 +323,9 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 cmn[SLOTS - 1] = wave_shl1(INF, cm[SLOTS - 1]);
             }
             // the column at offset 0 of row i-1 is not in row i's band: its minimum is final
-            const float leaving = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cm[0])));
-            if (i > 0 && leaving < INF) acc += leaving * leaving;
+            // (lane 0 holds it and keeps the sum; no scalar round trip)
+            const float leaving = cm[0];
+            acc += (lane == 0 && i > 0 && leaving < INF) ? leaving * leaving : 0.0f;
             // Lanes that are not cells (columns outside [0, n), offsets past 2W) carry values
             // that only ever reach other non-cells (the cell below keeps the column), so every
             // lane evaluates the same arithmetic and only the column minimum is masked.
@@ -327,8 +334,9 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 for (int s = 0; s < SLOTS; ++s) {
                     const int jc = min(max(jrow[s], 0), n - 1);
                     float sacc = 0.0f;
+                    const float* qrow = qex + (P > 0 ? i / P : 0) * D;
                     for (int p = 0; p < D; ++p) {
-                        const float t = qs[(int64_t)i * D + p] - cst[jc * D + p];
+                        const float t = qrow[p] - cst[jc * D + p];
                         sacc = __builtin_fmaf(t, t, sacc);
                     }
                     L[s] = U[s] = __builtin_sqrtf(sacc);
@@ -463,10 +471,12 @@ hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t ti_lds_bytes(int m, int n, int D) { return ((size_t)2 * m + n + (size_t)n * D) * 4 + 16; }
+size_t ti_lds_bytes(int m, int n, int D, int P) {
+    return ((size_t)2 * m + n + (size_t)n * D + (size_t)ti_exact_rows(m, P) * D) * 4 + 16;
+}
 
 hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s) {
-    const size_t lds = ti_lds_bytes(a.m, a.n, a.D);
+    const size_t lds = ti_lds_bytes(a.m, a.n, a.D, a.P);
     if (2 * a.W + 1 <= 64) hipLaunchKernelGGL(k_lb_ti<1>, dim3(nblocks), dim3(64), lds, s, a);
     else hipLaunchKernelGGL(k_lb_ti<2>, dim3(nblocks), dim3(64), lds, s, a);
     return hipGetLastError();
