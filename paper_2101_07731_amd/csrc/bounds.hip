@@ -232,21 +232,24 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
 // loads, candidate point per lane); the top cell of each row takes the
 // precomputed e(q_i, c_{i+W}) under TOP, else Eqs. 9-10 from its left
 // neighbour with gamma_j = e(c_{j-1}, c_j) from the index.
-template <int SLOTS>
+// TOP and the point width (NCH float4 chunks, zero-padded) are template
+// parameters, so the row loop has no runtime branch on them and an exact
+// row's distance is NCH unrolled 16-byte LDS reads per point.
+template <int SLOTS, bool TOP, int NCH>
 __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     const int lane = threadIdx.x;
     const int m = a.m, n = a.n, D = a.D, W = a.W, P = a.P;
     // LDS, staged per pair so that the row loop never waits on global memory:
-    float* top = reinterpret_cast<float*>(lds4);       // [m] exact top distances (TOP)
+    float4* cst = lds4;                                // [n][NCH] candidate points
+    float4* qex = cst + (int64_t)n * NCH;              // [exact rows][NCH] query points of the exact rows
+    float* top = reinterpret_cast<float*>(qex + (int64_t)ti_exact_rows(m, P) * NCH);   // [m] (TOP)
     float* dqs = top + m;                              // [m] query steps
     float* gcs = dqs + m;                              // [n] candidate steps
-    float* cst = gcs + n;                              // [n][D] candidate points
-    float* qex = cst + (int64_t)n * D;                 // [exact rows][D] query points of the exact rows
     const int KB = 2 * W + 1;                          // band offsets 0 .. 2W
     const float INF = __builtin_inff();
     const double u = 1.0 / 16777216.0;
     // longest recursion chain since an exact value (rows, plus one top step per row without TOP)
-    const int rmax = P > 0 ? (a.top ? P - 1 : 2 * (P - 1) + 1) : (a.top ? m : 2 * m + 1);
+    const int rmax = P > 0 ? (TOP ? P - 1 : 2 * (P - 1) + 1) : (TOP ? m : 2 * m + 1);
     const float slack = (float)((0.5 * D + 5.0 + rmax) * u * 1.02);
     const double defl = 1.0 - (double)(n + 5) * u * 1.001;
     const int kt = KB - 1;                             // top offset
@@ -271,13 +274,19 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         __syncthreads();
         for (int i = lane; i < m; i += kWave) dqs[i] = a.qstep[(int64_t)q * m + i];
         for (int j = lane; j < n; j += kWave) gcs[j] = a.gamma[(int64_t)ref * n + j];
-        for (int t = lane; t < n * D; t += kWave) cst[t] = cs[t];
-        // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[(i / P) D]
-        for (int t = lane; t < ti_exact_rows(m, P) * D; t += kWave) {
-            const int r = t / D;
-            qex[t] = qs[(int64_t)(P > 0 ? r * P : 0) * D + (t - r * D)];
+        auto chunk = [&](const float* pt, int k) __attribute__((always_inline)) -> float4 {
+            float v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = 4 * k + c < D ? pt[4 * k + c] : 0.0f;
+            return make_float4(v[0], v[1], v[2], v[3]);
+        };
+        for (int t = lane; t < n * NCH; t += kWave) cst[t] = chunk(cs + (int64_t)(t / NCH) * D, t % NCH);
+        // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
+        for (int t = lane; t < ti_exact_rows(m, P) * NCH; t += kWave) {
+            const int r = t / NCH;
+            qex[t] = chunk(qs + (int64_t)(P > 0 ? r * P : 0) * D, t % NCH);
         }
-        if (a.top) {
+        if (TOP) {
             for (int i = lane; i < m; i += kWave) {
                 const int j = i + W;
                 float d = INF;
@@ -307,7 +316,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         for (int i = 0; i < m; ++i) {
             const bool exact_row = (i == 0) || (P > 0 && since == 0);
             const float di = dqs[i];
-            const float topv = a.top ? top[i] : INF;
+            const float topv = TOP ? top[i] : INF;
             // row i-1 values of the same column (offset k+1)
             float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
             if (SLOTS == 1) {
@@ -333,11 +342,17 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     const int jc = min(max(jrow[s], 0), n - 1);
+                    const float4* qrow = qex + (P > 0 ? i / P : 0) * NCH;
+                    const float4* crow = cst + jc * NCH;
                     float sacc = 0.0f;
-                    const float* qrow = qex + (P > 0 ? i / P : 0) * D;
-                    for (int p = 0; p < D; ++p) {
-                        const float t = qrow[p] - cst[jc * D + p];
-                        sacc = __builtin_fmaf(t, t, sacc);
+#pragma unroll
+                    for (int k = 0; k < NCH; ++k) {
+                        const float4 qv = qrow[k], cv = crow[k];
+                        float t;
+                        t = qv.x - cv.x; sacc = __builtin_fmaf(t, t, sacc);
+                        t = qv.y - cv.y; sacc = __builtin_fmaf(t, t, sacc);
+                        t = qv.z - cv.z; sacc = __builtin_fmaf(t, t, sacc);
+                        t = qv.w - cv.w; sacc = __builtin_fmaf(t, t, sacc);
                     }
                     L[s] = U[s] = __builtin_sqrtf(sacc);
                 }
@@ -347,11 +362,11 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                     const bool istop = lane + 64 * s == kt;
                     const float lo = __builtin_fmaxf(Ln[s] - di, di - Un[s]);   // Eq. 7
                     const float hi = Un[s] + di;                                 // Eq. 8
-                    L[s] = (istop && a.top) ? topv : lo;
-                    U[s] = (istop && a.top) ? topv : hi;
+                    L[s] = (TOP && istop) ? topv : lo;
+                    U[s] = (TOP && istop) ? topv : hi;
                 }
             }
-            if (!exact_row && !a.top) {
+            if (!TOP && !exact_row) {
                 // top cell from (i, j-1), Eqs. 9-10 (exact when it has no left neighbour)
                 const bool hi_slot = (kl >> 6) != 0;
                 const float Lsel = hi_slot ? L[SLOTS - 1] : L[0];
@@ -368,7 +383,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                     } else {
                         float sacc = 0.0f;
                         for (int p = 0; p < D; ++p) {
-                            const float t = qs[(int64_t)i * D + p] - cst[j * D + p];
+                            const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
                             sacc = __builtin_fmaf(t, t, sacc);
                         }
                         lo = hi = __builtin_sqrtf(sacc);
@@ -472,14 +487,35 @@ hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
 }
 
 size_t ti_lds_bytes(int m, int n, int D, int P) {
-    return ((size_t)2 * m + n + (size_t)n * D + (size_t)ti_exact_rows(m, P) * D) * 4 + 16;
+    const size_t nch = (size_t)nch_pad(D);
+    return ((size_t)n * nch + (size_t)ti_exact_rows(m, P) * nch) * 16 + ((size_t)2 * m + n) * 4 + 16;
+}
+
+template <int SLOTS, int NCH>
+static void launch_lb_ti_nch(const TiArgs& a, int nblocks, size_t lds, hipStream_t s) {
+    if (a.top) hipLaunchKernelGGL((k_lb_ti<SLOTS, true, NCH>), dim3(nblocks), dim3(64), lds, s, a);
+    else hipLaunchKernelGGL((k_lb_ti<SLOTS, false, NCH>), dim3(nblocks), dim3(64), lds, s, a);
+}
+
+template <int SLOTS>
+static hipError_t launch_lb_ti_slots(const TiArgs& a, int nblocks, size_t lds, hipStream_t s) {
+    switch (nch_pad(a.D)) {
+        case 1: launch_lb_ti_nch<SLOTS, 1>(a, nblocks, lds, s); break;
+        case 2: launch_lb_ti_nch<SLOTS, 2>(a, nblocks, lds, s); break;
+        case 3: launch_lb_ti_nch<SLOTS, 3>(a, nblocks, lds, s); break;
+        case 4: launch_lb_ti_nch<SLOTS, 4>(a, nblocks, lds, s); break;
+        case 6: launch_lb_ti_nch<SLOTS, 6>(a, nblocks, lds, s); break;
+        case 8: launch_lb_ti_nch<SLOTS, 8>(a, nblocks, lds, s); break;
+        case 12: launch_lb_ti_nch<SLOTS, 12>(a, nblocks, lds, s); break;
+        case 16: launch_lb_ti_nch<SLOTS, 16>(a, nblocks, lds, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s) {
     const size_t lds = ti_lds_bytes(a.m, a.n, a.D, a.P);
-    if (2 * a.W + 1 <= 64) hipLaunchKernelGGL(k_lb_ti<1>, dim3(nblocks), dim3(64), lds, s, a);
-    else hipLaunchKernelGGL(k_lb_ti<2>, dim3(nblocks), dim3(64), lds, s, a);
-    return hipGetLastError();
+    return 2 * a.W + 1 <= 64 ? launch_lb_ti_slots<1>(a, nblocks, lds, s) : launch_lb_ti_slots<2>(a, nblocks, lds, s);
 }
 
 hipError_t launch_route(const RouteArgs& a, int max_in, hipStream_t s) {
