@@ -313,15 +313,26 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         }
         float acc = 0.0f;
         int since = 0;       // rows since the last exact row (exact rows: i = 0 and i mod P = 0)
+        // the row's query step and top distance, read one row ahead
+        float di_next = dqs[0];
+        float top_next = TOP ? top[0] : INF;
         for (int i = 0; i < m; ++i) {
             const bool exact_row = (i == 0) || (P > 0 && since == 0);
-            const float di = dqs[i];
-            const float topv = TOP ? top[i] : INF;
+            const float di = di_next;
+            const float topv = top_next;
+            {
+                const int in = i + 1 < m ? i + 1 : i;
+                di_next = dqs[in];
+                if (TOP) top_next = top[in];
+            }
             // row i-1 values of the same column (offset k+1)
             float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
             if (SLOTS == 1) {
-                Ln[0] = wave_shl1(-INF, L[0]);
-                Un[0] = wave_shl1(INF, U[0]);
+                // L, U by rotation: what lane 63 receives moves down only into the top
+                // offset, which every row overwrites (TOP, exact rows, Eqs. 9-10) unless
+                // its column lies outside the candidate, where it stays a non-cell
+                Ln[0] = __uint_as_float(wave_rol1(__float_as_uint(L[0])));
+                Un[0] = __uint_as_float(wave_rol1(__float_as_uint(U[0])));
                 cmn[0] = wave_shl1(INF, cm[0]);
             } else {
                 Ln[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(L[SLOTS - 1]), 0)), L[0]);
@@ -398,7 +409,8 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 const bool cell = ink[s] && (unsigned)jrow[s] < (unsigned)n;
                 // a safe lower bound of the Euclidean point distance, clamped at 0
                 const float safe = __builtin_fmaxf(__builtin_fmaf(-slack, U[s], L[s]), 0.0f);
-                cm[s] = __builtin_fminf(cmn[s], cell ? safe : INF);
+                // column minima are >= 0 or +inf: minimum on the bit patterns
+                cm[s] = __uint_as_float(min(__float_as_uint(cmn[s]), __float_as_uint(cell ? safe : INF)));
                 jrow[s] += 1;
             }
             since = (since + 1 == P) ? 0 : since + 1;
