@@ -210,8 +210,14 @@ __global__ __launch_bounds__(64) void k_topr(const float* __restrict__ lb, int n
 // Compaction (Sec. 2 DTW-NN filtering; Sec. 6 selective deployment): every
 // non-seed pair whose bound, shrunk by the prune margin, exceeds the
 // query's best-so-far is skipped; the rest goes to the DTW list, or to the
-// advanced-bound list when gating is on and LB_MV > e^2 bsf.  Wave ballot
-// plus one atomic per wave and list.
+// advanced-bound list when gating is on and LB_MV > e^2 bsf.  A block of
+// 256 threads covers kCompactPer candidates of one query (four per
+// thread): wave ballots, a prefix over the block's waves and rounds in
+// LDS, and one atomic per block and list (a counter per query takes many
+// fewer atomics than with one per wave).
+constexpr int kCompactRounds = 4;
+constexpr int kCompactPer = 256 * kCompactRounds;
+
 __global__ __launch_bounds__(256) void k_compact(const float* __restrict__ lb, int nc,
                                                  const int32_t* __restrict__ seeds, int R,
                                                  const unsigned long long* __restrict__ key,
@@ -219,32 +225,54 @@ __global__ __launch_bounds__(256) void k_compact(const float* __restrict__ lb, i
                                                  uint32_t* __restrict__ list, int32_t* cnt,
                                                  uint32_t* __restrict__ glist, int32_t* gcnt, int cap,
                                                  unsigned long long* stats) {
+    constexpr int NW = 4;   // waves per block
+    __shared__ int sd[kCompactRounds][NW], sg[kCompactRounds][NW];
+    __shared__ int base_d, base_g;
     const int q = blockIdx.y;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double bsf = (double)bsf_from_key(key[(int64_t)q * kKeyStride]);
-    const bool valid = r < nc;
-    bool seed = false;
-    for (int k = 0; k < R; ++k) seed |= (seeds[(int64_t)q * R + k] == r);
-    const double v = (valid && lb) ? (double)lb[(int64_t)q * nc + r] : 0.0;
-    const bool live = valid && !seed;
-    const bool pruned = live && (v * keep > bsf);
-    const bool gated = live && !pruned && use_gate && (v > gate_e2 * bsf);
-    const bool todtw = live && !pruned && !gated;
-    const uint64_t bd = __ballot(todtw), bg = __ballot(gated);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int based = 0, baseg = 0;
-    // the pruned count is derived per query at the end (pairs - seeds - listed)
-    if (lane == 0) {
-        if (bd) based = atomicAdd(&cnt[q], __popcll(bd));
-        if (bg) baseg = atomicAdd(&gcnt[q], __popcll(bg));
+    uint64_t bd[kCompactRounds], bg[kCompactRounds];
+    bool todtw[kCompactRounds], gated[kCompactRounds];
+#pragma unroll
+    for (int it = 0; it < kCompactRounds; ++it) {
+        const int r = blockIdx.x * kCompactPer + it * 256 + threadIdx.x;
+        const bool valid = r < nc;
+        bool seed = false;
+        for (int k = 0; k < R; ++k) seed |= (seeds[(int64_t)q * R + k] == r);
+        const double v = (valid && lb) ? (double)lb[(int64_t)q * nc + r] : 0.0;
+        const bool live = valid && !seed;
+        const bool pruned = live && (v * keep > bsf);
+        gated[it] = live && !pruned && use_gate && (v > gate_e2 * bsf);
+        todtw[it] = live && !pruned && !gated[it];
+        bd[it] = __ballot(todtw[it]);
+        bg[it] = __ballot(gated[it]);
+        if (lane == 0) {
+            sd[it][wave] = __popcll(bd[it]);
+            sg[it][wave] = __popcll(bg[it]);
+        }
     }
-    (void)pruned;
-    (void)stats;
-    based = __shfl(based, 0);
-    baseg = __shfl(baseg, 0);
-    if (todtw) list[(int64_t)q * cap + based + __popcll(bd & below)] = (uint32_t)r;
-    if (gated) glist[(int64_t)q * cap + baseg + __popcll(bg & below)] = (uint32_t)r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // exclusive prefix in (round, wave) order, then one atomic per list
+        int td = 0, tg = 0;
+        for (int it = 0; it < kCompactRounds; ++it)
+            for (int w = 0; w < NW; ++w) {
+                const int cd = sd[it][w], cg = sg[it][w];
+                sd[it][w] = td; sg[it][w] = tg;
+                td += cd; tg += cg;
+            }
+        base_d = td ? atomicAdd(&cnt[q], td) : 0;
+        base_g = tg ? atomicAdd(&gcnt[q], tg) : 0;
+    }
+    __syncthreads();
+    (void)stats;   // the pruned count is derived per query at the end (pairs - seeds - listed)
+#pragma unroll
+    for (int it = 0; it < kCompactRounds; ++it) {
+        const uint32_t r = (uint32_t)(blockIdx.x * kCompactPer + it * 256 + threadIdx.x);
+        if (todtw[it]) list[(int64_t)q * cap + base_d + sd[it][wave] + __popcll(bd[it] & below)] = r;
+        if (gated[it]) glist[(int64_t)q * cap + base_g + sg[it][wave] + __popcll(bg[it] & below)] = r;
+    }
 }
 
 // prefix[q+1] = prefix[q] + ceil(cnt[q] / P); also clears the work counter.
@@ -873,7 +901,7 @@ hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s) {
 }
 
 hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int use_gate, hipStream_t s) {
-    dim3 grid((p.nc + 255) / 256, p.nq);
+    dim3 grid((p.nc + kCompactPer - 1) / kCompactPer, p.nq);
     hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, p.lb, p.nc, p.seeds, p.R, p.key, keep, gate_e2,
                        use_gate, p.list, p.cnt, p.glist, p.gcnt, p.cap, p.stats);
     return hipGetLastError();
