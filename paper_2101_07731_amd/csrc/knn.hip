@@ -93,54 +93,86 @@ __global__ void k_envelope(const float* __restrict__ Q, int nq, int m, int n, in
 // would need a device-scope release per block, which writes back the
 // XCD's whole L2.)  The deflation covers any summation order of the E
 // terms.
-template <int QT, int LD = (QT <= 2 ? 4 : 2)>
+// CPL: candidate tiles per wave.  With four or more query slots a wave
+// takes two tiles, so each envelope value moved into a vector register
+// serves two med3 operations (3.5 VALU operations per element, query and
+// candidate instead of 4).
+template <int QT, int LD = (QT <= 2 ? 4 : 2), int CPL = (QT >= 4 ? 2 : 1)>
 __global__ __launch_bounds__(256) void k_lb_mv(const float* __restrict__ tiles, int ntiles, int E,
                                                const float* __restrict__ env, int nq, int nc,
                                                double deflate, float* __restrict__ lb, int seg4,
                                                float* __restrict__ part) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= ntiles) return;
+    const int tile0 = (blockIdx.x * 4 + wave) * CPL;
+    if (tile0 >= ntiles) return;
     const int qt = blockIdx.y;
     const int E4 = (E + 3) / 4, Ep = 4 * E4;
     const int f0 = blockIdx.z * seg4, f1 = min(E4, f0 + seg4);
-    const float4* __restrict__ cp = reinterpret_cast<const float4*>(tiles) + (int64_t)tile * E4 * 64 + lane;
-    const float* __restrict__ ep = env + (int64_t)qt * Ep * kQT * 2;
-    float acc[QT];
+    const float4* __restrict__ cp[CPL];
 #pragma unroll
-    for (int k = 0; k < QT; ++k) acc[k] = 0.0f;
-    auto term = [&](float c, int e) {
+    for (int c = 0; c < CPL; ++c) {   // a tile past the end reads the first one again (its results are dropped)
+        const int t = tile0 + c < ntiles ? tile0 + c : tile0;
+        cp[c] = reinterpret_cast<const float4*>(tiles) + (int64_t)t * E4 * 64 + lane;
+    }
+    const float* __restrict__ ep = env + (int64_t)qt * Ep * kQT * 2;
+    float acc[CPL][QT];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int k = 0; k < QT; ++k) acc[c][k] = 0.0f;
+    auto term = [&](const float (&cv)[CPL], int e) __attribute__((always_inline)) {
         const float* __restrict__ u = ep + (int64_t)e * kQT * 2;
 #pragma unroll
         for (int k = 0; k < QT; ++k) {
-            const float t = c - __builtin_amdgcn_fmed3f(c, u[2 * k + 1], u[2 * k]);
-            acc[k] = __builtin_fmaf(t, t, acc[k]);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const float t = cv[c] - __builtin_amdgcn_fmed3f(cv[c], u[2 * k + 1], u[2 * k]);
+                acc[c][k] = __builtin_fmaf(t, t, acc[c][k]);
+            }
         }
     };
+    auto terms4 = [&](const float4 (&a)[CPL], int e) __attribute__((always_inline)) {
+        float x[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) x[c] = a[c].x;
+        term(x, e);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) x[c] = a[c].y;
+        term(x, e + 1);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) x[c] = a[c].z;
+        term(x, e + 2);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) x[c] = a[c].w;
+        term(x, e + 3);
+    };
     int f = f0;
-    for (; f + LD <= f1; f += LD) {   // LD 16-byte loads (4 LD elements) in flight per lane
-        float4 a[LD];
+    for (; f + LD <= f1; f += LD) {   // LD 16-byte loads (4 LD elements) per tile in flight per lane
+        float4 a[LD][CPL];
 #pragma unroll
-        for (int i = 0; i < LD; ++i) a[i] = cp[(int64_t)(f + i) * 64];
+        for (int i = 0; i < LD; ++i)
 #pragma unroll
-        for (int i = 0; i < LD; ++i) {
-            const int e = 4 * (f + i);
-            term(a[i].x, e); term(a[i].y, e + 1); term(a[i].z, e + 2); term(a[i].w, e + 3);
-        }
+            for (int c = 0; c < CPL; ++c) a[i][c] = cp[c][(int64_t)(f + i) * 64];
+#pragma unroll
+        for (int i = 0; i < LD; ++i) terms4(a[i], 4 * (f + i));
     }
     for (; f < f1; ++f) {
-        const float4 a = cp[(int64_t)f * 64];
-        const int e = 4 * f;
-        term(a.x, e); term(a.y, e + 1); term(a.z, e + 2); term(a.w, e + 3);
-    }
-    const int r = tile * 64 + lane;
-    if (r >= nc) return;
+        float4 a[CPL];
 #pragma unroll
-    for (int k = 0; k < QT; ++k) {
-        const int q = qt * kQT + k;
-        if (q >= nq) continue;
-        if (gridDim.z == 1) lb[(int64_t)q * nc + r] = round_down_f((double)acc[k] * deflate);
-        else part[((int64_t)blockIdx.z * nq + q) * nc + r] = acc[k];
+        for (int c = 0; c < CPL; ++c) a[c] = cp[c][(int64_t)f * 64];
+        terms4(a, 4 * f);
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int r = (tile0 + c) * 64 + lane;
+        if (tile0 + c >= ntiles || r >= nc) continue;
+#pragma unroll
+        for (int k = 0; k < QT; ++k) {
+            const int q = qt * kQT + k;
+            if (q >= nq) continue;
+            if (gridDim.z == 1) lb[(int64_t)q * nc + r] = round_down_f((double)acc[c][k] * deflate);
+            else part[((int64_t)blockIdx.z * nq + q) * nc + r] = acc[c][k];
+        }
     }
 }
 
@@ -174,9 +206,7 @@ __global__ __launch_bounds__(64) void k_topr(const float* __restrict__ lb, int n
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) { v[k] = __builtin_inff(); id[k] = 0x7fffffff; }
     const float* row = lb + (int64_t)q * nc;
-    for (int r = lane; r < nc; r += kWave) {
-        float x = row[r];
-        int xi = r;
+    auto insert = [&](float x, int xi) __attribute__((always_inline)) {
         if (x < v[RMAX - 1]) {
 #pragma unroll
             for (int k = 0; k < RMAX; ++k) {   // insertion into the sorted local list
@@ -187,7 +217,16 @@ __global__ __launch_bounds__(64) void k_topr(const float* __restrict__ lb, int n
                 }
             }
         }
+    };
+    int r = lane;
+    for (; r + 3 * kWave < nc; r += 4 * kWave) {   // four loads in flight per lane
+        float x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = row[r + u * kWave];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) insert(x[u], r + u * kWave);
     }
+    for (; r < nc; r += kWave) insert(row[r], r);
     for (int k = 0; k < R; ++k) {
         float bv = v[0];
         int bi = id[0];
@@ -866,8 +905,12 @@ hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s, bool init) {
     return hipGetLastError();
 }
 
+// Tiles per wave of the LB_MV launch (see k_lb_mv).
+static int lb_mv_cpl(int nq) { return nq > 2 ? 2 : 1; }
+
 int lb_mv_segments(int ntiles, int nq, int E) {
-    const int64_t blocks = (int64_t)((ntiles + 3) / 4) * ((nq + kQT - 1) / kQT);
+    const int tpb = 4 * lb_mv_cpl(nq);
+    const int64_t blocks = (int64_t)((ntiles + tpb - 1) / tpb) * ((nq + kQT - 1) / kQT);
     if (blocks >= 2048) return 1;   // eight waves per CU already
     int64_t S = (8192 + blocks - 1) / blocks;
     const int ld = nq <= 2 ? 4 : 2;   // loads in flight of the kernel that runs
@@ -882,7 +925,8 @@ hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s) {
     const int S = p.part ? p.nseg : 1;
     const int E4 = (E + 3) / 4;
     const int seg = (E4 + S - 1) / S;   // in groups of 4 elements
-    dim3 grid((p.ntiles + 3) / 4, (p.nq + kQT - 1) / kQT, S);
+    const int tpb = 4 * lb_mv_cpl(p.nq);
+    dim3 grid((p.ntiles + tpb - 1) / tpb, (p.nq + kQT - 1) / kQT, S);
     auto kern = p.nq > 4 ? k_lb_mv<kQT> : p.nq > 2 ? k_lb_mv<4> : p.nq > 1 ? k_lb_mv<2> : k_lb_mv<1>;
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, p.tiles, p.ntiles, E, p.env, p.nq, p.nc, deflate, lb, seg,
                        p.part);
