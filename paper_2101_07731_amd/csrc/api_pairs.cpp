@@ -391,9 +391,9 @@ static tc_dtw_status run_bwd(const tc_dtw_pairs_plan* p, const float* x, const f
         a.grad_x = grad_x;
         a.grad_y = grad_y;
         a.counter = counters + k;
-        const size_t lds = bwd_lds_bytes(c.maxm, c.maxn, c.max_words);
+        const size_t lds = bwd_lds_bytes(c.maxm, c.maxn, c.max_words, c.dim);
         if (lds > lim) { (void)join_into(rs, s0); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the backward's LDS"); }
-        e = launch_dtw_bwd(a, c.maxm, c.maxn, c.max_words, c.nitems,
+        e = launch_dtw_bwd(a, c.maxm, c.maxn, c.max_words, c.dim, c.nitems,
                            persistent_grid(lds, p->waves_per_cu, c.nitems), s);
         if (e != hipSuccess) { (void)join_into(rs, s0); return hip_fail(e, "dtw backward launch"); }
     }
@@ -523,9 +523,9 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
     a.urows = P.urows ? 1 : 0;
     a.m = P.m; a.n = P.n; a.W = P.W;
     a.codes_stride = P.codes_stride;
-    if (bwd_lds_bytes(P.m, P.n, P.codes_stride) > lds_limit())
+    if (bwd_lds_bytes(P.m, P.n, P.codes_stride, P.D) > lds_limit())
         return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the backward's LDS");
-    const hipError_t e = launch_dtw_bwd(a, P.m, P.n, P.codes_stride, P.npairs, 0, s);
+    const hipError_t e = launch_dtw_bwd(a, P.m, P.n, P.codes_stride, P.D, P.npairs, 0, s);
     if (e != hipSuccess) return hip_fail(e, "dtw backward launch");
     return ok();
 }

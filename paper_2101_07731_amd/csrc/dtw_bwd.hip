@@ -2,21 +2,27 @@
 // both series along the optimal warping path that the forward recorded
 // as 2-bit argmin codes (0 = diagonal, 1 = (i-1,j), 2 = (i,j-1)).
 //
-// One wave per pair:
-//   1. the pair's codes are copied to LDS when they fit;
-//   2. lane 0 walks the path back from (m-1, n-1) to (0, 0); a monotone
-//      path meets every row i in one run of columns [rlo_i, rhi_i] and
-//      every column j in one run of rows [clo_j, chi_j], which are kept in
-//      LDS;
-//   3. lanes over rows form grad_x[i] = g * sum_{j in run} 2 (x_i - y_j),
-//      lanes over columns grad_y[j] = g * sum_{i in run} 2 (y_j - x_i),
-//      accumulated in float64 and rounded once to float32.
+// One block of 256 threads per pair:
+//   1. the pair's codes, and both series when they fit, are copied to LDS;
+//   2. thread 0 walks the path back from (m-1, n-1) to (0, 0), keeping the
+//      current code word in a register (consecutive steps mostly share
+//      it); a monotone path meets every row i in one run of columns
+//      [rlo_i, rhi_i] and every column j in one run of rows [clo_j, chi_j],
+//      which are kept in LDS;
+//   3. threads over (row, dimension) form grad_x[i][p] = g * sum_{j in run}
+//      2 (x_ip - y_jp), threads over (column, dimension) grad_y likewise,
+//      accumulated in float64 in increasing j (i) and rounded once to
+//      float32.
+#include <algorithm>
+
 #include "device_common.h"
 #include "internal.h"
 
 namespace tcdtw {
 
 constexpr int kBwdCodeLdsWords = 12288;   // 48 KB of staged codes
+constexpr int kBwdSeriesLdsFloats = 16384; // 64 KB of staged series (x then y)
+constexpr int kBwdThreads = 256;
 
 
 struct CodeMap {
@@ -53,7 +59,7 @@ struct CodeMap {
 
 __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     extern __shared__ int32_t sbw[];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     int m, n, W, pid, D;
     bool rows;
     int64_t xoff, yoff, soff;
@@ -72,26 +78,38 @@ __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     int32_t* clo = rhi + m;
     int32_t* chi = clo + n;
     uint32_t* scodes = reinterpret_cast<uint32_t*>(sbw + a.runs_ints);
+    float* sser = reinterpret_cast<float*>(scodes + a.stage_cap);
     CodeMap cm;
     cm.init(m, n, W, rows);
     const int64_t words = codes_words(m, n, W, rows);
     const bool staged = words <= a.stage_cap;
+    const bool sstaged = (int64_t)(m + n) * D <= a.series_cap;
     const uint32_t* gcodes = a.codes + soff;
-    if (staged) {
-        for (int64_t w = lane; w < words; w += kWave) scodes[w] = gcodes[w];
+    const float* xs = a.x + xoff;
+    const float* ys = a.y + yoff;
+    if (staged)
+        for (int64_t w = tid; w < words; w += kBwdThreads) scodes[w] = gcodes[w];
+    if (sstaged) {
+        for (int t = tid; t < m * D; t += kBwdThreads) sser[t] = xs[t];
+        for (int t = tid; t < n * D; t += kBwdThreads) sser[m * D + t] = ys[t];
     }
     __syncthreads();
 
-    if (lane == 0) {
+    if (tid == 0) {
         int i = m - 1, j = n - 1;
         rhi[i] = j;
         chi[j] = i;
+        int64_t cw_at = -1;
+        uint32_t cw = 0;
         while (i > 0 || j > 0) {
             int64_t w;
             int sh;
             cm.locate(i, j, w, sh);
-            const uint32_t word = staged ? scodes[w] : gcodes[w];
-            const int code = (word >> sh) & 3;
+            if (w != cw_at) {
+                cw = staged ? scodes[w] : gcodes[w];
+                cw_at = w;
+            }
+            const int code = (cw >> sh) & 3;
             int pi = i, pj = j;
             if (code == 0) { pi = i - 1; pj = j - 1; }
             else if (code == 1) { pi = i - 1; }
@@ -106,58 +124,66 @@ __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     __syncthreads();
 
     const float g2 = 2.0f * a.grad_dist[pid];
-    const float* xs = a.x + xoff;
-    const float* ys = a.y + yoff;
+    const float* xv_src = sstaged ? sser : xs;
+    const float* yv_src = sstaged ? sser + m * D : ys;
     float* gx = a.grad_x + xoff;
     float* gy = a.grad_y + yoff;
-    for (int i = lane; i < m; i += kWave) {
+    for (int t = tid; t < m * D; t += kBwdThreads) {
+        const int i = t / D, p = t - i * D;
         const int j0 = rlo[i], j1 = rhi[i];
-        for (int p = 0; p < D; ++p) {
-            const double xv = xs[(int64_t)i * D + p];
-            double acc = 0.0;
-            for (int j = j0; j <= j1; ++j) acc += xv - (double)ys[(int64_t)j * D + p];
-            gx[(int64_t)i * D + p] = (float)((double)g2 * acc);
-        }
+        const double xv = xv_src[t];
+        double acc = 0.0;
+        for (int j = j0; j <= j1; ++j) acc += xv - (double)yv_src[j * D + p];
+        gx[t] = (float)((double)g2 * acc);
     }
-    for (int j = lane; j < n; j += kWave) {
+    for (int t = tid; t < n * D; t += kBwdThreads) {
+        const int j = t / D, p = t - j * D;
         const int i0 = clo[j], i1 = chi[j];
-        for (int p = 0; p < D; ++p) {
-            const double yv = ys[(int64_t)j * D + p];
-            double acc = 0.0;
-            for (int i = i0; i <= i1; ++i) acc += yv - (double)xs[(int64_t)i * D + p];
-            gy[(int64_t)j * D + p] = (float)((double)g2 * acc);
-        }
+        const double yv = yv_src[t];
+        double acc = 0.0;
+        for (int i = i0; i <= i1; ++i) acc += yv - (double)xv_src[i * D + p];
+        gy[t] = (float)((double)g2 * acc);
     }
 }
 
-__global__ __launch_bounds__(64) void dtw_bwd_kernel(DtwBwdArgs a) {
+__global__ __launch_bounds__(kBwdThreads) void dtw_bwd_kernel(DtwBwdArgs a) {
     if (!a.counter) {
         bwd_item(a, blockIdx.x);
         return;
     }
+    __shared__ int s_item;
     for (;;) {
-        const int item = wave_next_item(a.counter);
-        if (item >= a.nitems) break;
+        __syncthreads();   // the previous item's LDS is free, s_item may be rewritten
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
+        const int item = s_item;
+        if (item >= a.nitems) break;
         bwd_item(a, item);
     }
 }
 
-size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words) {
-    const int64_t cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
-    return (size_t)(2 * (maxm + maxn)) * 4 + (size_t)cap * 4;
+static int64_t bwd_series_cap(int maxm, int maxn, int maxd) {
+    const int64_t f = (int64_t)(maxm + maxn) * maxd;
+    return f <= kBwdSeriesLdsFloats ? f : 0;
 }
 
-hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int nitems,
+size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words, int maxd) {
+    const int64_t cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
+    return (size_t)(2 * (maxm + maxn)) * 4 + (size_t)cap * 4 + (size_t)bwd_series_cap(maxm, maxn, maxd) * 4;
+}
+
+hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int maxd, int nitems,
                           int grid, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     DtwBwdArgs b = a;
     b.runs_ints = 2 * (maxm + maxn);
-    // the kernel stages a pair's codes only when they fit the reserved words
+    // the kernel stages a pair's codes (series) only when they fit the reserved words
     b.stage_cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
+    b.series_cap = bwd_series_cap(maxm, maxn, maxd);
     b.nitems = nitems;
-    const size_t lds = bwd_lds_bytes(maxm, maxn, max_words);
-    hipLaunchKernelGGL(dtw_bwd_kernel, dim3(b.counter ? grid : nitems), dim3(64), lds, s, b);
+    const size_t lds = bwd_lds_bytes(maxm, maxn, max_words, maxd);
+    const int blocks = b.counter ? std::max(1, std::min(grid, nitems)) : nitems;
+    hipLaunchKernelGGL(dtw_bwd_kernel, dim3(blocks), dim3(kBwdThreads), lds, s, b);
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct DtwBwdArgs {
     float* grad_y;
     int32_t runs_ints;       // LDS ints reserved for the row/column runs (>= 2*(m+n) of every pair)
     int64_t stage_cap;       // u32 words of LDS available for staging a pair's codes
+    int64_t series_cap;      // floats of LDS available for staging a pair's x and y (0: read them from HBM)
     int32_t* counter;        // non-null: persistent waves take items 0..nitems-1 from it
     int32_t nitems;
     int32_t urows;           // uniform: the pairs ran on the row mapping
@@ -90,9 +91,9 @@ size_t fwd_lds_bytes(const DtwFwdArgs& a, bool rows, bool f64);
 hipError_t launch_dtw_rows_pipe(const DtwFwdArgs& a, bool f64, bool save, int K, int nitems, int grid,
                                 hipStream_t s);
 size_t pipe_lds_bytes(int maxn, int D, int K, bool f64);
-hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int nitems,
+hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int maxd, int nitems,
                           int grid, hipStream_t s);
-size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words);
+size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words, int maxd);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
 
 // ------------------------------------------------------------- index build
