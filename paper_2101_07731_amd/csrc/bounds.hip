@@ -222,14 +222,45 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
 }
 
 // ------------------------------------------------------------------- K6
+// Chunk k (components 4k .. 4k+3, zero past D) of the point at pt; vec: one
+// 16-byte load (D a multiple of 4, pt 16-byte aligned).  Chunks at or past D
+// (the chunk count is padded up to an instantiated width) read nothing.
+__device__ __forceinline__ float4 point_chunk(const float* __restrict__ pt, int k, int D, bool vec) {
+    if (vec) return 4 * k < D ? *reinterpret_cast<const float4*>(pt + 4 * k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = 4 * k + c < D ? pt[4 * k + c] : 0.0f;
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// dst[r * NCH + k] = chunk k of point r * rstride of the series at src, for
+// rows r < rows, by one wave with eight chunks per lane in flight.
+template <int NCH>
+__device__ __forceinline__ void stage_point_chunks(float4* dst, const float* __restrict__ src, int rows, int rstride,
+                                                   int D, bool vec, int lane) {
+    const int total = rows * NCH;
+    auto at = [&](int t) __attribute__((always_inline)) {
+        return point_chunk(src + (int64_t)(t / NCH) * rstride * D, t % NCH, D, vec);
+    };
+    int t = lane;
+    for (; t + 7 * kWave < total; t += 8 * kWave) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = at(t + u * kWave);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[t + u * kWave] = v[u];
+    }
+    for (; t < total; t += kWave) dst[t] = at(t);
+}
+
 // LB_TI (LB_TIP with optional TOP, Sec. 4.1-4.2, Fig. 3) of one listed
 // pair per wave.  Lane k (and k + 64 with two slots) holds band offset k,
 // i.e. cell (i, i - W + k) of row i.  The cell of row i+1 on the same
 // column is offset k - 1, so both the (L, U) pair (Eqs. 7-8) and the
 // running column minimum of max(0, L) move one lane down per row (DPP
 // shift); a column's minimum is final when it leaves offset 0.  Exact rows
-// (i = 0 and i mod P = 0) compute e(q_i, c_j) (query point from scalar
-// loads, candidate point per lane); the top cell of each row takes the
+// (i = 0 and i mod P = 0) compute e(q_i, c_j) (query point broadcast from
+// LDS, candidate point per lane); the top cell of each row takes the
 // precomputed e(q_i, c_{i+W}) under TOP, else Eqs. 9-10 from its left
 // neighbour with gamma_j = e(c_{j-1}, c_j) from the index.
 // TOP and the point width (NCH float4 chunks, zero-padded) are template
@@ -271,34 +302,48 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         }
         const float* qs = a.Q + (int64_t)q * m * D;
         const float* cs = a.C + (int64_t)ref * n * D;
+        // points as whole 16-byte chunks when D is a multiple of 4 and both series are aligned
+        const bool vec = (D & 3) == 0 && ((reinterpret_cast<uintptr_t>(qs) | reinterpret_cast<uintptr_t>(cs)) & 15) == 0;
         __syncthreads();
-        for (int i = lane; i < m; i += kWave) dqs[i] = a.qstep[(int64_t)q * m + i];
-        for (int j = lane; j < n; j += kWave) gcs[j] = a.gamma[(int64_t)ref * n + j];
-        auto chunk = [&](const float* pt, int k) __attribute__((always_inline)) -> float4 {
-            float v[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = 4 * k + c < D ? pt[4 * k + c] : 0.0f;
-            return make_float4(v[0], v[1], v[2], v[3]);
-        };
-        for (int t = lane; t < n * NCH; t += kWave) cst[t] = chunk(cs + (int64_t)(t / NCH) * D, t % NCH);
+        copy_to_lds(dqs, a.qstep + (int64_t)q * m, m, lane, kWave);
+        copy_to_lds(gcs, a.gamma + (int64_t)ref * n, n, lane, kWave);
+        stage_point_chunks<NCH>(cst, cs, n, 1, D, vec, lane);
         // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
-        for (int t = lane; t < ti_exact_rows(m, P) * NCH; t += kWave) {
-            const int r = t / NCH;
-            qex[t] = chunk(qs + (int64_t)(P > 0 ? r * P : 0) * D, t % NCH);
-        }
+        stage_point_chunks<NCH>(qex, qs, ti_exact_rows(m, P), P > 0 ? P : 0, D, vec, lane);
         if (TOP) {
-            for (int i = lane; i < m; i += kWave) {
-                const int j = i + W;
-                float d = INF;
-                if (j < n) {
-                    float s = 0.0f;
-                    for (int p = 0; p < D; ++p) {
-                        const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
-                        s = __builtin_fmaf(t, t, s);
-                    }
-                    d = __builtin_sqrtf(s);
+            // e(q_i, c_{i+W}): query chunks of several rows in flight, candidate chunks from LDS;
+            // components summed in index order (padding adds exact zeros)
+            __syncthreads();
+            constexpr int RU = NCH <= 2 ? 4 : (NCH <= 4 ? 2 : 1);
+            for (int i0 = lane; i0 < m; i0 += RU * kWave) {
+                float4 qv[RU][NCH];
+#pragma unroll
+                for (int r = 0; r < RU; ++r) {
+                    const int i = i0 + r * kWave;
+#pragma unroll
+                    for (int k = 0; k < NCH; ++k)
+                        qv[r][k] = i < m ? point_chunk(qs + (int64_t)i * D, k, D, vec) : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                top[i] = d;
+#pragma unroll
+                for (int r = 0; r < RU; ++r) {
+                    const int i = i0 + r * kWave;
+                    if (i >= m) break;
+                    const int j = i + W;
+                    float d = INF;
+                    if (j < n) {
+                        float s = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < NCH; ++k) {
+                            const float4 c = cst[j * NCH + k];
+                            float t = qv[r][k].x - c.x; s = __builtin_fmaf(t, t, s);
+                            t = qv[r][k].y - c.y; s = __builtin_fmaf(t, t, s);
+                            t = qv[r][k].z - c.z; s = __builtin_fmaf(t, t, s);
+                            t = qv[r][k].w - c.w; s = __builtin_fmaf(t, t, s);
+                        }
+                        d = __builtin_sqrtf(s);
+                    }
+                    top[i] = d;
+                }
             }
         }
         __syncthreads();

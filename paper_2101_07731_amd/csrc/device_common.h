@@ -21,6 +21,22 @@ __device__ __forceinline__ uint32_t wave_ror1(uint32_t v) {
 __device__ __forceinline__ uint32_t wave_rol1(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kWaveRol1, 0xF, 0xF, false);
 }
+// Copies n elements from global memory to LDS with `nthreads` threads, eight
+// loads in flight per thread (a loop of load-then-store waits for every
+// load in turn).
+template <typename T>
+__device__ __forceinline__ void copy_to_lds(T* dst, const T* __restrict__ src, int64_t n, int tid, int nthreads) {
+    int64_t t = tid;
+    for (; t + 7 * (int64_t)nthreads < n; t += 8 * (int64_t)nthreads) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[t + u * (int64_t)nthreads];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[t + u * (int64_t)nthreads] = v[u];
+    }
+    for (; t < n; t += nthreads) dst[t] = src[t];
+}
+
 // Directed roundings of a non-negative double to float.
 __device__ __forceinline__ float round_down_f(double x) {
     float f = (float)x;

@@ -40,6 +40,26 @@ struct CodeMap {
         nwb = (tmax + 15) / 16;
         (void)m;
     }
+    // The word of (i, j) as base + ln with 0 <= ln < 64: the words base .. base + 63 are one
+    // round block of every band offset (diagonal) or one step block of every row of a 64-row
+    // block (rows).
+    __device__ __forceinline__ void locate64(int i, int j, int64_t& base, int& ln, int& shift) const {
+        if (diag) {
+            const int sigma = (j - i) + off;
+            const int slot = sigma & 1;
+            const int r = (i + j - slot) >> 1;
+            ln = sigma >> 1;
+            base = (int64_t)(r >> 3) * G;
+            shift = (r & 7) * 4 + 2 * slot;
+        } else {
+            const int b = i / kRowBlock, l = i - b * kRowBlock;
+            const int jlo = max(0, b * kRowBlock - W);
+            const int t = j - jlo + l;
+            ln = l;
+            base = ((int64_t)b * nwb + (t >> 4)) * kWave;
+            shift = (t & 15) * 2;
+        }
+    }
     __device__ __forceinline__ void locate(int i, int j, int64_t& word, int& shift) const {
         if (diag) {
             const int sigma = (j - i) + off;
@@ -87,39 +107,44 @@ __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     const uint32_t* gcodes = a.codes + soff;
     const float* xs = a.x + xoff;
     const float* ys = a.y + yoff;
-    if (staged)
-        for (int64_t w = tid; w < words; w += kBwdThreads) scodes[w] = gcodes[w];
+    if (staged) copy_to_lds(scodes, gcodes, words, tid, kBwdThreads);
     if (sstaged) {
-        for (int t = tid; t < m * D; t += kBwdThreads) sser[t] = xs[t];
-        for (int t = tid; t < n * D; t += kBwdThreads) sser[m * D + t] = ys[t];
+        copy_to_lds(sser, xs, (int64_t)m * D, tid, kBwdThreads);
+        copy_to_lds(sser + m * D, ys, (int64_t)n * D, tid, kBwdThreads);
     }
     __syncthreads();
 
-    if (tid == 0) {
+    if (tid < kWave) {
+        // wave 0 walks with wave-uniform (scalar) position: each lane holds one word of the
+        // current block of 64 (reloaded when the path leaves it) and a step reads its word
+        // from the lane that holds it, with no LDS round trip; lane 0 writes the runs
+        const int lane = tid;
         int i = m - 1, j = n - 1;
-        rhi[i] = j;
-        chi[j] = i;
-        int64_t cw_at = -1;
-        uint32_t cw = 0;
+        if (lane == 0) { rhi[i] = j; chi[j] = i; }
+        int64_t cur = -1;
+        uint32_t held = 0;
         while (i > 0 || j > 0) {
-            int64_t w;
-            int sh;
-            cm.locate(i, j, w, sh);
-            if (w != cw_at) {
-                cw = staged ? scodes[w] : gcodes[w];
-                cw_at = w;
+            int64_t base;
+            int ln, sh;
+            cm.locate64(i, j, base, ln, sh);
+            if (base != cur) {
+                const int64_t w = base + lane;
+                held = w < words ? (staged ? scodes[w] : gcodes[w]) : 0u;
+                cur = base;
             }
-            const int code = (cw >> sh) & 3;
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)held, ln);
+            const int code = (word >> sh) & 3;
             int pi = i, pj = j;
             if (code == 0) { pi = i - 1; pj = j - 1; }
             else if (code == 1) { pi = i - 1; }
             else { pj = j - 1; }
-            if (pi != i) { rlo[i] = j; rhi[pi] = pj; }
-            if (pj != j) { clo[j] = i; chi[pj] = pi; }
+            if (lane == 0) {
+                if (pi != i) { rlo[i] = j; rhi[pi] = pj; }
+                if (pj != j) { clo[j] = i; chi[pj] = pi; }
+            }
             i = pi; j = pj;
         }
-        rlo[0] = 0;
-        clo[0] = 0;
+        if (lane == 0) { rlo[0] = 0; clo[0] = 0; }
     }
     __syncthreads();
 
