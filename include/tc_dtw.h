@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define TC_DTW_ABI_VERSION 3
+#define TC_DTW_ABI_VERSION 4
 
 typedef struct ihipStream_t* tc_dtw_stream; /* same type as hipStream_t; NULL = default stream */
 
@@ -295,9 +295,50 @@ typedef struct {
                                the paper's subject); 1: independent DTW (Sec. 2 DTW_I, the sum of
                                the dimensions' univariate DTWs), with LB_MV or no bounds, uniform
                                lengths, W_eff <= 63 and up to 16 dimensions */
+    const struct tc_dtw_cand_boxes* pc_cand;  /* HOST pointer or NULL.  NULL: LB_PC boxes the
+                               query's points when the query arrives (Sec. 5).  Otherwise LB_PC, in
+                               tc_dtw_knn and tc_dtw_lower_bounds, uses these boxes of the candidates'
+                               points, built ahead of time (Sec. 8; see tc_dtw_build_cand_boxes) */
 } tc_dtw_knn_params;
 
 void tc_dtw_knn_params_default(tc_dtw_knn_params* p);
+
+/* ------------------------------------------------ candidate-side boxes ---
+ * LB_PC with the roles of query and candidate swapped (Sec. 8: the boxes of
+ * the candidate series are computed once, when the database is set up,
+ * instead of the query's boxes each time a query arrives).  For every
+ * candidate c and every group g of w = p->pc_group consecutive QUERY
+ * positions, the boxes of c's points in the expanded window
+ * [g*w - W, g*w + w - 1 + W] (Sec. 5's quantisation-based clustering
+ * applied to c, with p->pc_levels, pc_clusters and pc_min_cell).  The bound
+ * of a pair is then the sum over the query's points of the smallest squared
+ * distance to a box of the point's group; it bounds the same banded DTW
+ * because the band is symmetric and DTW(q, c) = DTW(c, q) (Sec. 2, Eq. 1).
+ * The boxes depend on the query length, the window and those parameters; a
+ * search checks them against the descriptor (ERR_INVALID on a mismatch).
+ *   ix         index with uniform candidate lengths (ERR_UNSUPPORTED otherwise)
+ *   query_len  the length of the queries the boxes will serve (>= 1)
+ *   buf        DEVICE, at least tc_dtw_cand_boxes_bytes() bytes, caller-owned
+ *              and kept alive while searches use it; receives
+ *              float boxes[count][groups][K][dim][2] (lo, hi; unused boxes
+ *              +inf, -inf) and, at byte offset off_nbox, int32 nbox[count][groups]
+ *   out        HOST descriptor, filled on success (pass it as p->pc_cand)
+ * tc_dtw_cand_boxes_bytes returns 0 for invalid arguments.  Errors:
+ * ERR_INVALID (bad index, length, parameters, null or short buffer),
+ * ERR_UNSUPPORTED (ragged index, pc_levels^dim >= 2^63), ERR_HIP. */
+typedef struct tc_dtw_cand_boxes {
+    void* buf;            /* DEVICE */
+    int64_t off_nbox;     /* byte offset of nbox inside buf */
+    int32_t count, dim, query_len, cand_len;
+    int32_t weff;         /* band half-width the boxes were built for */
+    int32_t groups;       /* ceil(query_len / pc_group) */
+    int32_t levels, clusters, group;
+    float min_cell;
+} tc_dtw_cand_boxes;
+
+size_t tc_dtw_cand_boxes_bytes(const tc_dtw_index* ix, int32_t query_len, const tc_dtw_knn_params* p);
+tc_dtw_status tc_dtw_build_cand_boxes(const tc_dtw_index* ix, int32_t query_len, const tc_dtw_knn_params* p,
+                                      void* buf, size_t bytes, tc_dtw_cand_boxes* out, tc_dtw_stream stream);
 
 /* ------------------------------------------------------- lower bounds ---
  * tc_dtw_lower_bounds: the dense bound matrix lb[q][c] (squared cost) of one

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcdtw.so")
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
 F64 = 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class TcDtwError(RuntimeError):
@@ -61,12 +61,19 @@ class Index(C.Structure):
                 ("total_len", C.c_int64), ("reserved", C.c_int64 * 3)]
 
 
+class CandBoxes(C.Structure):
+    _fields_ = [("buf", C.c_void_p), ("off_nbox", C.c_int64), ("count", C.c_int32), ("dim", C.c_int32),
+                ("query_len", C.c_int32), ("cand_len", C.c_int32), ("weff", C.c_int32), ("groups", C.c_int32),
+                ("levels", C.c_int32), ("clusters", C.c_int32), ("group", C.c_int32), ("min_cell", C.c_float)]
+
+
 class KnnParams(C.Structure):
     _fields_ = [("window", Window), ("bounds", C.c_uint32), ("early_abandon", C.c_int32),
                 ("ti_period", C.c_int32), ("ti_top", C.c_int32), ("pc_levels", C.c_int32),
                 ("pc_clusters", C.c_int32), ("pc_group", C.c_int32), ("pc_min_cell", C.c_float),
                 ("trigger_ti", C.c_float), ("trigger_pc", C.c_float), ("prune_margin", C.c_float),
-                ("seed_r", C.c_int32), ("k", C.c_int32), ("independent", C.c_int32)]
+                ("seed_r", C.c_int32), ("k", C.c_int32), ("independent", C.c_int32),
+                ("pc_cand", C.POINTER(CandBoxes))]
 
 
 class KnnStats(C.Structure):
@@ -102,6 +109,9 @@ _SIGS = {
     "tc_dtw_index_bytes": (C.c_size_t, [C.POINTER(Batch)]),
     "tc_dtw_build_index": (C.c_int, [C.POINTER(Batch), C.c_void_p, C.c_size_t, C.POINTER(Index), C.c_void_p]),
     "tc_dtw_knn_params_default": (None, [C.POINTER(KnnParams)]),
+    "tc_dtw_cand_boxes_bytes": (C.c_size_t, [C.POINTER(Index), C.c_int32, C.POINTER(KnnParams)]),
+    "tc_dtw_build_cand_boxes": (C.c_int, [C.POINTER(Index), C.c_int32, C.POINTER(KnnParams), C.c_void_p,
+                                          C.c_size_t, C.POINTER(CandBoxes), C.c_void_p]),
     "tc_dtw_lower_bounds_workspace_bytes": (C.c_size_t, [C.POINTER(Index), C.POINTER(Batch),
                                                          C.POINTER(KnnParams), C.c_uint32]),
     "tc_dtw_lower_bounds": (C.c_int, [C.POINTER(Index), C.POINTER(Batch), C.POINTER(KnnParams), C.c_uint32,

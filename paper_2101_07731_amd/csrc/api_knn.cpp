@@ -70,6 +70,7 @@ struct KnnPlan {
     int nq, nc, m, n, D, W, R, P, cap, ntiles, k;
     bool indep;
     bool plain, abandon, gate, pc, ti;
+    bool cand;              // LB_PC against candidate-side boxes (params.pc_cand)
     int ngroups, max_pts;
     size_t o_env, o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_glist, o_gcnt, o_prefix,
         o_items, o_counters, o_key, o_stats, o_boxes, o_nbox, o_qstep, o_glb, o_tlist, o_tlb, o_tout,
@@ -102,6 +103,16 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.ti = (p->bounds & TC_DTW_LB_TI) != 0;
     K.ngroups = (K.n + p->pc_group - 1) / p->pc_group;
     K.max_pts = std::min(K.m, p->pc_group + 2 * K.W);
+    K.cand = p->pc_cand != nullptr;
+    if (K.cand) {
+        const tc_dtw_cand_boxes* cb = p->pc_cand;
+        if (!cb->buf || cb->count != K.nc || cb->dim != K.D || cb->query_len != K.m || cb->cand_len != K.n ||
+            cb->weff != K.W || cb->levels != p->pc_levels || cb->clusters != p->pc_clusters ||
+            cb->group != p->pc_group || !(cb->min_cell == p->pc_min_cell) ||
+            cb->groups != (K.m + p->pc_group - 1) / p->pc_group)
+            return fail(TC_DTW_ERR_INVALID,
+                        "params.pc_cand was built for another index, query length, window or LB_PC parameters");
+    }
     K.k = p->k;
     if (K.k > K.nc) return fail(TC_DTW_ERR_INVALID, "k exceeds the number of candidates");
     // at least k seeds, so that the k-th best is finite before the compaction
@@ -131,8 +142,8 @@ static tc_dtw_status make_knn_plan(const tc_dtw_index* ix, const tc_dtw_batch* q
     K.o_stats = at(kNumStats * 8);
     const bool any_pc = K.pc || true;   // the dense bound matrix may ask for LB_PC / LB_TI too
     (void)any_pc;
-    K.o_boxes = at((size_t)K.nq * K.ngroups * p->pc_clusters * K.D * 2 * 4);
-    K.o_nbox = at((size_t)K.nq * K.ngroups * 4);
+    K.o_boxes = at(K.cand ? 0 : (size_t)K.nq * K.ngroups * p->pc_clusters * K.D * 2 * 4);
+    K.o_nbox = at(K.cand ? 0 : (size_t)K.nq * K.ngroups * 4);
     K.o_qstep = at((size_t)K.nq * K.m * 4);
     K.o_glb = at(K.gate ? (size_t)K.nq * K.cap * 4 : 0);
     K.o_tlist = at(K.ti ? (size_t)K.nq * K.cap * 4 : 0);
@@ -238,6 +249,13 @@ static PcArgs pc_args(const KnnPlan& K, const KnnPlanDev& d, const KnnExtra& x, 
     a.floor_len = p->pc_min_cell;
     a.range = reinterpret_cast<const float*>(static_cast<const char*>(ix->buf) + ix->off_range);
     a.boxes = x.boxes; a.nbox = x.nbox;
+    if (K.cand) {
+        const tc_dtw_cand_boxes* cb = p->pc_cand;
+        a.cand = 1;
+        a.boxes = static_cast<float*>(cb->buf);
+        a.nbox = reinterpret_cast<int32_t*>(static_cast<char*>(cb->buf) + cb->off_nbox);
+        a.ngroups = cb->groups;
+    }
     a.cap = K.cap;
     a.prefix = d.prefix; a.item_query = d.item_query; a.counter = d.counters + 2;
     a.lb_mv = d.lb;
@@ -667,7 +685,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     mark(0);
     if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
     if (K.ti && (e = launch_query_steps(d.Q, K.nq, K.m, K.D, x.qstep, s)) != hipSuccess) return hip_fail(e, "query steps");
-    if (K.pc && (e = launch_pc_boxes(pc_args(K, d, x, ix, p), s)) != hipSuccess) return hip_fail(e, "boxes");
+    if (K.pc && !K.cand && (e = launch_pc_boxes(pc_args(K, d, x, ix, p), s)) != hipSuccess) return hip_fail(e, "boxes");
     mark(1);
     if (!K.plain) {
         if ((e = launch_lb_mv(d, d.lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
@@ -788,6 +806,78 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     return ok();
 }
 
+// ------------------------------------------------ candidate-side boxes
+// LB_PC with the roles swapped (Sec. 8): k_pc_boxes run over the candidates
+// as the boxed series, with groups over query positions.
+struct CandBoxGeom {
+    int count, n, m, D, W, groups, max_pts, K;
+    size_t off_nbox, bytes;
+};
+
+static tc_dtw_status cand_box_geom(const tc_dtw_index* ix, int32_t query_len, const tc_dtw_knn_params* p,
+                                   CandBoxGeom& g) {
+    tc_dtw_status st;
+    if ((st = check_index(ix)) != TC_DTW_OK) return st;
+    if ((st = check_params(p)) != TC_DTW_OK) return st;
+    if (ix->uniform_len <= 0) return fail(TC_DTW_ERR_UNSUPPORTED, "candidate-side boxes need uniform candidate lengths");
+    if (query_len < 1) return fail(TC_DTW_ERR_INVALID, "query_len must be >= 1");
+    g.count = ix->count;
+    g.n = ix->uniform_len;
+    g.m = query_len;
+    g.D = ix->dim;
+    g.W = window_eff(g.m, g.n, p->window);
+    g.groups = (g.m + p->pc_group - 1) / p->pc_group;
+    g.max_pts = std::min(g.n, p->pc_group + 2 * g.W);
+    g.K = p->pc_clusters;
+    unsigned long long pw = 1;   // cell keys in base Lv need Lv^D < 2^63
+    for (int t = 0; t < g.D; ++t) {
+        if (pw > (1ull << 62) / (unsigned long long)p->pc_levels)
+            return fail(TC_DTW_ERR_UNSUPPORTED, "pc_levels^dim does not fit 63 bits");
+        pw *= (unsigned long long)p->pc_levels;
+    }
+    if (pc_boxes_lds_bytes(g.max_pts, g.K, g.D) > 163840)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "expanded window too long for the LDS box construction");
+    const size_t boxes = (size_t)g.count * g.groups * g.K * g.D * 2 * 4;
+    g.off_nbox = (boxes + 255) & ~(size_t)255;
+    g.bytes = g.off_nbox + (size_t)g.count * g.groups * 4;
+    return TC_DTW_OK;
+}
+
+size_t tc_dtw_cand_boxes_bytes(const tc_dtw_index* ix, int32_t query_len, const tc_dtw_knn_params* p) {
+    CandBoxGeom g;
+    return cand_box_geom(ix, query_len, p, g) == TC_DTW_OK ? g.bytes : 0;
+}
+
+tc_dtw_status tc_dtw_build_cand_boxes(const tc_dtw_index* ix, int32_t query_len, const tc_dtw_knn_params* p,
+                                      void* buf, size_t bytes, tc_dtw_cand_boxes* out, tc_dtw_stream stream) {
+    CandBoxGeom g;
+    tc_dtw_status st = cand_box_geom(ix, query_len, p, g);
+    if (st != TC_DTW_OK) return st;
+    if (!out) return fail(TC_DTW_ERR_INVALID, "null descriptor");
+    if (!buf || bytes < g.bytes) return fail(TC_DTW_ERR_INVALID, "buffer smaller than tc_dtw_cand_boxes_bytes()");
+    if ((st = check_device()) != TC_DTW_OK) return st;
+    PcArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Q = reinterpret_cast<const float*>(static_cast<const char*>(ix->buf) + ix->off_series);
+    a.nq = g.count; a.m = g.n; a.n = g.m; a.D = g.D; a.W = g.W;
+    a.Lv = p->pc_levels; a.K = g.K; a.w = p->pc_group;
+    a.ngroups = g.groups; a.max_pts = g.max_pts;
+    a.floor_len = p->pc_min_cell;
+    a.range = reinterpret_cast<const float*>(static_cast<const char*>(ix->buf) + ix->off_range);
+    a.boxes = static_cast<float*>(buf);
+    a.nbox = reinterpret_cast<int32_t*>(static_cast<char*>(buf) + g.off_nbox);
+    hipError_t e = launch_pc_boxes(a, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "candidate boxes");
+    std::memset(out, 0, sizeof *out);
+    out->buf = buf;
+    out->off_nbox = (int64_t)g.off_nbox;
+    out->count = g.count; out->dim = g.D; out->query_len = g.m; out->cand_len = g.n;
+    out->weff = g.W; out->groups = g.groups;
+    out->levels = p->pc_levels; out->clusters = p->pc_clusters; out->group = p->pc_group;
+    out->min_cell = p->pc_min_cell;
+    return ok();
+}
+
 size_t tc_dtw_lower_bounds_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,
                                            const tc_dtw_knn_params* p, uint32_t kind) {
     if (is_ragged_search(ix, queries)) {
@@ -869,7 +959,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         if ((e = launch_lb_mv(d, lb, s)) != hipSuccess) return hip_fail(e, "lb_mv");
     } else if (kind == TC_DTW_LB_PC) {
         PcArgs a = pc_args(K, d, x, ix, p);
-        if ((e = launch_pc_boxes(a, s)) != hipSuccess) return hip_fail(e, "boxes");
+        if (!K.cand && (e = launch_pc_boxes(a, s)) != hipSuccess) return hip_fail(e, "boxes");
         a.in_list = nullptr; a.in_uniform = K.nc; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
         if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
             return hip_fail(e, "pc items");

@@ -157,11 +157,13 @@ __global__ __launch_bounds__(64) void k_pc_boxes(PcArgs a) {
 // query's boxes are a few KB, read through the caches), summed over points.
 // In search mode a pair is only evaluated when its LB_MV exceeds e^2 bsf,
 // and the evaluation stops once the partial sum already proves the pair
-// prunable.
+// prunable.  With candidate-side boxes (Sec. 8, roles swapped) the points
+// are the query's and the boxes the candidate's, grouped over query positions.
 template <int DMAX>
 __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
     const int lane = threadIdx.x;
-    const int D = a.D, n = a.n, K = a.K, w = a.w;
+    const bool cand = a.cand != 0;
+    const int D = a.D, n = cand ? a.m : a.n, K = a.K, w = a.w;
     const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
     for (;;) {
         const int item = wave_next_item(a.counter);
@@ -179,9 +181,11 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
                 continue;
             }
         }
-        const float* c = a.C + (int64_t)ref * n * D;
-        const float* bxq = a.boxes + (int64_t)q * a.ngroups * K * D * 2;
-        const int32_t* nbq = a.nbox + (int64_t)q * a.ngroups;
+        // the evaluated points, and the series whose boxes they are measured against
+        const float* c = cand ? a.Q + (int64_t)q * n * D : a.C + (int64_t)ref * n * D;
+        const int owner = cand ? ref : q;
+        const float* bxq = a.boxes + (int64_t)owner * a.ngroups * K * D * 2;
+        const int32_t* nbq = a.nbox + (int64_t)owner * a.ngroups;
         const double stop = a.key ? (double)bsf / a.keep : __builtin_inf();
         float acc = 0.0f;
         for (int j0 = 0; j0 < n; j0 += kWave) {
@@ -530,7 +534,15 @@ size_t pc_boxes_lds_bytes(int max_pts, int K, int D) {
 
 hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s) {
     const size_t lds = pc_boxes_lds_bytes(a.max_pts, a.K, a.D);
-    hipLaunchKernelGGL(k_pc_boxes, dim3(a.ngroups, a.nq), dim3(64), lds, s, a);
+    // the boxed series in launches of at most 65535 (the grid's y limit)
+    for (int q0 = 0; q0 < a.nq; q0 += 65535) {
+        PcArgs b = a;
+        b.nq = std::min(65535, a.nq - q0);
+        b.Q = a.Q + (int64_t)q0 * a.m * a.D;
+        b.boxes = a.boxes + (int64_t)q0 * a.ngroups * a.K * a.D * 2;
+        b.nbox = a.nbox + (int64_t)q0 * a.ngroups;
+        hipLaunchKernelGGL(k_pc_boxes, dim3(a.ngroups, b.nq), dim3(64), lds, s, b);
+    }
     return hipGetLastError();
 }
 

@@ -276,8 +276,10 @@ struct PcArgs {
     int32_t Lv, K, w, ngroups, max_pts;
     float floor_len;           // <= 0: 1e-5 * (range[1] - range[0])
     const float* range;        // index value range (min, max)
-    float* boxes;              // [nq][ngroups][K][D][2]
-    int32_t* nbox;             // [nq][ngroups]
+    float* boxes;              // [nq][ngroups][K][D][2] (cand: [nc][ngroups][K][D][2])
+    int32_t* nbox;             // [nq][ngroups] (cand: [nc][ngroups])
+    int32_t cand;              // 1: the boxes are the candidates' (over query-position groups) and
+                               // the query's points are evaluated against them
     // list evaluation
     const uint32_t* in_list;   // [nq][cap] or null (every candidate)
     const int32_t* in_cnt;

@@ -34,7 +34,8 @@ class Index:
 
 
 def params(window=None, frac=(1, 10), bounds="mv", **kw):
-    """tc_dtw_knn_params from keyword arguments (names as in the C struct)."""
+    """tc_dtw_knn_params from keyword arguments (names as in the C struct;
+    pc_cand takes a CandBoxes object)."""
     p = L.KnnParams()
     L.lib().tc_dtw_knn_params_default(C.byref(p))
     p.window = window_spec(window, frac)
@@ -42,8 +43,30 @@ def params(window=None, frac=(1, 10), bounds="mv", **kw):
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError("unknown search parameter " + k)
+        if k == "pc_cand":
+            v = C.pointer(v.desc) if v is not None else None
         setattr(p, k, v)
     return p
+
+
+class CandBoxes:
+    """Candidate-side LB_PC boxes of an index (tc_dtw_build_cand_boxes; the
+    roles of Sec. 5 swapped, as Sec. 8 suggests), built once for a query
+    length, window and LB_PC parameters, and passed to searches as
+    pc_cand=... with the same parameters.  Owns its device buffer."""
+
+    def __init__(self, index, query_len, **kw):
+        p = params(**kw)
+        lib = L.lib()
+        nbytes = lib.tc_dtw_cand_boxes_bytes(C.byref(index.ix), int(query_len), C.byref(p))
+        if nbytes == 0:
+            L.check(lib.tc_dtw_build_cand_boxes(C.byref(index.ix), int(query_len), C.byref(p), None, 0,
+                                                None, _stream()))
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=index.buf.device)
+        self.desc = L.CandBoxes()
+        L.check(lib.tc_dtw_build_cand_boxes(C.byref(index.ix), int(query_len), C.byref(p),
+                                            C.c_void_p(self.buf.data_ptr()), nbytes, C.byref(self.desc),
+                                            _stream()))
 
 
 def lower_bounds(index, queries, kind="mv", **kw):

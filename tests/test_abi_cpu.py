@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     lib = L.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.tc_dtw_abi_version() == 3
+    assert lib.tc_dtw_abi_version() == 4
 
 
 def _batch(count=2, dim=3, ulen=8, data=0x1000):
@@ -210,3 +210,56 @@ def test_independent_dtw_validated_on_the_host():
     offs = (C.c_int64 * 3)(0, 512, 992)
     Qr = L.Batch(0x1000, offs, lens, 3, 8, 0, None)
     assert ws(ix, Qr) > 0 and ws(ix, Qr, independent=1) == 0            # uneven lengths
+
+
+def test_candidate_boxes_validated_on_the_host():
+    """Candidate-side LB_PC boxes: sized from the index, the query length and
+    the LB_PC parameters; a search rejects a descriptor built for another
+    query length, window or parameter set before any device call."""
+    lib = L.lib()
+    ix = L.Index()
+    ix.buf = C.c_void_p(0x4000)
+    ix.bytes = 1 << 20
+    ix.count = 10
+    ix.dim = 2
+    ix.uniform_len = 64
+    ix.max_len = 64
+    ix.ntiles = 1
+    p = L.KnnParams()
+    lib.tc_dtw_knn_params_default(C.byref(p))
+    nb = lib.tc_dtw_cand_boxes_bytes(C.byref(ix), 64, C.byref(p))
+    groups = (64 + p.pc_group - 1) // p.pc_group
+    boxes = 10 * groups * p.pc_clusters * 2 * 2 * 4
+    assert nb == (boxes + 255) // 256 * 256 + 10 * groups * 4
+    assert lib.tc_dtw_cand_boxes_bytes(C.byref(ix), 0, C.byref(p)) == 0
+    assert lib.tc_dtw_cand_boxes_bytes(C.byref(ix), 64, None) == 0
+    out = L.CandBoxes()
+    st = lib.tc_dtw_build_cand_boxes(C.byref(ix), 64, C.byref(p), C.c_void_p(0x8000), nb - 1, C.byref(out), None)
+    assert st == L.ERR_INVALID
+    ixr = L.Index()
+    C.memmove(C.byref(ixr), C.byref(ix), C.sizeof(ix))
+    ixr.uniform_len = 0
+    assert lib.tc_dtw_cand_boxes_bytes(C.byref(ixr), 64, C.byref(p)) == 0
+    # a descriptor as tc_dtw_build_cand_boxes fills it for query length 64, W = 6
+    d = L.CandBoxes(0x8000, (boxes + 255) // 256 * 256, 10, 2, 64, 64, 6, groups, p.pc_levels, p.pc_clusters,
+                    p.pc_group, p.pc_min_cell)
+    Q = L.Batch(0x1000, None, None, 3, 2, 64, None)
+
+    def ws(**kw):
+        q = L.KnnParams()
+        lib.tc_dtw_knn_params_default(C.byref(q))
+        q.bounds = L.LB_MV | L.LB_PC
+        q.pc_cand = C.pointer(d)
+        for k, v in kw.items():
+            setattr(q, k, v)
+        return lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q), C.byref(q))
+
+    assert ws() > 0
+    assert ws(pc_clusters=5) == 0
+    assert ws(pc_group=4) == 0
+    assert ws(window=L.Window(0, 1, 5)) == 0
+    Q32 = L.Batch(0x1000, None, None, 3, 2, 60, None)
+    q = L.KnnParams()
+    lib.tc_dtw_knn_params_default(C.byref(q))
+    q.pc_cand = C.pointer(d)
+    assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q32), C.byref(q)) == 0

@@ -285,6 +285,57 @@ def test_lb_pc_dense_matrix(dev, case):
     np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
 
 
+@pytest.mark.parametrize("case", [(8, 3, (1, 10), 2, 6, 6, 80), (16, 4, (1, 5), 3, 4, 6, 80),
+                                  (33, 2, (1, 10), 2, 16, 3, 33), (5, 5, (1, 10), 2, 6, 6, 71)],
+                         ids=["d8_W8_L2_K6", "d4_W16_L3_K4", "d2_W3_L2_K16_w3", "d5_m71_n80"])
+def test_lb_pc_candidate_boxes_dense_matrix(dev, case):
+    """LB_PC with the roles swapped (boxes of the candidates, built once per
+    index) against oracle.lb_pc(c, q): same rounding bar as the query-side
+    bound, the points now the query's (m of them)."""
+    from paper_2101_07731_amd import search, synth
+    D, seed, frac, Lv, K, w, m = case
+    n = 80 if D != 2 else 33
+    Q, Cs = synth.cascade_knn(nq=11, nc=90, T=n, D=D, seed=50 + seed)
+    Q = np.ascontiguousarray(Q[:, :m])
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_pc candidate boxes dense", case)
+    kw = dict(frac=frac, pc_levels=Lv, pc_clusters=K, pc_group=w)
+    cb = search.CandBoxes(ix, m, **kw)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="pc", pc_cand=cb,
+                             **kw).cpu().numpy().astype(np.float64)
+    W = O.window_eff(m, n, 0, *frac)
+    fl = _pc_floor(Cs)
+    ref = np.array([[O.lb_pc(c, q, W, Lv=Lv, K=K, w=w, floor_len=fl) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12))
+    slack = 2 * (m + D + 5) * 2.0 ** -24 * 1.01 + 1e-7
+    np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
+    # a descriptor built for another query length is refused
+    from paper_2101_07731_amd import _lib as L
+    with pytest.raises(L.TcDtwError):
+        search.lower_bounds(ix, torch.from_numpy(np.ascontiguousarray(Q[:, :m - 1])).to(dev), kind="pc",
+                            pc_cand=cb, **kw)
+
+
+@pytest.mark.parametrize("frac", [(1, 10), (1, 5)])
+def test_cascade_with_candidate_boxes(dev, frac):
+    """The search with LB_PC on candidate-side boxes returns the oracle's
+    neighbours (1-NN and k = 4)."""
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.cascade_knn(nq=30, nc=700, T=96, D=8, seed=27)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    cb = search.CandBoxes(ix, 96, frac=frac)
+    Qd = torch.from_numpy(Q).to(dev)
+    say("knn candidate boxes", frac)
+    for e in (0.0, 0.1, 0.5):
+        idx, dist, st = search.knn(ix, Qd, stats=True, frac=frac, bounds="mv+pc", trigger_pc=e, pc_cand=cb)
+        check_against_oracle(idx.cpu().numpy(), dist.cpu().numpy(), Q, Cs, *frac)
+        assert st["pruned_mv"] + st["pruned_pc"] + st["dtw_started"] == st["pairs"], st
+    idx, dist = search.knn(ix, Qd, k=4, frac=frac, bounds="mv+pc+ti", pc_cand=cb)
+    ri, rd = O.knn_exhaustive_k(Q, Cs, 4, num=frac[0], den=frac[1])
+    np.testing.assert_array_equal(idx.cpu().numpy(), ri)
+    np.testing.assert_array_equal(dist.cpu().numpy(), rd.astype(np.float32))
+
+
 @pytest.mark.parametrize("P,top", [(5, 1), (0, 0), (3, 0), (0, 1), (1, 0)])
 @pytest.mark.parametrize("frac", [(1, 10), (1, 5)])
 def test_lb_ti_dense_matrix(dev, P, top, frac):

@@ -242,6 +242,38 @@ def test_bounds_below_dtw_and_lb_ad(seed):
             assert O.lb_pc(q, c, weff, Lv, K, w) <= ad + tol
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_candidate_side_boxes_bound_the_same_dtw(seed):
+    """LB_PC with the roles swapped (Sec. 8: boxes of the candidate, built
+    ahead of time, against the query's points) is oracle.lb_pc(c, q).  It
+    bounds DTW(q, c) because the band is symmetric: DTW(q, c) = DTW(c, q)
+    (the transposed path), which the brute force over all warping paths
+    confirms on tiny pairs; with one box per single-position group it is
+    the candidate-envelope LB_MV."""
+    rng = np.random.default_rng(300 + seed)
+    for _ in range(40):
+        D = int(rng.integers(1, 5))
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(max(1, m - 4), m + 5))
+        q, c = walk(rng, m, D), walk(rng, n, D)
+        if rng.random() < 0.3:
+            c = q[rng.integers(0, m, size=n)] + 0.1 * rng.standard_normal((n, D))
+        weff = O.window_eff(m, n, int(rng.integers(0, 8)))
+        d = O.dtw(q, c, weff)
+        assert O.dtw(c, q, weff) == pytest.approx(d, rel=1e-12, abs=1e-12)
+        tol = 1e-9 * max(1.0, d)
+        for Lv, K, w in ((2, 6, 6), (3, 4, 3), (2, 16, 6)):
+            assert O.lb_pc(c, q, weff, Lv, K, w) <= O.lb_ad(c, q, weff) + tol
+            assert O.lb_pc(c, q, weff, Lv, K, w) <= d + tol
+        assert O.lb_pc(c, q, weff, Lv=2, K=1, w=1) == pytest.approx(O.lb_mv(c, q, weff), rel=1e-12, abs=1e-12)
+    for _ in range(20):
+        m, n, D = int(rng.integers(1, 6)), int(rng.integers(1, 6)), int(rng.integers(1, 3))
+        q, c = rng.standard_normal((m, D)), rng.standard_normal((n, D))
+        weff = O.window_eff(m, n, int(rng.integers(0, 3)))
+        assert brute_force_dtw(c, q, weff) == pytest.approx(brute_force_dtw(q, c, weff), rel=1e-12, abs=1e-12)
+        assert O.lb_pc(c, q, weff, 2, 2, 2) <= brute_force_dtw(q, c, weff) + 1e-9
+
+
 def test_ti_cells_bracket_true_distance():
     rng = np.random.default_rng(15)
     for _ in range(40):
