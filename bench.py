@@ -42,7 +42,7 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "total")
 
-EXTRAS = ("full_cascade", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
+EXTRAS = ("full_cascade", "cand_boxes", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
           "lb_mv_streaming", "plain_gpu")
 
 
@@ -329,6 +329,29 @@ def main():
                                "pruned_pc": stf["pruned_pc"], "pruned_ti": stf["pruned_ti"],
                                "pct_dtw_pruned": round(100.0 * (1 - stf["dtw_started"] / stf["pairs"]), 3),
                                "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3)}
+    if "cand_boxes" in extras:
+        # LB_PC (e = 0.5, so that it runs on more pairs) with the query's boxes built per query
+        # (Sec. 5) against the candidates' boxes built once per index (Sec. 8, roles swapped)
+        kwp = dict(frac=frac, bounds="mv+pc", trigger_pc=0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cb = search.CandBoxes(ix, T, frac=frac)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        res = {}
+        for name, extra in (("query_boxes", {}), ("candidate_boxes", {"pc_cand": cb})):
+            search.knn(ix, Qd, **kwp, **extra)
+            stc = {}
+
+            def run_pc(extra=extra, stc=stc):
+                stc.update(search.knn(ix, Qd, stats=True, **kwp, **extra)[2])
+
+            msc = _events_ms(run_pc, 3)
+            res[name] = {"queries_per_s": round(nq / (msc * 1e-3), 2), "pruned_pc": stc["pruned_pc"],
+                         "stage_ms_prep": round(stc["stage_ms"][0], 3),
+                         "stage_ms_lb_pc": round(stc["stage_ms"][4], 3)}
+        out["cand_boxes"] = {"bounds": "mv+pc", "trigger_pc": 0.5, "build_ms": round(build_ms, 3),
+                             "bytes": int(cb.buf.numel()), **res}
     if "knn_k10" in extras:
         # the 10 nearest neighbours of every query (same workload and bounds)
         st10 = {}
