@@ -309,7 +309,7 @@ def main():
             # bytes per survivor launch from the FETCH_SIZE / WRITE_SIZE passes on this kernel,
             # calibrated on the index copy kernel (profiles/knn_dtw_ring_traffic_1000x10000_d8.md);
             # only meaningful for that workload and build of the kernel
-            "traffic": 9.955e9 if (args.workload == "cascade" and W == 25 and args.bounds == "mv") else None,
+            "traffic": 9.949e9 if (args.workload == "cascade" and W == 25 and args.bounds == "mv") else None,
             "per_unit": "%d VALU lane-ops per band cell (d subtractions, d fused multiply-adds, "
                         "a 3-way min, an add)" % alu_ops_per_cell,
         },
