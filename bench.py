@@ -22,6 +22,7 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+T_START = time.perf_counter()
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
@@ -44,6 +45,11 @@ STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "to
 
 EXTRAS = ("full_cascade", "cand_boxes", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
           "lb_mv_streaming", "plain_gpu")
+
+
+def note(what):
+    """One progress line per bench stage on stderr (the JSON line stays alone on stdout)."""
+    print("bench: %s (%.1f s)" % (what, time.perf_counter() - T_START), file=sys.stderr, flush=True)
 
 
 def parse():
@@ -261,6 +267,7 @@ def main():
         steps.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    note("%d timed steps" % args.steps)
 
     nq, nc, T, D = Q.shape[0], Cs.shape[0], Q.shape[1], Q.shape[2]
     W = min(max(T * frac[0] // frac[1], 0), T - 1)
@@ -317,6 +324,7 @@ def main():
 
     extras = set() if args.extras is None else set(args.extras or EXTRAS)
     if "full_cascade" in extras:
+        note("full_cascade")
         kwf = dict(frac=frac, bounds="mv+pc+ti")
         search.knn(ix, Qd, **kwf)
         stf = {}
@@ -330,6 +338,7 @@ def main():
                                "pct_dtw_pruned": round(100.0 * (1 - stf["dtw_started"] / stf["pairs"]), 3),
                                "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3)}
     if "cand_boxes" in extras:
+        note("cand_boxes")
         # LB_PC (e = 0.5, so that it runs on more pairs) with the query's boxes built per query
         # (Sec. 5) against the candidates' boxes built once per index (Sec. 8, roles swapped)
         kwp = dict(frac=frac, bounds="mv+pc", trigger_pc=0.5)
@@ -353,6 +362,7 @@ def main():
         out["cand_boxes"] = {"bounds": "mv+pc", "trigger_pc": 0.5, "build_ms": round(build_ms, 3),
                              "bytes": int(cb.buf.numel()), **res}
     if "knn_k10" in extras:
+        note("knn_k10")
         # the 10 nearest neighbours of every query (same workload and bounds)
         st10 = {}
 
@@ -365,6 +375,7 @@ def main():
                           "rescored": st10["rescored"],
                           "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, st10["stage_ms"])}}
     if "knn_independent" in extras:
+        note("knn_independent")
         # independent DTW (Sec. 2 DTW_I) on the same workload, LB_MV bounds
         sti = {}
 
@@ -377,6 +388,7 @@ def main():
                                   "dtw_gcups": round(sti["cells"] / (sti["stage_ms"][5] * 1e-3) / 1e9, 2),
                                   "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, sti["stage_ms"])}}
     if "single_query_latency" in extras:
+        note("single_query_latency")
         # queries arriving one at a time (Sec. 7.1): one tc_dtw_knn call per query against the
         # same index; GPU time from events around each call, wall time including the host side
         ws1 = torch.empty(search.knn_workspace_bytes(ix, Qd[:1], **kw), dtype=torch.uint8, device=dev)
@@ -404,6 +416,7 @@ def main():
             "wall_ms_p50": round(float(np.percentile(wall_ms, 50)), 4),
             "wall_ms_p99": round(float(np.percentile(wall_ms, 99)), 4)}
     if "cascade_setup" in extras:
+        note("cascade_setup")
         # setup-stage choice of bounds and triggers on a sample of 100 queries (Sec. 6)
         best, times = search.tune_cascade(ix, Qd[:100], frac=frac)
         out["cascade_setup"] = {"sample_queries": 100, "best": "%s e_pc=%s e_ti=%s" % best,
@@ -412,8 +425,10 @@ def main():
                      ("long_knn", extra_long_knn), ("ragged_banks", extra_ragged_banks),
                      ("lb_mv_streaming", extra_lb_mv_streaming)):
         if name in extras:
+            note(name)
             out[name] = fn(dev)
     if "plain_gpu" in extras:
+        note("plain_gpu")
         kwp = dict(frac=frac, bounds="plain")
         search.knn(ix, Qd, **kwp)
         torch.cuda.synchronize()
@@ -426,6 +441,7 @@ def main():
                             "cascade_speedup": round(tp / (wall / args.steps), 3)}
 
     if not args.no_cpu:
+        note("cpu_baseline")
         import oracle as O
         nsamp = min(args.cpu_queries, nq)
         th = cpu_threads()
