@@ -3,10 +3,12 @@
 // as 2-bit argmin codes (0 = diagonal, 1 = (i-1,j), 2 = (i,j-1)).
 //
 // One block of 256 threads per pair:
-//   1. the pair's codes, and both series when they fit, are copied to LDS;
-//   2. thread 0 walks the path back from (m-1, n-1) to (0, 0), keeping the
-//      current code word in a register (consecutive steps mostly share
-//      it); a monotone path meets every row i in one run of columns
+//   1. the pair's codes, and both series when they fit, are copied to LDS
+//      (eight loads in flight per thread);
+//   2. wave 0 walks the path back from (m-1, n-1) to (0, 0) at a
+//      wave-uniform position, its lanes holding the 64 code words around
+//      it (consecutive steps mostly stay among them), each step reading its
+//      word from the lane that holds it; a monotone path meets every row i in one run of columns
 //      [rlo_i, rhi_i] and every column j in one run of rows [clo_j, chi_j],
 //      which are kept in LDS;
 //   3. threads over (row, dimension) form grad_x[i][p] = g * sum_{j in run}
