@@ -89,6 +89,16 @@ __device__ __forceinline__ float abandon_threshold(float bsf, float gamma) {
 // One round of the diagonal mapping: E step on anti-diagonal 2r with the
 // candidate point cin, O step on 2r+1 with the candidate point loaded into
 // cout (which the next round uses as its cin).
+// Smallest of (diag, up, left) and its 2-bit code (0 diagonal, 1 up, 2 left;
+// ties go to the earlier of that order).  The minimum comes from one 3-way
+// min, so the DP recurrence does not wait on the comparisons that form the code.
+template <typename T>
+__device__ __forceinline__ T min3_code(T diag, T up, T left, uint32_t& code) {
+    const T best = vmin3(diag, up, left);
+    code = best == diag ? 0u : (best == up ? 1u : 2u);
+    return best;
+}
+
 template <typename T, int NCH, bool SAVE, bool WODD>
 __device__ __forceinline__ void diag_round(const int (&qk)[NCH], const int (&ck)[NCH],
                                            int off, const float4 (&cin)[NCH], float4 (&cout)[NCH],
@@ -107,10 +117,8 @@ __device__ __forceinline__ void diag_round(const int (&qk)[NCH], const int (&ck)
         const T left = wave_shr1(INF, vO);
         T best;
         if (SAVE) {
-            uint32_t code = 0;
-            best = vE;
-            if (up < best) { best = up; code = 1; }
-            if (left < best) { best = left; code = 2; }
+            uint32_t code;
+            best = min3_code(vE, up, left, code);
             cw |= code << shift;
         } else {
             best = vmin3(vE, up, left);
@@ -125,10 +133,8 @@ __device__ __forceinline__ void diag_round(const int (&qk)[NCH], const int (&ck)
         const T left = vE;
         T best;
         if (SAVE) {
-            uint32_t code = 0;
-            best = vO;
-            if (up < best) { best = up; code = 1; }
-            if (left < best) { best = left; code = 2; }
+            uint32_t code;
+            best = min3_code(vO, up, left, code);
             cw |= code << (shift + 2);
         } else {
             best = vmin3(vO, up, left);
@@ -384,10 +390,8 @@ __device__ __forceinline__ void rows_steps(int ring, const T* rowbuf, T* rowbuf_
         const T cost = point_cost<NCH>(B.qv, cv, T(0));
         T best;
         if (SAVE) {
-            uint32_t code = 0;
-            best = diag;
-            if (up < best) { best = up; code = 1; }
-            if (left < best) { best = left; code = 2; }
+            uint32_t code;
+            best = min3_code(diag, up, left, code);
             B.cw |= code << ((t & 15) * 2);
             if ((t & 15) == 15 || t == B.T_end - 1) {
                 B.cp[(int64_t)(t >> 4) * kWave] = B.cw;
