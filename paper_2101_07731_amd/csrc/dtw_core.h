@@ -393,10 +393,6 @@ __device__ __forceinline__ void rows_steps(int ring, const T* rowbuf, T* rowbuf_
             uint32_t code;
             best = min3_code(diag, up, left, code);
             B.cw |= code << ((t & 15) * 2);
-            if ((t & 15) == 15 || t == B.T_end - 1) {
-                B.cp[(int64_t)(t >> 4) * kWave] = B.cw;
-                B.cw = 0;
-            }
         } else {
             best = vmin3(diag, up, left);
         }
@@ -404,6 +400,14 @@ __device__ __forceinline__ void rows_steps(int ring, const T* rowbuf, T* rowbuf_
         v = ((unsigned)(t + B.k0) <= W2) ? v : INF;
         B.cur = v;
         return v;
+    };
+    // A code word (16 steps) is stored once its last step is done, or at the
+    // block's last step.  ta is a multiple of 16 (the callers step by 64), so
+    // no word ends inside an unrolled group of U steps (U divides 16) and the
+    // group's steps run without a branch between them.
+    auto store_word = [&](int t_last) __attribute__((always_inline)) {
+        B.cp[(int64_t)(t_last >> 4) * kWave] = B.cw;
+        B.cw = 0;
     };
     int t = ta;
     for (; t + U <= tb; t += U) {
@@ -423,6 +427,7 @@ __device__ __forceinline__ void rows_steps(int ring, const T* rowbuf, T* rowbuf_
 #pragma unroll
             for (int u = 0; u < U; ++u) rowbuf_w[B.wb + t + u] = out[u];
         }
+        if (SAVE && (((t + U) & 15) == 0 || t + U == B.T_end)) store_word(t + U - 1);
     }
     for (; t < tb; ++t) {
         const int sb = ring + ((B.cs0 + t) & (kRowRing - 1));
@@ -431,6 +436,7 @@ __device__ __forceinline__ void rows_steps(int ring, const T* rowbuf, T* rowbuf_
         for (int k = 0; k < NCH; ++k) cv[k] = lds4[sb + k * kRowStride];
         const T v = step(t, cv, rowbuf[B.rb + t]);
         if (lane == kRowBlock - 1) rowbuf_w[B.wb + t] = v;
+        if (SAVE && ((t & 15) == 15 || t == B.T_end - 1)) store_word(t);
     }
 }
 
