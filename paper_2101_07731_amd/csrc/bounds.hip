@@ -362,6 +362,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         }
         float acc = 0.0f;
         int since = 0;       // rows since the last exact row (exact rows: i = 0 and i mod P = 0)
+        int exr = 0;         // staged query point of the next exact row (qex[i / P])
         // the row's query step and top distance, read one row ahead
         float di_next = dqs[0];
         float top_next = TOP ? top[0] : INF;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     const int jc = min(max(jrow[s], 0), n - 1);
-                    const float4* qrow = qex + (P > 0 ? i / P : 0) * NCH;
+                    const float4* qrow = qex + exr * NCH;
                     const float4* crow = cst + jc * NCH;
                     float sacc = 0.0f;
 #pragma unroll
@@ -416,6 +417,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                     }
                     L[s] = U[s] = __builtin_sqrtf(sacc);
                 }
+                ++exr;
             } else {
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
