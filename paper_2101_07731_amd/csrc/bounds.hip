@@ -277,9 +277,10 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     // LDS, staged per pair so that the row loop never waits on global memory:
     float4* cst = lds4;                                // [n][NCH] candidate points
     float4* qex = cst + (int64_t)n * NCH;              // [exact rows][NCH] query points of the exact rows
-    float* top = reinterpret_cast<float*>(qex + (int64_t)ti_exact_rows(m, P) * NCH);   // [m] (TOP)
-    float* dqs = top + m;                              // [m] query steps
-    float* gcs = dqs + m;                              // [n] candidate steps
+    // [m + 1] (query step, TOP distance) of each row, read as one 8-byte pair per row;
+    // entry m is padding, read once past the last row
+    float2* tdq = reinterpret_cast<float2*>(qex + (int64_t)ti_exact_rows(m, P) * NCH);
+    float* gcs = reinterpret_cast<float*>(tdq + m + 1);   // [n] candidate steps
     const int KB = 2 * W + 1;                          // band offsets 0 .. 2W
     const float INF = __builtin_inff();
     const double u = 1.0 / 16777216.0;
@@ -309,7 +310,19 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         // points as whole 16-byte chunks when D is a multiple of 4 and both series are aligned
         const bool vec = (D & 3) == 0 && ((reinterpret_cast<uintptr_t>(qs) | reinterpret_cast<uintptr_t>(cs)) & 15) == 0;
         __syncthreads();
-        copy_to_lds(dqs, a.qstep + (int64_t)q * m, m, lane, kWave);
+        {
+            const float* qsp = a.qstep + (int64_t)q * m;
+            int i = lane;
+            for (; i + 3 * kWave < m; i += 4 * kWave) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = qsp[i + u * kWave];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) tdq[i + u * kWave].x = v[u];
+            }
+            for (; i < m; i += kWave) tdq[i].x = qsp[i];
+            if (lane == 0) tdq[m] = make_float2(0.0f, INF);
+        }
         copy_to_lds(gcs, a.gamma + (int64_t)ref * n, n, lane, kWave);
         stage_point_chunks<NCH>(cst, cs, n, 1, D, vec, lane);
         // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
@@ -346,7 +359,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                         }
                         d = __builtin_sqrtf(s);
                     }
-                    top[i] = d;
+                    tdq[i].y = d;
                 }
             }
         }
@@ -364,16 +377,20 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
         int since = 0;       // rows since the last exact row (exact rows: i = 0 and i mod P = 0)
         int exr = 0;         // staged query point of the next exact row (qex[i / P])
         // the row's query step and top distance, read one row ahead
-        float di_next = dqs[0];
-        float top_next = TOP ? top[0] : INF;
+        float di_next, top_next;
+        {
+            const float2 t0 = tdq[0];
+            di_next = t0.x;
+            top_next = TOP ? t0.y : INF;
+        }
         for (int i = 0; i < m; ++i) {
             const bool exact_row = (i == 0) || (P > 0 && since == 0);
             const float di = di_next;
             const float topv = top_next;
             {
-                const int in = i + 1 < m ? i + 1 : i;
-                di_next = dqs[in];
-                if (TOP) top_next = top[in];
+                const float2 t1 = tdq[i + 1];
+                di_next = t1.x;
+                if (TOP) top_next = t1.y;
             }
             // row i-1 values of the same column (offset k+1)
             float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
@@ -559,7 +576,7 @@ hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
 
 size_t ti_lds_bytes(int m, int n, int D, int P) {
     const size_t nch = (size_t)nch_pad(D);
-    return ((size_t)n * nch + (size_t)ti_exact_rows(m, P) * nch) * 16 + ((size_t)2 * m + n) * 4 + 16;
+    return ((size_t)n * nch + (size_t)ti_exact_rows(m, P) * nch) * 16 + (size_t)(m + 1) * 8 + (size_t)n * 4 + 16;
 }
 
 template <int SLOTS, int NCH>
