@@ -410,9 +410,10 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 cmn[SLOTS - 1] = wave_shl1(INF, cm[SLOTS - 1]);
             }
             // the column at offset 0 of row i-1 is not in row i's band: its minimum is final
-            // (lane 0 holds it and keeps the sum; no scalar round trip)
-            const float leaving = cm[0];
-            acc += (lane == 0 && i > 0 && leaving < INF) ? leaving * leaving : 0.0f;
+            // (lane 0 holds it and keeps the sum, no scalar round trip; the other lanes' sums
+            // are never read, and +inf, also before the first row, means no cell)
+            const float leaving = cm[0] < INF ? cm[0] : 0.0f;
+            acc = __builtin_fmaf(leaving, leaving, acc);
             // Lanes that are not cells (columns outside [0, n), offsets past 2W) carry values
             // that only ever reach other non-cells (the cell below keeps the column), so every
             // lane evaluates the same arithmetic and only the column minimum is masked.
