@@ -199,12 +199,17 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
                 for (int p = 0; p < DMAX; ++p) cv[p] = p < D ? c[(int64_t)j * D + p] : 0.0f;
                 float best = __builtin_inff();
                 for (int b = 0; b < nb; ++b) {
-                    const float* bb = bg + b * D * 2;
+                    // the box's (lo, hi) pairs, all loads issued before any use (dimensions
+                    // past D re-read dimension 0 and are skipped below)
+                    const float2* bb = reinterpret_cast<const float2*>(bg + b * D * 2);
+                    float2 lh[DMAX];
+#pragma unroll
+                    for (int p = 0; p < DMAX; ++p) lh[p] = bb[p < D ? p : 0];
                     float s = 0.0f;
 #pragma unroll
                     for (int p = 0; p < DMAX; ++p) {
                         if (p < D) {
-                            const float t = __builtin_fmaxf(__builtin_fmaxf(bb[2 * p] - cv[p], cv[p] - bb[2 * p + 1]), 0.0f);
+                            const float t = __builtin_fmaxf(__builtin_fmaxf(lh[p].x - cv[p], cv[p] - lh[p].y), 0.0f);
                             s = __builtin_fmaf(t, t, s);
                         }
                     }
