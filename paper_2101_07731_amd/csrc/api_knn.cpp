@@ -775,6 +775,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         f.indep = K.indep ? 1 : 0;
         f.nn_idx = nn_idx; f.nn_dist = nn_dist;
         f.stats = d.stats;
+        f.key = d.key;
         if ((e = launch_knn_finalize(f, s)) != hipSuccess) return hip_fail(e, "finalize");
     }
     mark(7);

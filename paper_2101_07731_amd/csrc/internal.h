@@ -194,7 +194,8 @@ struct KnnFinalArgs {
     const int32_t* pruned_pc;  // [nq] or null
     const int32_t* pruned_ti;  // [nq] or null
     int32_t nc;
-    double ratio;              // finalists: float32 DTW <= k-th smallest * ratio
+    double ratio;              // finalists: float32 DTW <= (bound of the k-th smallest) * ratio
+    const unsigned long long* key;   // [nq] threshold keys after the DTW stage (k-th best key)
     int32_t k;                 // neighbours per query; nn_idx / nn_dist are [nq][k]
     int32_t indep;             // 1: independent DTW
     int32_t* nn_idx;

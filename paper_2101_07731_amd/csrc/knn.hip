@@ -734,35 +734,12 @@ template <int NCH, bool WODD, bool ROWS>
 __global__ __launch_bounds__(64) void k_knn_finalize(KnnFinalArgs a) {
     const int q = blockIdx.x, lane = threadIdx.x;
     const int ns = a.R, nl = a.cnt[q], K = a.k;
-    // the k-th smallest float32 value over the seeds and the list: K rounds,
-    // each taking the smallest (value, slot) after the previous one
-    float kth = __builtin_inff();
-    {
-        float pv = -__builtin_inff();
-        int ps = -1, found = 0;
-        for (int t = 0; t < K; ++t) {
-            float bv = __builtin_inff();
-            int bs = 0x7fffffff;
-            for (int x = lane; x < ns + nl; x += kWave) {
-                const bool ok = x < ns ? a.seeds[(int64_t)q * ns + x] >= 0 : true;
-                const float v = x < ns ? a.seed_dist[(int64_t)q * ns + x] : a.list_dist[(int64_t)q * a.cap + x - ns];
-                if (ok && v < __builtin_inff() && (v > pv || (v == pv && x > ps)) && (v < bv || (v == bv && x < bs))) {
-                    bv = v;
-                    bs = x;
-                }
-            }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const float ov = __shfl_xor(bv, o);
-                const int os = __shfl_xor(bs, o);
-                if (ov < bv || (ov == bv && os < bs)) { bv = ov; bs = os; }
-            }
-            if (bs == 0x7fffffff) break;
-            pv = bv; ps = bs;
-            ++found;
-        }
-        if (found == K) kth = pv;
-    }
+    // An upper bound of the k-th smallest float32 value over the seeds and the
+    // list: the query's threshold key, the largest of its k best keys (k = 1:
+    // the best), each v / (1 - gamma) rounded up for a completed DTW's float32
+    // value v.  A bound above the k-th value only adds finalists.
+    (void)K;
+    const float kth = bsf_from_key(a.key[(int64_t)q * kKeyStride]);
     const double thr = (double)kth * a.ratio;
     // the k best (float64 value, index) so far, ascending; kept by lane 0
     __shared__ double tk_v[kMaxK];
