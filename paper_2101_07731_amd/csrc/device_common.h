@@ -94,6 +94,13 @@ __device__ __forceinline__ int wave_next_item(int* counter) {
     return __builtin_amdgcn_readlane(v, 0);
 }
 
+// A 64-bit value read from lane 0 into scalar registers.
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // A condition made wave-uniform from lane 0's value (for conditions that are
 // equal in every lane but computed from vector registers).
 __device__ __forceinline__ bool wave_uniform(bool c) { return __builtin_amdgcn_readlane((int)c, 0) != 0; }

@@ -386,14 +386,21 @@ __device__ __forceinline__ void topk_insert_wave(unsigned long long* slots, int 
             if (ov > v || (ov == v && oa < at)) { v = ov; at = oa; }
         }
     };
+    // Every value that decides an exit is read from lane 0 into scalar
+    // registers, so both exits are uniform branches (a loop exit on a
+    // shuffled vector value may be compiled as divergent, leaving lanes
+    // 1..63 spinning on the result of a parked lane 0).
+    x = readlane_u64(x);
     for (;;) {
         unsigned long long mx;
         int mi;
         wave_max(mx, mi);
+        mx = readlane_u64(mx);
+        mi = __builtin_amdgcn_readlane(mi, 0);
         if (x >= mx) return;
         unsigned long long old = 0;
         if (lane == 0) old = atomicCAS(slots + mi, mx, x);
-        if (__shfl(old, 0) == mx) break;
+        if (readlane_u64(old) == mx) break;
     }
     unsigned long long m2;
     int at;
