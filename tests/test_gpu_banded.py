@@ -178,3 +178,65 @@ def test_dtw_loss_autograd(dev):
         v, rq, rc, _ = O.path_grad(x[b], y[b], 4, 1.0)
         np.testing.assert_allclose(X.grad[b].cpu().numpy(), rq, rtol=1e-6, atol=1e-5)
         np.testing.assert_allclose(Y.grad[b].cpu().numpy(), rc, rtol=1e-6, atol=1e-5)
+
+
+def _f32_backward_check(dev, x, y, frac, label):
+    """The product path (float32 forward recording the argmin codes, then the
+    adjoint) on every pair, each gradient element against the oracle's
+    float64 path gradient.  A float32 forward can leave the float64 path
+    only where two predecessors tie within float32 rounding; such a pair is
+    reported, and its gradient must still be the gradient of a path whose
+    cost equals the float64 DTW within the float32 error bound (Euler's
+    identity for the degree-2 homogeneous path cost, and translation
+    invariance).  Returns the pairs that left the oracle's path."""
+    from paper_2101_07731_amd.pairs import DTWLoss
+    B, m, D = x.shape
+    n = y.shape[1]
+    rng = np.random.default_rng(17)
+    g = rng.uniform(0.5, 2.0, size=B).astype(np.float32)
+    X = torch.from_numpy(x).to(dev).requires_grad_(True)
+    Y = torch.from_numpy(y).to(dev).requires_grad_(True)
+    dist = DTWLoss.apply(X, Y, None, frac, False)
+    (dist * torch.from_numpy(g).to(dev)).sum().backward()
+    gx, gy = X.grad.cpu().numpy().astype(np.float64), Y.grad.cpu().numpy().astype(np.float64)
+    dist = dist.detach().cpu().numpy()
+    weff = O.window_eff(m, n, 0, *frac)
+    u = 2.0 ** -24
+    gam = (m + n + D + 2) * u * 1.01
+    off = []
+    for b in range(B):
+        v, rq, rc, _ = O.path_grad(x[b], y[b], weff, float(g[b]))
+        assert abs(float(dist[b]) - v) <= gam * v + 1e-30, (b, dist[b], v)
+        scale = max(1.0, np.abs(rq).max(), np.abs(rc).max())
+        # each element is g * sum of at most (m + n - 1) terms 2 (x_i - y_j): float32 rounding only
+        tol = 4 * (m + n) * u * scale
+        if np.abs(gx[b] - rq).max() <= tol and np.abs(gy[b] - rc).max() <= tol:
+            continue
+        off.append(b)
+        xs, ys = x[b].astype(np.float64), y[b].astype(np.float64)
+        np.testing.assert_allclose(gx[b].sum(0) + gy[b].sum(0), 0.0, atol=tol)
+        ex, ey = (xs * gx[b]).sum(), (ys * gy[b]).sum()
+        path_cost = (ex + ey) / (2.0 * float(g[b]))
+        assert abs(path_cost - v) <= 4 * gam * v + 1e-4 * (abs(ex) + abs(ey)) / float(g[b]), (b, path_cost, v)
+    say(label, "pairs off the float64 path:", off)
+    return off
+
+
+def test_backward_f32_forward_loss_workload(dev):
+    """DTW as a loss at full size (256 pairs, length 512, d = 12, W = 51,
+    random walks plus N(0, 1e-6) jitter): the float32 forward's path
+    gradient, every element of every pair, against the oracle."""
+    from paper_2101_07731_amd import synth
+    x, y = synth.loss_pairs()
+    off = _f32_backward_check(dev, x, y, (1, 10), "loss workload")
+    assert len(off) <= 3, off
+
+
+def test_backward_f32_forward_fd_set(dev):
+    """The finite-difference set (8 pairs, length 32, d = 12, W = 3) through
+    the float32 forward: every element against the oracle's path gradient
+    (pinned on the CPU against float64 central differences)."""
+    from paper_2101_07731_amd import synth
+    x, y = synth.loss_pairs(npairs=8, T=32, D=12, seed=5)
+    off = _f32_backward_check(dev, x, y, (1, 10), "fd set")
+    assert off == []

@@ -88,19 +88,24 @@ def test_ragged_lb_mv_sound_and_tight(dev, D):
             assert lb[qi, ci] >= ref * (1 - slack) - 1e-30, (qi, ci, lb[qi, ci], ref)
 
 
-def test_bank_workload_sampled(dev):
-    """Two of the five banks of the uneven 1-NN workload (4096 references of
-    lengths U[64, 2048], d = 4 and d = 32) with their queries; one sampled
-    query per bank against the oracle."""
-    from paper_2101_07731_amd import search, synth
-    banks, queries = synth.ragged_banks()
-    for D in (4, 32):
-        Cs = banks[D]
-        Q = [q for d, q in queries if d == D]
-        say("bank", D, len(Q), len(Cs))
-        idx, dist, st, _ = run(dev, Q, Cs)
-        assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
-        k = int(np.argmin([q.shape[0] for q in Q]))          # the shortest query keeps the oracle quick
-        ri, rd = O.knn_exhaustive([Q[k]], Cs, num=1, den=10)
-        assert idx[k] == ri[0]
-        assert dist[k] == np.float32(rd[0])
+@pytest.fixture(scope="module")
+def bank_workload():
+    from paper_2101_07731_amd import synth
+    return synth.ragged_banks()
+
+
+@pytest.mark.parametrize("D", [2, 4, 8, 16, 32])
+def test_bank_workload_sampled(dev, bank_workload, D):
+    """Each of the five banks of the uneven 1-NN workload (4096 references of
+    lengths U[64, 2048], d = 2, 4, 8, 16, 32) with its queries; the bank's
+    shortest query against the oracle's exhaustive search."""
+    banks, queries = bank_workload
+    Cs = banks[D]
+    Q = [q for d, q in queries if d == D]
+    say("bank", D, len(Q), len(Cs))
+    idx, dist, st, _ = run(dev, Q, Cs)
+    assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
+    k = int(np.argmin([q.shape[0] for q in Q]))          # the shortest query keeps the oracle quick
+    ri, rd = O.knn_exhaustive([Q[k]], Cs, num=1, den=10, threads=16)
+    assert idx[k] == ri[0]
+    assert dist[k] == np.float32(rd[0])

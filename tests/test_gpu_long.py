@@ -1,0 +1,133 @@
+"""The long-series workload (200 queries x 2000 references, length 1024,
+d = 16, window 10%: W = 102) on the GPU against the FP64 oracle, with the
+point-clustering bound LB_PC (Sec. 5) at K = 4 and K = 16 boxes per
+expanded window and Lv = 2 and 3 quantisation levels.
+
+* Boxes: k_pc_boxes' cells, box counts and box bounds equal the oracle's
+  orc_pc_boxes bit for bit (the float32 cell assignment is the contract).
+* Dense LB_PC: never above the oracle's float64 bound, and within the
+  documented float32 deflation of it.
+* Search: mv+pc (and mv+pc+ti) 1-NN equal to the oracle's exhaustive
+  search on sampled queries.
+"""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+T_LONG, D_LONG = 1024, 16
+PC_SETS = [(2, 4), (3, 4), (2, 16), (3, 16)]     # (Lv, K)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2101_07731_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def long_data():
+    from paper_2101_07731_amd import synth
+    return synth.long_knn()
+
+
+def _pc_floor(Cs):
+    """The smallest cell length the library derives from an index: 1e-5 of the
+    float32 value range, computed as float32(1e-5 * float64(max - min))."""
+    rng = np.float32(Cs.max()) - np.float32(Cs.min())
+    return float(np.float32(1e-5 * np.float64(rng)))
+
+
+def _pool_map(fn, items):
+    # the oracle's C calls release the GIL
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(fn, items))
+
+
+@pytest.mark.parametrize("Lv,K", PC_SETS, ids=["L%d_K%d" % s for s in PC_SETS])
+def test_pc_boxes_bitwise_long(dev, long_data, Lv, K):
+    """Cell keys, box counts and tight box bounds of k_pc_boxes against the
+    oracle, bit for bit, for 6 queries of the long workload (171 groups of
+    up to 210 points each).  The kernel is reached through the
+    candidate-side box builder run on an index of the queries, which boxes
+    each indexed series' points over groups of the other series' positions
+    (the same kernel the per-query boxes of a search use)."""
+    from paper_2101_07731_amd import search
+    Q, Cs = long_data
+    Qs = Q[[0, 1, 57, 100, 150, 199]]
+    W = O.window_eff(T_LONG, T_LONG, 0, 1, 10)
+    assert W == 102
+    fl = _pc_floor(Cs)
+    ixq = search.Index(torch.from_numpy(np.ascontiguousarray(Qs)).to(dev))
+    cb = search.CandBoxes(ixq, T_LONG, frac=(1, 10), pc_levels=Lv, pc_clusters=K, pc_group=6, pc_min_cell=fl)
+    G = cb.desc.groups
+    assert G == (T_LONG + 5) // 6
+    raw = cb.buf.cpu().numpy()
+    boxes = raw[:len(Qs) * G * K * D_LONG * 2 * 4].view(np.float32).reshape(len(Qs), G, K, D_LONG, 2)
+    nbox = raw[cb.desc.off_nbox:cb.desc.off_nbox + len(Qs) * G * 4].view(np.int32).reshape(len(Qs), G)
+    say("pc boxes long", Lv, K, "groups", G, "mean boxes", nbox.mean())
+    for t, q in enumerate(Qs):
+        lo, hi, nb = O.pc_boxes(q, T_LONG, W, Lv=Lv, K=K, w=6, floor_len=fl)
+        np.testing.assert_array_equal(nbox[t], nb)
+        # the oracle's boxes are float64 minima / maxima of float32 values: exact
+        np.testing.assert_array_equal(boxes[t, :, :, :, 0].astype(np.float64), lo)
+        np.testing.assert_array_equal(boxes[t, :, :, :, 1].astype(np.float64), hi)
+    assert nbox.max() == K          # the merge into box K happens at this shape
+
+
+@pytest.mark.parametrize("Lv,K", PC_SETS, ids=["L%d_K%d" % s for s in PC_SETS])
+def test_lb_pc_dense_long(dev, long_data, Lv, K):
+    """The dense LB_PC matrix of 4 queries against all 2000 references of the
+    long workload, every element against the oracle."""
+    from paper_2101_07731_amd import search
+    Q, Cs = long_data
+    Qs = np.ascontiguousarray(Q[[0, 13, 101, 199]])
+    W = O.window_eff(T_LONG, T_LONG, 0, 1, 10)
+    fl = _pc_floor(Cs)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_pc dense long", Lv, K)
+    lb = search.lower_bounds(ix, torch.from_numpy(Qs).to(dev), kind="pc", frac=(1, 10), pc_levels=Lv,
+                             pc_clusters=K, pc_group=6).cpu().numpy().astype(np.float64)
+    pairs = [(a, b) for a in range(len(Qs)) for b in range(len(Cs))]
+    ref = np.array(_pool_map(lambda ab: O.lb_pc(Qs[ab[0]], Cs[ab[1]], W, Lv=Lv, K=K, w=6, floor_len=fl),
+                             pairs)).reshape(len(Qs), len(Cs))
+    assert np.all(lb <= ref * (1 + 1e-12))
+    slack = 2 * (T_LONG + D_LONG + 5) * 2.0 ** -24 * 1.01 + 1e-7
+    np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
+
+
+@pytest.mark.parametrize("K", [4, 16])
+def test_knn_long_mv_pc_sampled(dev, long_data, K):
+    """The whole long workload searched with LB_MV + LB_PC (every gated pair
+    gets LB_PC: e = 0), sampled queries against the oracle's exhaustive
+    search; the prune counts add up."""
+    from paper_2101_07731_amd import search
+    Q, Cs = long_data
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    say("knn long mv+pc", K)
+    idx, dist, st = search.knn(ix, Qd, stats=True, frac=(1, 10), bounds="mv+pc", pc_clusters=K, trigger_pc=0.0)
+    say("stats", st)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert st["pruned_mv"] + st["pruned_pc"] + st["dtw_started"] == st["pairs"] == 200 * 2000
+    sample = np.array([0, 77, 199])
+    ri, rd = O.knn_exhaustive(Q[sample], Cs, num=1, den=10, threads=16)
+    np.testing.assert_array_equal(idx[sample], ri)
+    np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
+    # LB_MV alone gives the same neighbours
+    i2, d2 = search.knn(ix, Qd, frac=(1, 10), bounds="mv")
+    np.testing.assert_array_equal(i2.cpu().numpy(), idx)
+    np.testing.assert_array_equal(d2.cpu().numpy(), dist)
