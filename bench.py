@@ -34,17 +34,53 @@ WORKLOADS = {
               "plain 1-NN: 64 queries x 256 references, length 64, d=3, random walks, window 10% (W=6)"),
 }
 
-# MI355X VALU rate for the plain (non-packed) fp32 instructions the kernels use: one wave64
-# instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12
-# lane-operations/s.  The published 157.3 TFLOP/s counts packed fp32 (two FMAs per lane per
-# instruction, 2 flops each), which the kernels do not use.
+# MI355X fp32 vector peak: 256 CUs x 2.4 GHz x 256 flops per CU per clock (128 lanes of fused
+# multiply-add per clock, counted as 2 flops each; the rate assumes packed fp32) = 157.3 TFLOP/s.
+# The DTW kernels issue plain (non-packed) fp32 instructions, one wave64 instruction per SIMD
+# every 4 cycles = 39.3e12 lane-operations/s, so a kernel that issues one instruction per
+# slot reaches at most (3d + 3) / (2 (2d + 2)) of the published peak.
+FP32_PEAK_FLOPS = 256 * 2.4e9 * 256
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+# The counter figures of the DTW survivor launch, with the digest of the sources the kernel is
+# built from when they were taken: the traffic is reported only while the sources are unchanged.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "knn_dtw_ring_traffic_1000x10000_d8.md")
+DTW_KERNEL_SOURCES = ("knn.hip", "dtw_core.h", "device_common.h")
 
 
 STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "total")
 
-EXTRAS = ("full_cascade", "cand_boxes", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency", "batched_pairs", "dtw_loss", "long_knn", "ragged_banks",
-          "lb_mv_streaming", "plain_gpu")
+EXTRAS = ("full_cascade", "cand_boxes", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency",
+          "batched_pairs", "dtw_loss", "long_knn", "ragged_banks", "lb_mv_streaming", "plain_gpu", "windows")
+# measured on every run: the batched and forward+backward pair rates of the metric, and the plain
+# (no bounds) method on the same GPU
+DEFAULT_EXTRAS = ("plain_gpu", "windows", "batched_pairs", "dtw_loss")
+
+
+def source_digest(names=DTW_KERNEL_SOURCES):
+    """sha256 (16 hex digits) of the named kernel sources, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2101_07731_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """(bytes per DTW survivor launch, digest) from the committed counter summary, or (None, reason)."""
+    import re
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None, "no counter summary"
+    md = re.search(r"source digest: `([0-9a-f]{16})`", txt)
+    mb = re.search(r"bytes per launch: `([0-9.eE+]+)`", txt)
+    if not md or not mb:
+        return None, "counter summary without digest"
+    if md.group(1) != source_digest():
+        return None, "kernel sources changed since the counters were taken"
+    return float(mb.group(1)), md.group(1)
 
 
 def note(what):
@@ -64,7 +100,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", nargs="*", default=None, choices=EXTRAS, metavar="NAME",
                     help="also time further workloads: all of them with no name, else the named ones "
-                         "(%s)" % ", ".join(EXTRAS))
+                         "(%s); %s always run unless --no-extras" % (", ".join(EXTRAS), ", ".join(DEFAULT_EXTRAS)))
+    ap.add_argument("--no-extras", action="store_true", help="time the search step only")
     return ap.parse_args()
 
 
@@ -277,9 +314,13 @@ def main():
     st = steps[-1]
     dtw_ms = float(np.mean([s["stage_ms"][5] for s in steps]))
     cells = float(np.mean([s["cells"] for s in steps]))
-    alu_ops_per_cell = 2 * D + 2
-    peak_gcells = VALU_LANE_OPS / alu_ops_per_cell / 1e9
+    flops_per_cell = 3 * D + 3
     achieved_gcells = cells / (dtw_ms * 1e-3) / 1e9
+    achieved_tflops = achieved_gcells * 1e9 * flops_per_cell / 1e12
+    peak_tflops = FP32_PEAK_FLOPS / 1e12
+    traffic, traffic_src = measured_traffic()
+    if not (args.workload == "cascade" and W == 25 and args.bounds == "mv"):
+        traffic, traffic_src = None, "counters taken on the 1000 x 10000, W = 25, LB_MV workload only"
     pruned = 1.0 - st["dtw_started"] / st["pairs"]
 
     out = {
@@ -309,20 +350,43 @@ def main():
         "roofline": {
             "kernel": "k_knn_dtw_ring" if W <= 63 else "k_knn_dtw_rows",
             "bound": "alu",
-            "achieved": round(achieved_gcells, 2),
-            "peak": round(peak_gcells, 2),
-            "unit": "Gcell/s",
-            "frac": round(achieved_gcells / peak_gcells, 4),
-            # bytes per survivor launch from the FETCH_SIZE / WRITE_SIZE passes on this kernel,
-            # calibrated on the index copy kernel (profiles/knn_dtw_ring_traffic_1000x10000_d8.md);
-            # only meaningful for that workload and build of the kernel
-            "traffic": 9.949e9 if (args.workload == "cascade" and W == 25 and args.bounds == "mv") else None,
-            "per_unit": "%d VALU lane-ops per band cell (d subtractions, d fused multiply-adds, "
-                        "a 3-way min, an add)" % alu_ops_per_cell,
+            "achieved": round(achieved_tflops, 3),
+            "peak": round(peak_tflops, 1),
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tflops / peak_tflops, 4),
+            # HBM-side bytes per survivor launch from the FETCH_SIZE / WRITE_SIZE passes, calibrated
+            # on the index copy kernel; null once the kernel's sources differ from the profiled build
+            "traffic": traffic,
+            "traffic_source": traffic_src,
+            "per_unit": "%d flops per band cell (d subtractions, d squares accumulated by fused "
+                        "multiply-add, a 3-way min counted as 2, an add); %.1f G cells/s" %
+                        (flops_per_cell, achieved_gcells),
+            "single_issue_frac": round(achieved_gcells * (2 * D + 2) * 1e9 / VALU_LANE_OPS, 4),
         },
     }
 
-    extras = set() if args.extras is None else set(args.extras or EXTRAS)
+    extras = set() if args.no_extras else set(DEFAULT_EXTRAS)
+    if args.extras is not None:
+        extras |= set(args.extras or EXTRAS)
+    if "windows" in extras:
+        note("windows")
+        # the same workload at windows 5% and 20% (W = 12 and 51), LB_MV, one search call per step
+        wres = {}
+        for fw in ((1, 20), (1, 5)):
+            kww = dict(frac=fw, bounds=args.bounds)
+            wsw = torch.empty(search.knn_workspace_bytes(ix, Qd, **kww), dtype=torch.uint8, device=dev)
+            stw = {}
+
+            def runw(kww=kww, wsw=wsw, stw=stw):
+                stw.update(search.knn(ix, Qd, stats=True, workspace=wsw, **kww)[2])
+
+            msw = _events_ms(runw, 5)
+            Ww = min(T * fw[0] // fw[1], T - 1)
+            wres["W%d" % Ww] = {"queries_per_s": round(nq / (msw * 1e-3), 2), "ms": round(msw, 3),
+                                "pct_dtw_pruned": round(100.0 * (1 - stw["dtw_started"] / stw["pairs"]), 3),
+                                "dtw_gcups": round(stw["cells"] / (stw["stage_ms"][5] * 1e-3) / 1e9, 2),
+                                "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, stw["stage_ms"])}}
+        out["windows"] = wres
     if "full_cascade" in extras:
         note("full_cascade")
         kwf = dict(frac=frac, bounds="mv+pc+ti")
@@ -429,6 +493,8 @@ def main():
             out[name] = fn(dev)
     if "plain_gpu" in extras:
         note("plain_gpu")
+        # the plain method (Sec. 7.2's "default windowed DTW": every DTW computed, no bounds, no
+        # abandoning) on the same GPU: the whole batch in one call, and one call per query
         kwp = dict(frac=frac, bounds="plain")
         search.knn(ix, Qd, **kwp)
         torch.cuda.synchronize()
@@ -436,25 +502,63 @@ def main():
         _, _, sp = search.knn(ix, Qd, stats=True, **kwp)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
+        nper = min(50, nq)
+        wsp = torch.empty(search.knn_workspace_bytes(ix, Qd[:1], **kwp), dtype=torch.uint8, device=dev)
+        search.knn(ix, Qd[:1], workspace=wsp, **kwp)
+        ms_per_query = _events_ms(lambda: [search.knn(ix, Qd[i:i + 1], workspace=wsp, **kwp)
+                                           for i in range(nper)], 1) / nper
         out["plain_gpu"] = {"queries_per_s": round(nq / tp, 2),
                             "dtw_kernel_gcups": round(sp["cells"] / (sp["stage_ms"][5] * 1e-3) / 1e9, 2),
-                            "cascade_speedup": round(tp / (wall / args.steps), 3)}
+                            "cascade_speedup": round(tp / (wall / args.steps), 3),
+                            "one_query_per_call_queries_per_s": round(1e3 / ms_per_query, 2),
+                            "cascade_speedup_vs_one_query_per_call": round(ms_per_query * nq / ms_step, 3)}
 
     if not args.no_cpu:
         note("cpu_baseline")
         import oracle as O
         nsamp = min(args.cpu_queries, nq)
         th = cpu_threads()
+        gi, gd = idx.cpu().numpy(), dist.cpu().numpy()
         t0 = time.perf_counter()
         ri, rd = O.knn_exhaustive(Q[:nsamp], Cs, num=frac[0], den=frac[1], threads=th)
         tc = time.perf_counter() - t0
-        ok = bool(np.array_equal(ri, idx.cpu().numpy()[:nsamp]) and
-                  np.array_equal(rd.astype(np.float32), dist.cpu().numpy()[:nsamp]))
+        ok = bool(np.array_equal(ri, gi[:nsamp]) and np.array_equal(rd.astype(np.float32), gd[:nsamp]))
         out["cpu_baseline"] = {"value": round(nsamp / tc, 3), "unit": "queries/s", "cores": th,
                                "kind": "oracle",
                                "sample": "first %d of %d queries against all %d references, exhaustive "
                                          "FP64 banded DTW (%.1f s)" % (nsamp, nq, nc, tc),
                                "matches_gpu": ok}
+        # the oracle's sequential cascade (the paper's CPU method, Sec. 6 and 7.1: LB_MV, then LB_PC
+        # and LB_TI behind their triggers, DTW with row-wise early abandoning) beside its exhaustive
+        # search, on all the cores used above and on one core: the paper's speedup T(default) / T(X)
+        # and share of skipped DTWs on this data
+        note("cpu_cascade")
+        n1 = min(8, nq)
+        cpu = {"cores_all": th, "sample_all_cores": nsamp, "sample_one_core": n1}
+        t0 = time.perf_counter()
+        O.knn_exhaustive(Q[:n1], Cs, num=frac[0], den=frac[1], threads=1)
+        t_ex1 = time.perf_counter() - t0
+        cpu["exhaustive"] = {"all_cores_queries_per_s": round(nsamp / tc, 3),
+                             "one_core_queries_per_s": round(n1 / t_ex1, 3)}
+        for name, bits in (("LB_MV", 0), ("LB_MV+LB_PC+LB_TI", 6)):
+            rec = {}
+            for label, nqs, thr in (("all_cores", nsamp, th), ("one_core", n1, 1)):
+                t0 = time.perf_counter()
+                ci, cd, cs = O.knn_cascade(Q[:nqs], Cs, num=frac[0], den=frac[1], bounds=bits, threads=thr)
+                tcs = time.perf_counter() - t0
+                if not (np.array_equal(ci, ri[:nqs]) and np.array_equal(cd, rd[:nqs])):
+                    raise AssertionError("the oracle's cascade differs from its exhaustive search")
+                rec[label + "_queries_per_s"] = round(nqs / tcs, 3)
+                if label == "all_cores":
+                    pairs_ = float(cs["pairs"].sum())
+                    rec["pct_dtw_skipped"] = round(100.0 * (1 - cs["dtw_started"].sum() / pairs_), 3)
+                    rec["skipped_by"] = {"mv": int(cs["pruned_mv"].sum()), "pc": int(cs["pruned_pc"].sum()),
+                                         "ti": int(cs["pruned_ti"].sum())}
+                    rec["speedup_vs_exhaustive_all_cores"] = round(tc / tcs, 3)
+                else:
+                    rec["speedup_vs_exhaustive_one_core"] = round(t_ex1 / tcs, 3)
+            cpu[name] = rec
+        out["cpu_cascade"] = cpu
     print(json.dumps(out), flush=True)
 
 
