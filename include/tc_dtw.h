@@ -21,8 +21,9 @@
  *    reachable for unequal lengths m, n.
  *  - All device memory is owned by the caller: inputs, outputs, the index
  *    buffer, the saved-state buffer and the workspace.  The library never
- *    allocates or frees device memory; sizes come from the *_bytes()
- *    queries.  Workspace contents need no initialisation and are
+ *    allocates or frees device memory (its only device memory of its own
+ *    is the static scratch array of tc_dtw_banded_noalloc); sizes come from
+ *    the *_bytes() queries.  Workspace contents need no initialisation and are
  *    meaningless after a call.
  *  - Every call that takes a stream enqueues its work on that stream and
  *    returns without waiting (unless a HOST output such as stats is
@@ -43,7 +44,7 @@
 extern "C" {
 #endif
 
-#define TC_DTW_ABI_VERSION 4
+#define TC_DTW_ABI_VERSION 5
 
 typedef struct ihipStream_t* tc_dtw_stream; /* same type as hipStream_t; NULL = default stream */
 
@@ -135,6 +136,28 @@ tc_dtw_status tc_dtw_backward(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_d
                               const void* saved, const float* grad_dist,
                               float* grad_x, float* grad_y,
                               void* ws, size_t ws_bytes, tc_dtw_stream stream);
+
+/* ------------------------------------------- banded DTW, no allocation ---
+ * tc_dtw_banded_noalloc: tc_dtw_banded for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * results as tc_dtw_banded without ws / ws_bytes: the scratch that
+ * tc_dtw_banded plans into for pairs of uneven shapes (32 class counters
+ * and a 48-byte descriptor per pair, about tc_dtw_banded_workspace_bytes())
+ * lives in a static device array of tc_dtw_noalloc_scratch_bytes() bytes
+ * (8 MiB, about 170 000 pairs), one per GPU, held until the process ends.
+ * The call allocates no device memory and creates no streams or events: the
+ * plan's classes run one after another on `stream` (tc_dtw_banded runs them
+ * concurrently on library streams).  Pair descriptors are copied from host
+ * memory with hipMemcpyAsync.
+ * Concurrency: every call on one GPU uses that GPU's one array; calls that
+ * overlap on a GPU (from other streams or threads) race and must be
+ * serialised by the caller.
+ * Errors: as tc_dtw_banded, and UNSUPPORTED (checked on the host, before
+ * any HIP call) when the batch's plan exceeds the static scratch. */
+size_t tc_dtw_noalloc_scratch_bytes(void);
+tc_dtw_status tc_dtw_banded_noalloc(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_window win,
+                                    uint32_t flags, float* dist, void* saved, tc_dtw_stream stream);
 
 /* ------------------------------------------------- reusable pair plans ---
  * A plan fixes the shapes of a batch of pairs once: lengths, dims, W_eff,

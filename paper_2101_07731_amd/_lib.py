@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcdtw.so")
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
 F64 = 1
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class TcDtwError(RuntimeError):
@@ -96,6 +96,9 @@ _SIGS = {
     "tc_dtw_saved_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
     "tc_dtw_banded": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_uint32, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tc_dtw_noalloc_scratch_bytes": (C.c_size_t, []),
+    "tc_dtw_banded_noalloc": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_uint32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "tc_dtw_backward_workspace_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
     "tc_dtw_backward": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -53,4 +53,14 @@ struct Carve {
     size_t need() const { return (used + 255) & ~(size_t)255; }
 };
 
+// tc_dtw_banded's body: pairs of uneven shapes are planned into `ws` (class
+// counters and pair descriptors) on every call.  With `fork` the plan's
+// classes run concurrently on the library's streams, else all on `s`.
+// `buffer` (may be null), called after the host-side checks with the plan
+// size, may supply the plan buffer in place of ws (or refuse with a status).
+tc_dtw_status banded_direct(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_window win, uint32_t flags,
+                            float* dist, void* saved, void* ws, size_t ws_bytes, bool fork,
+                            tc_dtw_status (*buffer)(size_t need, void* ctx, void** buf, size_t* bytes),
+                            void* ctx, hipStream_t s);
+
 }  // namespace tcdtw

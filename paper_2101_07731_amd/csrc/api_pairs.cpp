@@ -318,20 +318,28 @@ static tc_dtw_status check_plan(const tc_dtw_pairs_plan* p) {
     return TC_DTW_OK;
 }
 
+// With `fork` the classes run concurrently on the library's streams (forked
+// from and joined back into s0); without it every class runs on s0 in turn,
+// and the call creates no streams or events.
 static tc_dtw_status run_fwd(const tc_dtw_pairs_plan* p, const float* x, const float* y, uint32_t flags,
-                             float* dist, void* saved, hipStream_t s0) {
+                             float* dist, void* saved, hipStream_t s0, bool fork = true) {
     const bool f64 = (flags & TC_DTW_F64) != 0;
     char* base = static_cast<char*>(p->buf);
     int32_t* counters = reinterpret_cast<int32_t*>(base);
     hipError_t e = launch_zero_i32(counters, TC_DTW_PLAN_MAX_CLASSES, s0);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
     const size_t lim = lds_limit();
-    RunStreams* rs = run_streams(e);
-    if (!rs) return hip_fail(e, "run streams");
-    std::lock_guard<std::mutex> lk(rs->mu);
-    if ((e = fork_from(rs, s0)) != hipSuccess) return hip_fail(e, "stream fork");
+    RunStreams* rs = nullptr;
+    std::unique_lock<std::mutex> lk;
+    if (fork) {
+        rs = run_streams(e);
+        if (!rs) return hip_fail(e, "run streams");
+        lk = std::unique_lock<std::mutex>(rs->mu);
+        if ((e = fork_from(rs, s0)) != hipSuccess) return hip_fail(e, "stream fork");
+    }
+    auto join = [&]() { return rs ? join_into(rs, s0) : hipSuccess; };
     for (int k = 0; k < p->nclasses; ++k) {
-        hipStream_t s = rs->s[p->cls[k].stream % TC_DTW_RUN_STREAMS];
+        hipStream_t s = rs ? rs->s[p->cls[k].stream % TC_DTW_RUN_STREAMS] : s0;
         const tc_dtw_plan_class& c = p->cls[k];
         DtwFwdArgs a;
         std::memset(&a, 0, sizeof a);
@@ -349,19 +357,19 @@ static tc_dtw_status run_fwd(const tc_dtw_pairs_plan* p, const float* x, const f
         const int K = c.rows ? c.waves_per_pair : 1;
         if (K > 1) {
             const size_t lds = pipe_lds_bytes(c.maxn, c.dim, K, f64);
-            if (lds > lim) { (void)join_into(rs, s0); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair"); }
+            if (lds > lim) { (void)join(); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair"); }
             const int per_cu = std::max(1, std::min(p->waves_per_cu / K, (int)(lim / lds)));
             const int grid = std::max(1, std::min(c.nitems, 256 * per_cu));
             e = launch_dtw_rows_pipe(a, f64, saved != nullptr, K, c.nitems, grid, s);
         } else {
             const size_t lds = fwd_lds_bytes(a, c.rows != 0, f64);
-            if (lds > lim) { (void)join_into(rs, s0); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair"); }
+            if (lds > lim) { (void)join(); return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair"); }
             e = launch_dtw_fwd(a, f64, saved != nullptr, c.rows != 0, c.nitems,
                                persistent_grid(lds, p->waves_per_cu, c.nitems), s);
         }
-        if (e != hipSuccess) { (void)join_into(rs, s0); return hip_fail(e, "dtw forward launch"); }
+        if (e != hipSuccess) { (void)join(); return hip_fail(e, "dtw forward launch"); }
     }
-    if ((e = join_into(rs, s0)) != hipSuccess) return hip_fail(e, "stream join");
+    if ((e = join()) != hipSuccess) return hip_fail(e, "stream join");
     return ok();
 }
 
@@ -421,6 +429,51 @@ static tc_dtw_status plan_in_workspace(const PairsPlan& P, void* ws, size_t ws_b
     return upload(P, off, ws, s);
 }
 
+// The direct call (declared in api_common.h).  `buffer` runs after the
+// host-side checks and before any HIP call of this function.
+tc_dtw_status banded_direct(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_window win, uint32_t flags,
+                            float* dist, void* saved, void* ws, size_t ws_bytes, bool fork,
+                            tc_dtw_status (*buffer)(size_t need, void* ctx, void** buf, size_t* bytes),
+                            void* ctx, hipStream_t s) {
+    PairsPlan P;
+    HostSet X, Y;
+    tc_dtw_status st = make_plan(x, y, win, nullptr, false, P, X, Y);
+    if (st != TC_DTW_OK) return st;
+    if (!dist) return fail(TC_DTW_ERR_INVALID, "null dist pointer");
+    if (flags & ~TC_DTW_F64) return fail(TC_DTW_ERR_INVALID, "unknown flag bits");
+    const size_t need = plan_layout(P, nullptr);
+    if (buffer && (st = buffer(need, ctx, &ws, &ws_bytes)) != TC_DTW_OK) return st;
+    if (need > 0 && (!ws || ws_bytes < need))
+        return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_banded_workspace_bytes()");
+    if ((st = check_device()) != TC_DTW_OK) return st;
+    const bool f64 = (flags & TC_DTW_F64) != 0;
+    if (!P.uniform) {
+        tc_dtw_pairs_plan pl;
+        if ((st = plan_in_workspace(P, ws, ws_bytes, s, pl)) != TC_DTW_OK) return st;
+        return run_fwd(&pl, X.data, Y.data, flags, dist, saved, s, fork);
+    }
+    DtwFwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.x = X.data;
+    a.y = Y.data;
+    a.D = P.D;
+    a.npairs = P.npairs;
+    a.dist = dist;
+    a.codes = static_cast<uint32_t*>(saved);
+    a.uniform = 1;
+    a.m = P.m; a.n = P.n; a.W = P.W;
+    a.P = pairs_per_wave(P);
+    a.wodd = P.W & 1;
+    a.codes_stride = P.codes_stride;
+    if (fwd_lds_bytes(a, P.urows, f64) > lds_limit())
+        return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
+    const int items = P.urows ? P.npairs : (P.npairs + a.P - 1) / a.P;
+    const hipError_t e = launch_dtw_fwd(a, f64, saved != nullptr, P.urows, items, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "dtw forward launch");
+    return ok();
+}
+
+
 }  // namespace tcdtw
 
 using namespace tcdtw;
@@ -446,42 +499,8 @@ size_t tc_dtw_saved_bytes(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_w
 tc_dtw_status tc_dtw_banded(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw_window win,
                             uint32_t flags, float* dist, void* saved,
                             void* ws, size_t ws_bytes, tc_dtw_stream stream) {
-    PairsPlan P;
-    HostSet X, Y;
-    tc_dtw_status st = make_plan(x, y, win, nullptr, false, P, X, Y);
-    if (st != TC_DTW_OK) return st;
-    if (!dist) return fail(TC_DTW_ERR_INVALID, "null dist pointer");
-    if (flags & ~TC_DTW_F64) return fail(TC_DTW_ERR_INVALID, "unknown flag bits");
-    const size_t need = plan_layout(P, nullptr);
-    if (need > 0 && (!ws || ws_bytes < need))
-        return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_banded_workspace_bytes()");
-    if ((st = check_device()) != TC_DTW_OK) return st;
-    const bool f64 = (flags & TC_DTW_F64) != 0;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (!P.uniform) {
-        tc_dtw_pairs_plan pl;
-        if ((st = plan_in_workspace(P, ws, ws_bytes, s, pl)) != TC_DTW_OK) return st;
-        return run_fwd(&pl, X.data, Y.data, flags, dist, saved, s);
-    }
-    DtwFwdArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.x = X.data;
-    a.y = Y.data;
-    a.D = P.D;
-    a.npairs = P.npairs;
-    a.dist = dist;
-    a.codes = static_cast<uint32_t*>(saved);
-    a.uniform = 1;
-    a.m = P.m; a.n = P.n; a.W = P.W;
-    a.P = pairs_per_wave(P);
-    a.wodd = P.W & 1;
-    a.codes_stride = P.codes_stride;
-    if (fwd_lds_bytes(a, P.urows, f64) > lds_limit())
-        return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
-    const int items = P.urows ? P.npairs : (P.npairs + a.P - 1) / a.P;
-    const hipError_t e = launch_dtw_fwd(a, f64, saved != nullptr, P.urows, items, 0, s);
-    if (e != hipSuccess) return hip_fail(e, "dtw forward launch");
-    return ok();
+    return banded_direct(x, y, win, flags, dist, saved, ws, ws_bytes, true, nullptr, nullptr,
+                         reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t tc_dtw_backward_workspace_bytes(const tc_dtw_batch* x, const tc_dtw_batch* y,

@@ -111,6 +111,27 @@ def banded(x, y, window=None, frac=(1, 10), f64=False, save=False):
     return (dist, saved) if save else dist
 
 
+def banded_noalloc(x, y, window=None, frac=(1, 10), f64=False, saved=None, dist=None):
+    """As banded, through tc_dtw_banded_noalloc: the library's static scratch
+    instead of a workspace (the caller passes the outputs; `saved` may be a
+    buffer of tc_dtw_saved_bytes() bytes to record the argmin codes)."""
+    X, Y = SeriesSet(x), SeriesSet(y)
+    win = window_spec(window, frac)
+    dev = X.flat.device
+    if dist is None:
+        dist = torch.empty(X.count, dtype=torch.float32, device=dev)
+    L.check(L.lib().tc_dtw_banded_noalloc(C.byref(X.batch), C.byref(Y.batch), win, L.F64 if f64 else 0,
+                                          C.c_void_p(dist.data_ptr()),
+                                          C.c_void_p(saved.data_ptr()) if saved is not None else None,
+                                          _stream()))
+    return dist
+
+
+def saved_bytes(x, y, window=None, frac=(1, 10)):
+    X, Y = SeriesSet(x), SeriesSet(y)
+    return L.lib().tc_dtw_saved_bytes(C.byref(X.batch), C.byref(Y.batch), window_spec(window, frac))
+
+
 def backward(x, y, saved, grad_dist, window=None, frac=(1, 10)):
     """Gradients (grad_x, grad_y) of sum_b grad_dist[b] * DTW(x[b], y[b]) along the saved paths."""
     X, Y = SeriesSet(x), SeriesSet(y)

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     lib = L.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.tc_dtw_abi_version() == 4
+    assert lib.tc_dtw_abi_version() == 5
 
 
 def _batch(count=2, dim=3, ulen=8, data=0x1000):
@@ -263,3 +263,23 @@ def test_candidate_boxes_validated_on_the_host():
     lib.tc_dtw_knn_params_default(C.byref(q))
     q.pc_cand = C.pointer(d)
     assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q32), C.byref(q)) == 0
+
+
+def test_noalloc_rejects_a_plan_beyond_its_scratch_on_the_host():
+    """tc_dtw_banded_noalloc refuses a batch whose pair plan exceeds its static
+    scratch with UNSUPPORTED before any HIP call (no device here), and its
+    other argument checks are tc_dtw_banded's."""
+    import numpy as np
+    lib = L.lib()
+    cap = lib.tc_dtw_noalloc_scratch_bytes()
+    assert cap == 8 << 20
+    n = cap // 48 + 10
+    lens = np.full(n, 5, dtype=np.int32)
+    lens[::2] = 6
+    b = L.Batch(0x1000, None, lens.ctypes.data_as(C.POINTER(C.c_int32)), n, 2, 0, None)
+    st = lib.tc_dtw_banded_noalloc(C.byref(b), C.byref(b), L.Window(0, 1, 10), 0, C.c_void_p(0x2000), None, None)
+    assert st == L.ERR_UNSUPPORTED
+    assert b"static scratch" in lib.tc_dtw_last_error()
+    x = _batch()
+    st = lib.tc_dtw_banded_noalloc(C.byref(x), C.byref(x), L.Window(2, 0, 0), 0, None, None, None)
+    assert st == L.ERR_INVALID
