@@ -660,9 +660,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     tc_dtw_status st = make_knn_plan(ix, queries, p, K, Qs);
     if (st != TC_DTW_OK) return st;
     if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
-    if (K.ti && 2 * K.W + 1 > 128)
-        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
-    if (K.ti && ti_lds_bytes(K.m, K.n, K.D, p->ti_period) > 163840)
+    if (K.ti && ti_lds_bytes(K.m, K.n, K.D, p->ti_period, K.W) > 163840)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI stages a pair in LDS: series too long");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
@@ -721,9 +719,12 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
             PcArgs a = pc_args(K, d, x, ix, p);
             a.in_list = d.glist; a.in_cnt = d.gcnt; a.in_uniform = 0;
             a.out_lb = x.glb; a.key = d.key;
-            if ((e = launch_list_items(d.gcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+            // query-side boxes: waves over 64 listed candidates of a query; candidate-side: one pair per wave
+            const int per = K.cand ? 1 : kWave;
+            if ((e = launch_list_items(d.gcnt, 0, K.nq, per, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
                 return hip_fail(e, "pc items");
-            if ((e = launch_lb_pc(a, pc_blocks, s)) != hipSuccess) return hip_fail(e, "lb_pc");
+            e = K.cand ? launch_lb_pc(a, pc_blocks, s) : launch_lb_pc_lanes(a, pc_blocks, s);
+            if (e != hipSuccess) return hip_fail(e, "lb_pc");
             r.in_list = d.glist; r.in_cnt = d.gcnt; r.lb_prev = nullptr; r.lb_new = x.glb;
             r.next_list = K.ti ? x.tlist : nullptr; r.next_lb = x.tlb; r.next_cnt = x.tcnt;
             r.next_e2 = e_ti * e_ti;
@@ -741,7 +742,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
             a.in_list = x.tlist; a.out_lb = x.tout; a.lb_in = x.tlb; a.key = d.key;
             if ((e = launch_list_items(x.tcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
                 return hip_fail(e, "ti items");
-            const int ti_blocks = persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period), (int64_t)K.nq * K.cap);
+            const int ti_blocks = persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period, K.W), (int64_t)K.nq * K.cap);
             if ((e = launch_lb_ti(a, ti_blocks, s)) != hipSuccess) return hip_fail(e, "lb_ti");
             RouteArgs r2 = r;
             r2.in_list = x.tlist; r2.in_cnt = x.tcnt; r2.lb_prev = x.tlb; r2.lb_new = x.tout;
@@ -944,9 +945,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
     if (!lb) return fail(TC_DTW_ERR_INVALID, "null lb pointer");
     if (kind != TC_DTW_LB_MV && kind != TC_DTW_LB_PC && kind != TC_DTW_LB_TI)
         return fail(TC_DTW_ERR_INVALID, "kind must be one of TC_DTW_LB_MV, TC_DTW_LB_PC, TC_DTW_LB_TI");
-    if (kind == TC_DTW_LB_TI && 2 * K.W + 1 > 128)
-        return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI supports band half-widths up to 63");
-    if (kind == TC_DTW_LB_TI && ti_lds_bytes(K.m, K.n, K.D, p->ti_period) > 163840)
+    if (kind == TC_DTW_LB_TI && ti_lds_bytes(K.m, K.n, K.D, p->ti_period, K.W) > 163840)
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_TI stages a pair in LDS: series too long");
     if (K.plain) return fail(TC_DTW_ERR_INVALID, "params.bounds must include TC_DTW_LB_MV");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_lower_bounds_workspace_bytes()");
@@ -962,17 +961,19 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         PcArgs a = pc_args(K, d, x, ix, p);
         if (!K.cand && (e = launch_pc_boxes(a, s)) != hipSuccess) return hip_fail(e, "boxes");
         a.in_list = nullptr; a.in_uniform = K.nc; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
-        if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
+        const int per = K.cand ? 1 : kWave;
+        if ((e = launch_list_items(nullptr, K.nc, K.nq, per, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
             return hip_fail(e, "pc items");
-        if ((e = launch_lb_pc(a, persistent_blocks(0, (int64_t)K.nq * K.nc), s)) != hipSuccess)
-            return hip_fail(e, "lb_pc");
+        const int blocks = persistent_blocks(0, (int64_t)K.nq * ((K.nc + per - 1) / per));
+        e = K.cand ? launch_lb_pc(a, blocks, s) : launch_lb_pc_lanes(a, blocks, s);
+        if (e != hipSuccess) return hip_fail(e, "lb_pc");
     } else {
         if ((e = launch_query_steps(d.Q, K.nq, K.m, K.D, x.qstep, s)) != hipSuccess) return hip_fail(e, "query steps");
         TiArgs a = ti_args(K, d, x, ix, p);
         a.in_list = nullptr; a.cap = K.nc; a.out_lb = lb; a.key = nullptr;
         if ((e = launch_list_items(nullptr, K.nc, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
             return hip_fail(e, "ti items");
-        if ((e = launch_lb_ti(a, persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period), (int64_t)K.nq * K.nc), s)) != hipSuccess)
+        if ((e = launch_lb_ti(a, persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period, K.W), (int64_t)K.nq * K.nc), s)) != hipSuccess)
             return hip_fail(e, "lb_ti");
     }
     return ok();

@@ -17,32 +17,11 @@
 //    scaled by 1 - (n + 5) u and rounded down.
 #include <algorithm>
 
-#include "device_common.h"
-#include "internal.h"
+#include "bounds_common.h"
 
 namespace tcdtw {
 
 extern __shared__ float4 lds4[];
-
-__device__ __forceinline__ float rdown(double x) {
-    float f = (float)x;
-    if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);
-    return f;
-}
-
-__device__ __forceinline__ uint32_t okey(float f) {
-    const uint32_t b = __float_as_uint(f);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float okey_to_float(uint32_t k) {
-    const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
-    return __uint_as_float(b);
-}
-
-__device__ __forceinline__ float key_bsf(const unsigned long long* key) {
-    const unsigned long long k = __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __uint_as_float((uint32_t)(k >> 32));
-}
 
 // --------------------------------------------------------- query steps
 // delta[q][i] = e(q_{i-1}, q_i) (delta[q][0] = 0), the query-side distances
@@ -231,15 +210,103 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
 }
 
 // ------------------------------------------------------------------- K6
-// Chunk k (components 4k .. 4k+3, zero past D) of the point at pt; vec: one
-// 16-byte load (D a multiple of 4, pt 16-byte aligned).  Chunks at or past D
-// (the chunk count is padded up to an instantiated width) read nothing.
-__device__ __forceinline__ float4 point_chunk(const float* __restrict__ pt, int k, int D, bool vec) {
-    if (vec) return 4 * k < D ? *reinterpret_cast<const float4*>(pt + 4 * k) : make_float4(0.f, 0.f, 0.f, 0.f);
-    float v[4];
+// LB_PC with the query's boxes (Sec. 5), lanes over candidates: a wave takes
+// up to 64 listed candidates of one query, so the query's boxes of a group
+// are the same for every lane; they are read through the scalar cache into
+// scalar registers (through a constant-address-space pointer: the boxes are
+// never written while the kernel runs, and uniform loads from that address
+// space are scalar loads), and
+// each lane walks its own candidate's points in order.  Per (point, box,
+// dimension): two subtractions with a scalar operand, a 3-way max with 0 and
+// an FMA; per box a minimum.  EXACT: D == 4 NCH (whole 16-byte chunks, no
+// per-dimension test).
+
+// Squared distance of a point (NCH chunks) to the box at bb ([D][2] lo, hi).
+template <int NCH, bool EXACT>
+__device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const float4 (&c)[NCH]) {
+    float s = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = 4 * k + c < D ? pt[4 * k + c] : 0.0f;
-    return make_float4(v[0], v[1], v[2], v[3]);
+    for (int k = 0; k < NCH; ++k) {
+        const float cv[4] = {c[k].x, c[k].y, c[k].z, c[k].w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int p = 4 * k + t;
+            if (EXACT || p < D) {
+                const float v = __builtin_fmaxf(__builtin_fmaxf(bb[2 * p] - cv[t], cv[t] - bb[2 * p + 1]), 0.0f);
+                s = __builtin_fmaf(v, v, s);
+            }
+        }
+    }
+    return s;
+}
+
+template <int NCH, bool EXACT>
+__global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
+    const int lane = threadIdx.x;
+    const int D = a.D, n = a.n, K = a.K, w = a.w, G = a.ngroups;
+    const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
+    const bool vec = EXACT && (reinterpret_cast<uintptr_t>(a.C) & 15) == 0;
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.prefix[a.nq]) break;
+        const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
+        const int e = (item - __builtin_amdgcn_readfirstlane(a.prefix[q])) * kWave + lane;
+        const int cnt = a.in_list ? a.in_cnt[q] : a.in_uniform;
+        bool live = e < cnt;
+        const int ref = live ? (a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e) : 0;
+        double stop = __builtin_inf();
+        if (a.key) {
+            const float bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
+            // selective deployment: only pairs with LB_MV > e^2 bsf
+            if (live && !((double)a.lb_mv[(int64_t)q * a.nc + ref] > a.e2 * (double)bsf)) {
+                a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
+                live = false;
+            }
+            stop = (double)bsf / a.keep;
+        }
+        if (__ballot(live) == 0) continue;
+        const float* cs = a.C + (int64_t)ref * n * D;
+        const float* bq = a.boxes + (int64_t)q * G * K * D * 2;
+        const int32_t* nbq = a.nbox + (int64_t)q * G;
+        float acc = 0.0f;
+        for (int g = 0; g < G; ++g) {
+            const int nb = __builtin_amdgcn_readfirstlane(nbq[g]);
+            const float* bg = bq + (int64_t)g * K * D * 2;
+            const int j1 = min(n, (g + 1) * w);
+            const const_as_float* bc = (const const_as_float*)bg;
+            // two points against two boxes per step: four independent chains, and each box's
+            // scalar load serves two points
+            for (int j = g * w; j < j1; j += 2) {
+                const bool two = j + 1 < j1;
+                float4 c0[NCH], c1[NCH];
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) {
+                    c0[k] = point_chunk(cs + (int64_t)j * D, k, D, vec);
+                    c1[k] = point_chunk(cs + (int64_t)(two ? j + 1 : j) * D, k, D, vec);
+                }
+                float m0 = __builtin_inff(), m1 = __builtin_inff();
+                int b = 0;
+                for (; b + 1 < nb; b += 2) {
+                    const const_as_float* b0 = bc + b * D * 2;
+                    const const_as_float* b1 = b0 + D * 2;
+                    m0 = __builtin_fminf(m0, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c0), box_dist<NCH, EXACT>(b1, D, c0)));
+                    m1 = __builtin_fminf(m1, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c1), box_dist<NCH, EXACT>(b1, D, c1)));
+                }
+                if (b < nb) {
+                    const const_as_float* b0 = bc + b * D * 2;
+                    m0 = __builtin_fminf(m0, box_dist<NCH, EXACT>(b0, D, c0));
+                    m1 = __builtin_fminf(m1, box_dist<NCH, EXACT>(b0, D, c1));
+                }
+                acc += m0;
+                if (two) acc += m1;
+            }
+            // the partial sum is already a bound: stop once it proves every live pair prunable
+            if (a.key && (g & 7) == 7 && g + 1 < G &&
+                __ballot(live && !((double)acc * defl > stop)) == 0)
+                break;
+        }
+        if (live) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
+    }
 }
 
 // dst[r * NCH + k] = chunk k of point r * rstride of the series at src, for
@@ -571,6 +638,27 @@ hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NCH>
+static void launch_lb_pc_lanes_nch(const PcArgs& a, int nblocks, hipStream_t s) {
+    if (a.D == 4 * NCH) hipLaunchKernelGGL((k_lb_pc_lanes<NCH, true>), dim3(nblocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_lb_pc_lanes<NCH, false>), dim3(nblocks), dim3(64), 0, s, a);
+}
+
+hipError_t launch_lb_pc_lanes(const PcArgs& a, int nblocks, hipStream_t s) {
+    switch (nch_pad(a.D)) {
+        case 1: launch_lb_pc_lanes_nch<1>(a, nblocks, s); break;
+        case 2: launch_lb_pc_lanes_nch<2>(a, nblocks, s); break;
+        case 3: launch_lb_pc_lanes_nch<3>(a, nblocks, s); break;
+        case 4: launch_lb_pc_lanes_nch<4>(a, nblocks, s); break;
+        case 6: launch_lb_pc_lanes_nch<6>(a, nblocks, s); break;
+        case 8: launch_lb_pc_lanes_nch<8>(a, nblocks, s); break;
+        case 12: launch_lb_pc_lanes_nch<12>(a, nblocks, s); break;
+        case 16: launch_lb_pc_lanes_nch<16>(a, nblocks, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
     if (a.D <= 4) hipLaunchKernelGGL(k_lb_pc<4>, dim3(nblocks), dim3(64), 0, s, a);
     else if (a.D <= 8) hipLaunchKernelGGL(k_lb_pc<8>, dim3(nblocks), dim3(64), 0, s, a);
@@ -580,7 +668,8 @@ hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t ti_lds_bytes(int m, int n, int D, int P) {
+size_t ti_lds_bytes(int m, int n, int D, int P, int W) {
+    if (2 * W + 1 > 2 * kWave) return ti_cols_lds_bytes(m);
     const size_t nch = (size_t)nch_pad(D);
     return ((size_t)n * nch + (size_t)ti_exact_rows(m, P) * nch) * 16 + (size_t)(m + 1) * 8 + (size_t)n * 4 + 16;
 }
@@ -608,7 +697,9 @@ static hipError_t launch_lb_ti_slots(const TiArgs& a, int nblocks, size_t lds, h
 }
 
 hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s) {
-    const size_t lds = ti_lds_bytes(a.m, a.n, a.D, a.P);
+    // bands of up to 128 offsets: one or two offsets per lane; wider: the column mapping
+    if (2 * a.W + 1 > 2 * kWave) return launch_lb_ti_cols(a, nblocks, s);
+    const size_t lds = ti_lds_bytes(a.m, a.n, a.D, a.P, a.W);
     return 2 * a.W + 1 <= 64 ? launch_lb_ti_slots<1>(a, nblocks, lds, s) : launch_lb_ti_slots<2>(a, nblocks, lds, s);
 }
 

@@ -333,10 +333,15 @@ hipError_t launch_query_steps(const float* Q, int nq, int m, int D, float* delta
 size_t pc_boxes_lds_bytes(int max_pts, int K, int D);
 hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s);
 hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s);
+// query-side boxes only; items are chunks of 64 list entries of one query
+hipError_t launch_lb_pc_lanes(const PcArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_lb_ti(const TiArgs& a, int nblocks, hipStream_t s);
 // Exact rows of LB_TIP: row 0 and, with P > 0, every multiple of P.
 __host__ __device__ inline int ti_exact_rows(int m, int P) { return P > 0 ? (m - 1) / P + 1 : 1; }
-size_t ti_lds_bytes(int m, int n, int D, int P);
+// LDS of the LB_TI launch for a pair of lengths (m, n) and band half-width W
+size_t ti_lds_bytes(int m, int n, int D, int P, int W);
+size_t ti_cols_lds_bytes(int m);
+hipError_t launch_lb_ti_cols(const TiArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_route(const RouteArgs& a, int max_in, hipStream_t s);
 hipError_t launch_list_items(const int32_t* cnt, int cnt_uniform, int nq, int per, int32_t* prefix,
                              int32_t* item_query, int32_t* counter, hipStream_t s);

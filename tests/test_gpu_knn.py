@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from ti_allowance import ti_lower_allowance
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -355,28 +356,6 @@ def test_lb_ti_dense_matrix(dev, P, top, frac):
     np.testing.assert_array_less(lo - 1e-30, lb + 1e-30)
 
 
-def ti_lower_allowance(q, c, W, P, top):
-    """The smallest value the float32 LB_TI may return for (q, c): per band
-    cell the oracle's float64 triangle bounds (L, U) with L lowered by twice
-    the kernel's allowance s U (the allowance it subtracts, plus at most as
-    much float32 drift of the recursion), s = (D/2 + 5 + r_max) u 1.02 with
-    r_max the longest chain of recursion steps since an exact value; the
-    column minima of max(0, .) squared and summed, then lowered by the
-    float32 summation error and the kernel's final deflation, 2 (n + 5) u."""
-    m, D = q.shape
-    n = c.shape[0]
-    u = 2.0 ** -24
-    if P > 0:
-        rmax = P - 1 if top else 2 * (P - 1) + 1
-    else:
-        rmax = m if top else 2 * m + 1
-    s = (0.5 * D + 5.0 + rmax) * u * 1.02
-    Lo, Hi = O.ti_cells(q, c, W, P=P, top=top)
-    cell = np.maximum(Lo - 2.0 * 1.01 * s * Hi, 0.0)
-    col = np.nanmin(np.where(np.isnan(Lo), np.inf, cell), axis=0)
-    return float(np.sum(col * col)) * (1.0 - 2.0 * (n + 5) * u * 1.01)
-
-
 @pytest.mark.parametrize("bounds", ["mv+pc", "mv+ti", "mv+pc+ti"])
 @pytest.mark.parametrize("frac", [(1, 20), (1, 10), (1, 5)])
 def test_cascade_with_advanced_bounds(dev, bounds, frac):
@@ -407,8 +386,32 @@ def test_full_size_sampled_full_cascade(dev):
     assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == 1000 * 10000
 
 
+@pytest.mark.parametrize("P,top", [(5, 1), (0, 0), (3, 0), (1, 0), (5, 0)])
+@pytest.mark.parametrize("case", [(150, 150, (1, 2)), (300, 300, (1, 2)), (180, 300, (1, 4))],
+                         ids=["T150_W74", "T300_W150", "m180_n300_W120"])
+def test_lb_ti_dense_matrix_wide_band(dev, P, top, case):
+    """LB_TI for bands wider than 63 (the column mapping), against the oracle:
+    never above it and never below the per-cell allowance."""
+    from paper_2101_07731_amd import search, synth
+    m, n, frac = case
+    D = 5
+    Q, Cs = synth.cascade_knn(nq=5, nc=24, T=max(m, n), D=D, seed=41)
+    Q = np.ascontiguousarray(Q[:, :m])
+    Cs = np.ascontiguousarray(Cs[:, :n])
+    W = O.window_eff(m, n, 0, *frac)
+    assert 2 * W + 1 > 128
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_ti dense wide", P, top, case, "W", W)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="ti", frac=frac, ti_period=P,
+                             ti_top=top).cpu().numpy().astype(np.float64)
+    ref = np.array([[O.lb_ti(q, c, W, P=P, top=top) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12) + 1e-30)
+    lo = np.array([[ti_lower_allowance(q, c, W, P, top) for c in Cs] for q in Q])
+    np.testing.assert_array_less(lo - 1e-30, lb + 1e-30)
+
+
 def test_tune_cascade_picks_a_runnable_choice(dev):
-    """Setup-stage choice of bounds and triggers; LB_TI choices are skipped when W_eff > 63."""
+    """Setup-stage choice of bounds and triggers, also with a band wider than 63."""
     from paper_2101_07731_amd import search, synth
     Q, Cs = synth.cascade_knn(nq=20, nc=400, T=96, D=8, seed=31)
     ix = search.Index(torch.from_numpy(Cs).to(dev))
@@ -421,4 +424,4 @@ def test_tune_cascade_picks_a_runnable_choice(dev):
     Ql, Cl = synth.long_knn(nq=3, nc=20, T=300, D=4)
     ixl = search.Index(torch.from_numpy(Cl).to(dev))
     _, tl = search.tune_cascade(ixl, torch.from_numpy(Ql).to(dev), reps=1, frac=(1, 2))   # W = 150
-    assert all("ti" not in k[0] for k in tl) and ("mv", None, None) in tl
+    assert len(tl) == len(search.CASCADE_CHOICES)

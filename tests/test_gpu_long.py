@@ -7,7 +7,9 @@ expanded window and Lv = 2 and 3 quantisation levels.
   orc_pc_boxes bit for bit (the float32 cell assignment is the contract).
 * Dense LB_PC: never above the oracle's float64 bound, and within the
   documented float32 deflation of it.
-* Search: mv+pc (and mv+pc+ti) 1-NN equal to the oracle's exhaustive
+* Dense LB_TI (the column mapping of bands wider than 63): never above the
+  oracle's bound, and never below its per-cell rounding allowance.
+* Search: mv+pc, mv+ti and mv+pc+ti 1-NN equal to the oracle's exhaustive
   search on sampled queries.
 """
 import sys
@@ -131,3 +133,67 @@ def test_knn_long_mv_pc_sampled(dev, long_data, K):
     i2, d2 = search.knn(ix, Qd, frac=(1, 10), bounds="mv")
     np.testing.assert_array_equal(i2.cpu().numpy(), idx)
     np.testing.assert_array_equal(d2.cpu().numpy(), dist)
+
+
+def _ti_allowance(q, c, W, P, top):
+    from ti_allowance import ti_lower_allowance
+    return ti_lower_allowance(q, c, W, P, top)
+
+
+@pytest.mark.parametrize("P,top", [(5, 1), (5, 0)])
+def test_lb_ti_dense_long(dev, long_data, P, top):
+    """The dense LB_TI matrix of 4 queries against all 2000 references of the
+    long workload (W = 102): every element at most the oracle's bound; a
+    sample of 40 elements at least its per-cell allowance."""
+    from paper_2101_07731_amd import search
+    Q, Cs = long_data
+    Qs = np.ascontiguousarray(Q[[0, 13, 101, 199]])
+    W = O.window_eff(T_LONG, T_LONG, 0, 1, 10)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_ti dense long", P, top)
+    lb = search.lower_bounds(ix, torch.from_numpy(Qs).to(dev), kind="ti", frac=(1, 10), ti_period=P,
+                             ti_top=top).cpu().numpy().astype(np.float64)
+    pairs = [(a, b) for a in range(len(Qs)) for b in range(len(Cs))]
+    ref = np.array(_pool_map(lambda ab: O.lb_ti(Qs[ab[0]], Cs[ab[1]], W, P=P, top=top), pairs)).reshape(len(Qs), -1)
+    assert np.all(lb <= ref * (1 + 1e-12) + 1e-30)
+    rng = np.random.default_rng(3)
+    samp = [(int(a), int(b)) for a, b in zip(rng.integers(0, 4, 40), rng.integers(0, 2000, 40))]
+    lo = _pool_map(lambda ab: _ti_allowance(Qs[ab[0]], Cs[ab[1]], W, P, top), samp)
+    for (a, b), v in zip(samp, lo):
+        assert lb[a, b] >= v - 1e-30, (a, b, lb[a, b], v, ref[a, b])
+
+
+@pytest.mark.parametrize("bounds", ["mv+ti", "mv+pc+ti"])
+def test_knn_long_full_cascade_sampled(dev, long_data, bounds):
+    """The whole long workload with LB_TI in the cascade (every gated pair
+    gets the advanced bounds: e = 0), sampled queries against the oracle."""
+    from paper_2101_07731_amd import search
+    Q, Cs = long_data
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    say("knn long", bounds)
+    idx, dist, st = search.knn(ix, Qd, stats=True, frac=(1, 10), bounds=bounds, pc_clusters=16, trigger_pc=0.0,
+                               trigger_ti=0.0)
+    say("stats", st)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == st["pairs"] == 200 * 2000
+    sample = np.array([5, 120])
+    ri, rd = O.knn_exhaustive(Q[sample], Cs, num=1, den=10, threads=16)
+    np.testing.assert_array_equal(idx[sample], ri)
+    np.testing.assert_array_equal(dist[sample], rd.astype(np.float32))
+
+
+def test_lb_ti_window_204(dev):
+    """LB_TI at W = 204 (length 1024, window 20%), d = 16: every element of a
+    3 x 12 matrix against the oracle and its allowance."""
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.long_knn(nq=3, nc=12, T=1024, D=16, seed=44)
+    W = O.window_eff(1024, 1024, 0, 1, 5)
+    assert W == 204
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="ti", frac=(1, 5)).cpu().numpy().astype(np.float64)
+    pairs = [(a, b) for a in range(3) for b in range(12)]
+    ref = np.array(_pool_map(lambda ab: O.lb_ti(Q[ab[0]], Cs[ab[1]], W), pairs)).reshape(3, 12)
+    lo = np.array(_pool_map(lambda ab: _ti_allowance(Q[ab[0]], Cs[ab[1]], W, 5, 1), pairs)).reshape(3, 12)
+    assert np.all(lb <= ref * (1 + 1e-12) + 1e-30)
+    np.testing.assert_array_less(lo - 1e-30, lb + 1e-30)
