@@ -91,6 +91,20 @@ int tc_dtw_abi_version(void);
 const char* tc_dtw_last_error(void);
 const char* tc_dtw_status_string(tc_dtw_status s);
 
+/* tc_dtw_sync_status: waits for `stream`, then reads and clears the
+ * device's status word, into which kernels record conditions they detect
+ * but cannot return (the calls are asynchronous): a reference value that
+ * is not finite (tc_dtw_build_index), a query value that is not finite
+ * (the searches and the bound matrices), and a bounded wait between the
+ * waves sharing a long pair that ran out (tc_dtw_banded / _run: that
+ * pair's distance is NaN).  The word is one per device and accumulates
+ * over all calls since it was last read.  Returns TC_DTW_OK if it was
+ * clear, else TC_DTW_ERR_DEVICE with the conditions in tc_dtw_last_error();
+ * TC_DTW_ERR_DEVICE also when there is no usable device.  For tests, the
+ * environment variable TC_DTW_FAKE_NO_DEVICE (set, not "0") makes every
+ * call behave as on a machine without a usable device. */
+tc_dtw_status tc_dtw_sync_status(tc_dtw_stream stream);
+
 /* --------------------------------------------------------- banded DTW ---
  * tc_dtw_banded: DTW of x->count pairs (x_b, y_b), b = 0..count-1
  * (Sec. 2, Eq. 1 within the Sakoe-Chiba band).

@@ -92,6 +92,7 @@ _SIGS = {
     "tc_dtw_abi_version": (C.c_int, []),
     "tc_dtw_last_error": (C.c_char_p, []),
     "tc_dtw_status_string": (C.c_char_p, [C.c_int]),
+    "tc_dtw_sync_status": (C.c_int, [C.c_void_p]),
     "tc_dtw_banded_workspace_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_uint32]),
     "tc_dtw_saved_bytes": (C.c_size_t, [C.POINTER(Batch), C.POINTER(Batch), Window]),
     "tc_dtw_banded": (C.c_int, [C.POINTER(Batch), C.POINTER(Batch), Window, C.c_uint32, C.c_void_p,

@@ -1,6 +1,7 @@
 // Host-side helpers of the C ABI.
 #include "api_common.h"
 
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -23,6 +24,10 @@ tc_dtw_status hip_fail(hipError_t e, const char* what) {
 }
 
 tc_dtw_status check_device() {
+    // test hook: behave as on a machine without a usable device
+    const char* fake = std::getenv("TC_DTW_FAKE_NO_DEVICE");
+    if (fake && *fake && std::strcmp(fake, "0") != 0)
+        return fail(TC_DTW_ERR_DEVICE, "no usable device (TC_DTW_FAKE_NO_DEVICE is set)");
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

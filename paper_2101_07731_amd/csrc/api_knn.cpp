@@ -205,6 +205,7 @@ static KnnPlanDev dev_plan(const KnnPlan& K, const tc_dtw_index* ix, const HostS
     d.part = K.nseg > 1 ? reinterpret_cast<float*>(ws + K.o_part) : nullptr;
     d.k = K.k;
     d.topk = K.k > 1 ? reinterpret_cast<unsigned long long*>(ws + K.o_topk) : nullptr;
+    d.status = status_word();
     return d;
 }
 
@@ -450,6 +451,7 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
     r.key = d.key; r.stats = d.stats;
     r.seeds = d.seeds; r.seed_dist = d.seed_dist; r.R = K.R; r.list_cnt = d.cnt;
     r.nn_idx = nn_idx; r.nn_dist = nn_dist;
+    r.status = status_word();
 
     hipEvent_t ev[8];
     const bool timed = stats != nullptr;
@@ -593,6 +595,7 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
     a.tiles = L.uniform ? reinterpret_cast<float*>(base + L.off_tiles) : nullptr;
     a.gamma = reinterpret_cast<float*>(base + L.off_gamma);
     a.range_keys = reinterpret_cast<uint32_t*>(base + L.off_range);
+    a.status = status_word();
     // meta: dst offsets, gamma offsets, lengths, source offsets
     int64_t* dst_off = reinterpret_cast<int64_t*>(base + L.off_meta);
     int64_t* gam_off = dst_off + R.count;
@@ -929,6 +932,7 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         a.tab = reinterpret_cast<float*>(w + R.o_tab);
         a.t_off = reinterpret_cast<const int64_t*>(w + R.o_toff);
         a.lb = lb;
+        a.status = status_word();
         hipError_t e;
         if ((e = hipMemcpyAsync(w + R.o_qoff, R.q_off.data(), R.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
             (e = hipMemcpyAsync(w + R.o_qlen, R.q_len.data(), R.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||

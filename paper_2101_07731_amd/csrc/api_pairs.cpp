@@ -354,6 +354,7 @@ static tc_dtw_status run_fwd(const tc_dtw_pairs_plan* p, const float* x, const f
         a.dist = dist;
         a.codes = static_cast<uint32_t*>(saved);
         a.counter = counters + k;
+        a.status = status_word();
         const int K = c.rows ? c.waves_per_pair : 1;
         if (K > 1) {
             const size_t lds = pipe_lds_bytes(c.maxn, c.dim, K, f64);

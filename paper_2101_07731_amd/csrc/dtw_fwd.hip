@@ -214,6 +214,7 @@ __global__ __launch_bounds__(512) void dtw_rows_pipe_kernel(DtwFwdArgs a) {
             const bool bad = *sflag != 0;
             a.dist[d.out] = bad ? __builtin_nanf("") : (float)v;
             if (a.dist64) a.dist64[d.out] = bad ? __builtin_nan("") : (double)v;
+            if (bad && a.status) atomicOr(a.status, kStatusWaitExpired);
         }
         __syncthreads();
     }

@@ -106,12 +106,15 @@ __global__ void k_index_gamma(const float* series, const int64_t* dst_off, const
     }
 }
 
-// rk keys -> float[2] (min, max) in place.
-__global__ void k_range_finish(uint32_t* rk) {
+// rk keys -> float[2] (min, max) in place.  A value that is not finite
+// (NaN keys order beyond the infinities) leaves a non-finite min or max,
+// which is reported in the status word.
+__global__ void k_range_finish(uint32_t* rk, uint32_t* status) {
     if (threadIdx.x == 0) {
         const float lo = key_to_float(rk[0]), hi = key_to_float(rk[1]);
         reinterpret_cast<float*>(rk)[0] = lo;
         reinterpret_cast<float*>(rk)[1] = hi;
+        if (status && !(__builtin_isfinite(lo) && __builtin_isfinite(hi))) atomicOr(status, kStatusNonFiniteRef);
     }
 }
 
@@ -127,7 +130,7 @@ hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s) {
     const int gx = (a.maxlen + 255) / 256;
     hipLaunchKernelGGL(k_index_gamma, dim3(gx, gy), dim3(256), 0, s, a.series, a.dst_off, a.lens,
                        a.count, a.ulen, a.D, a.gamma_off, a.gamma);
-    hipLaunchKernelGGL(k_range_finish, dim3(1), dim3(64), 0, s, a.range_keys);
+    hipLaunchKernelGGL(k_range_finish, dim3(1), dim3(64), 0, s, a.range_keys, a.status);
     return hipGetLastError();
 }
 

@@ -6,6 +6,16 @@
 
 namespace tcdtw {
 
+// Bits of the device status word (one per device; kernels OR conditions into
+// it, tc_dtw_sync_status reads and clears it).
+enum : uint32_t {
+    kStatusNonFiniteRef = 1u,     // a reference value is not finite (index build)
+    kStatusNonFiniteQuery = 2u,   // a query value is not finite (search preparation)
+    kStatusWaitExpired = 4u       // a bounded wait between the waves of a pair ran out (distance NaN)
+};
+// The current device's status word (null if it cannot be located).
+uint32_t* status_word();
+
 // Largest band half-width handled by the diagonal-pair mapping: W_eff + 1
 // lanes per pair must fit one wave.
 constexpr int kDiagMaxW = 63;
@@ -39,6 +49,7 @@ struct DtwFwdArgs {
     int64_t codes_stride;    // uniform: u32 words per pair
     int32_t* counter;        // non-null: persistent waves take items 0..nitems-1 from it
     int32_t nitems;
+    uint32_t* status;        // device status word (or null)
 };
 
 // Arguments of the backward kernel.
@@ -109,6 +120,7 @@ struct IndexBuildArgs {
     float* tiles;
     float* gamma;
     uint32_t* range_keys;     // 2 words, become float min / max
+    uint32_t* status;         // device status word (or null)
 };
 hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s);
 
@@ -152,6 +164,7 @@ struct KnnPlanDev {
     int32_t nseg;
     unsigned long long* topk;   // [nq][k] keys of the k best candidates so far (k > 1), else null
     int32_t k;
+    uint32_t* status;     // device status word (or null)
 };
 // Element segments of the LB_MV launch (more when few query tiles would leave HBM idle).
 int lb_mv_segments(int ntiles, int nq, int E);
@@ -232,6 +245,7 @@ struct RaggedKnnArgs {
     const int32_t* list_cnt;
     int32_t* nn_idx;
     float* nn_dist;
+    uint32_t* status;          // device status word (or null)
 };
 hipError_t launch_rq_tables(const RaggedKnnArgs& a, hipStream_t s);
 hipError_t launch_rlb_mv(const RaggedKnnArgs& a, hipStream_t s);

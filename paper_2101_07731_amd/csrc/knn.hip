@@ -47,7 +47,8 @@ __global__ void k_knn_init(int nq, unsigned long long* key, int32_t* cnt, int32_
 // Layout env[qtile][e][QT][2] (e = j*D + p), so one 64-byte scalar load
 // gives the (U, L) pairs of a tile's QT queries for one element.
 __global__ void k_envelope(const float* __restrict__ Q, int nq, int m, int n, int D, int W,
-                           float* __restrict__ env) {
+                           float* __restrict__ env, uint32_t* status) {
+    bool bad = false;   // a non-finite query value (the minimum and maximum skip NaN)
     const int E = n * D;
     const int Ep = (E + 3) / 4 * 4;     // padded like the candidate tiles; padding gets (+inf, -inf)
     const int nqt = (nq + kQT - 1) / kQT;
@@ -63,17 +64,20 @@ __global__ void k_envelope(const float* __restrict__ Q, int nq, int m, int n, in
             const float* s = Q + (int64_t)q * m * D + p;
             U = s[(int64_t)i0 * D];
             L = U;
+            bad |= !__builtin_isfinite(U);
 #pragma unroll 8
             for (int i = i0 + 1; i <= i1; ++i) {    // unrolled: eight loads in flight
                 const float v = s[(int64_t)i * D];
                 U = __builtin_fmaxf(U, v);
                 L = __builtin_fminf(L, v);
+                bad |= !__builtin_isfinite(v);
             }
         }
         float* o = env + (((int64_t)(q / kQT) * Ep + e) * kQT + (q % kQT)) * 2;
         o[0] = U;
         o[1] = L;
     }
+    if (bad && status) atomicOr(status, kStatusNonFiniteQuery);
 }
 
 // LB_MV (Sec. 3, squared form) of up to kQT queries against 64 candidates
@@ -884,7 +888,8 @@ hipError_t launch_knn_prep(const KnnPlanDev& p, hipStream_t s, bool init) {
     if (p.env) {
         const int64_t total = (int64_t)((p.nq + kQT - 1) / kQT) * kQT * (((int64_t)p.n * p.D + 3) / 4 * 4);
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_envelope, dim3(blocks), dim3(256), 0, s, p.Q, p.nq, p.m, p.n, p.D, p.W, p.env);
+        hipLaunchKernelGGL(k_envelope, dim3(blocks), dim3(256), 0, s, p.Q, p.nq, p.m, p.n, p.D, p.W, p.env,
+                           p.status);
     }
     return hipGetLastError();
 }

@@ -72,11 +72,14 @@ __global__ __launch_bounds__(256) void k_rq_tables(RaggedKnnArgs a) {
     const float* src = a.Q + a.q_off[q];
     float* mx = a.tab + a.t_off[q];
     float* mn = mx + (int64_t)L * md;
+    bool bad = false;
     for (int64_t e = threadIdx.x; e < md; e += blockDim.x) {
         const float v = src[e];
         mx[e] = v;
         mn[e] = v;
+        bad |= !__builtin_isfinite(v);
     }
+    if (bad && a.status) atomicOr(a.status, kStatusNonFiniteQuery);
     __syncthreads();
     for (int k = 1; k < L; ++k) {
         const int half = 1 << (k - 1);

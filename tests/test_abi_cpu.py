@@ -283,3 +283,19 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch_on_the_host():
     x = _batch()
     st = lib.tc_dtw_banded_noalloc(C.byref(x), C.byref(x), L.Window(2, 0, 0), 0, None, None, None)
     assert st == L.ERR_INVALID
+
+
+def test_fake_no_device_and_sync_status(monkeypatch):
+    """With TC_DTW_FAKE_NO_DEVICE set, calls that pass the host checks fail
+    with ERR_DEVICE (named in the message) instead of touching a device;
+    tc_dtw_sync_status reports the same."""
+    lib = L.lib()
+    monkeypatch.setenv("TC_DTW_FAKE_NO_DEVICE", "1")
+    x = _batch()
+    st = lib.tc_dtw_banded(C.byref(x), C.byref(x), L.Window(2, 0, 0), 0, C.c_void_p(0x2000), None, None, 0, None)
+    assert st == L.ERR_DEVICE
+    assert b"TC_DTW_FAKE_NO_DEVICE" in lib.tc_dtw_last_error()
+    assert lib.tc_dtw_sync_status(None) == L.ERR_DEVICE
+    # the host checks still come first
+    st = lib.tc_dtw_banded(C.byref(x), C.byref(x), L.Window(-1, 0, 0), 0, C.c_void_p(0x2000), None, None, 0, None)
+    assert st == L.ERR_INVALID
