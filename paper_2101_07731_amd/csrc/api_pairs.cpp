@@ -20,6 +20,7 @@ namespace tcdtw {
 // The diagonal mapping stages both series of a pair in LDS; beyond this
 // many bytes a pair runs on the row mapping, whose LDS stays small.
 constexpr size_t kDiagLdsBudget = 32768;
+constexpr size_t kLdsPerWorkgroup = 163840;   // gfx950: 160 KB of LDS per workgroup
 constexpr int kDefaultWavesPerCu = 16;
 
 struct PairClass {
@@ -127,6 +128,12 @@ static tc_dtw_status make_plan(const tc_dtw_batch* xb, const tc_dtw_batch* yb, t
         P.n = Y.ulen;
         P.W = window_eff(P.m, P.n, w);
         P.urows = use_rows(P.m, P.n, P.W, P.D, diag_max);
+        // a batch too small to fill the chip with one wave per pair runs the cooperative
+        // diagonal kernel (float32), whose time is the serial chain, not occupancy: it keeps
+        // the diagonal mapping wherever its LDS fits (the codes layout follows the mapping)
+        if (P.urows && P.W <= diag_max && P.npairs <= kCoopMaxItems &&
+            diag_coop_lds_bytes(P.m, P.n, P.W, P.D, 1) <= kLdsPerWorkgroup)
+            P.urows = false;
         P.codes_stride = codes_words(P.m, P.n, P.W, P.urows);
         P.saved_words = P.codes_stride * P.npairs;
         return TC_DTW_OK;
@@ -469,6 +476,17 @@ tc_dtw_status banded_direct(const tc_dtw_batch* x, const tc_dtw_batch* y, tc_dtw
     if (fwd_lds_bytes(a, P.urows, f64) > lds_limit())
         return fail(TC_DTW_ERR_UNSUPPORTED, "series too long for the LDS staging of one pair");
     const int items = P.urows ? P.npairs : (P.npairs + a.P - 1) / a.P;
+    if (!f64 && !P.urows && items <= kCoopMaxItems) {
+        // too few items to fill the chip with one wave each: the serial chain of the recurrence
+        // sets the time, so three more waves per item form the point costs ahead of it
+        DtwFwdArgs c = a;
+        while (c.P > 1 && diag_coop_lds_bytes(P.m, P.n, P.W, P.D, c.P) > lds_limit()) --c.P;
+        if (diag_coop_lds_bytes(P.m, P.n, P.W, P.D, c.P) <= lds_limit()) {
+            const hipError_t e = launch_dtw_diag_coop(c, saved != nullptr, (P.npairs + c.P - 1) / c.P, s);
+            if (e != hipSuccess) return hip_fail(e, "dtw forward launch");
+            return ok();
+        }
+    }
     const hipError_t e = launch_dtw_fwd(a, f64, saved != nullptr, P.urows, items, 0, s);
     if (e != hipSuccess) return hip_fail(e, "dtw forward launch");
     return ok();

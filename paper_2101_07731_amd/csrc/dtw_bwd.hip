@@ -3,15 +3,20 @@
 // as 2-bit argmin codes (0 = diagonal, 1 = (i-1,j), 2 = (i,j-1)).
 //
 // One block of 256 threads per pair:
-//   1. the pair's codes, and both series when they fit, are copied to LDS
-//      (eight loads in flight per thread);
+//   1. the pair's codes are copied to LDS (eight loads in flight per thread);
 //   2. wave 0 walks the path back from (m-1, n-1) to (0, 0) at a
 //      wave-uniform position, its lanes holding the 64 code words around
-//      it (consecutive steps mostly stay among them), each step reading its
-//      word from the lane that holds it; a monotone path meets every row i in one run of columns
-//      [rlo_i, rhi_i] and every column j in one run of rows [clo_j, chi_j],
-//      which are kept in LDS;
-//   3. threads over (row, dimension) form grad_x[i][p] = g * sum_{j in run}
+//      it (consecutive steps mostly stay among them; on the diagonal layout
+//      the next block back is read ahead), each step reading its word from
+//      the lane that holds it and appending its 2-bit step to a record in
+//      LDS (one word per 16 steps); meanwhile waves 1-3 copy both series to
+//      LDS when they fit;
+//   3. all threads decode the record: each takes a run of consecutive steps,
+//      a block scan of the row and column decrements gives its starting
+//      cell, and it writes the runs its steps close: a monotone path meets
+//      every row i in one run of columns [rlo_i, rhi_i] and every column j
+//      in one run of rows [clo_j, chi_j];
+//   4. threads over (row, dimension) form grad_x[i][p] = g * sum_{j in run}
 //      2 (x_ip - y_jp), threads over (column, dimension) grad_y likewise,
 //      accumulated in float64 in increasing j (i) and rounded once to
 //      float32.
@@ -79,6 +84,96 @@ struct CodeMap {
     }
 };
 
+// The walk of wave 0 (all positions and codes wave-uniform, in scalar
+// registers): from (m-1, n-1) back to (0, 0), each step's 2-bit code appended
+// to `rec` (16 to a word, written by lane 0).  `codes` is the pair's code
+// record, in LDS or global memory (one instantiation each, so that LDS reads
+// are LDS instructions).  Each lane holds one word of the current block of
+// 64; on the diagonal layout (32-bit index arithmetic) the block before it
+// is read ahead, since a step never moves to a later block and moves back at
+// most one.  Returns the number of steps.
+// Diagonal layout: the walk keeps (sigma, slot, r) of the current cell
+// (sigma = j - i + off, slot = sigma & 1, r = (i + j - slot) / 2) and
+// updates them per step: a diagonal step leaves sigma and the slot and
+// lowers r; a step to (i-1, j) or (i, j-1) moves sigma by +1 or -1, flips
+// the slot and lowers r when the slot was 0.  The walk ends at (0, 0), the
+// only cell with r = 0 and slot 0.  The word of a cell is block r / 8,
+// lane sigma / 2; a step never moves to a later block and moves back at
+// most one, so the block before the current one is read ahead.
+__device__ __forceinline__ int walk_diag(const CodeMap& cm, const uint32_t* codes, int words, int m, int n,
+                                         uint32_t* rec, int lane) {
+    int sigma = (n - m) + cm.off;
+    int slot = sigma & 1;
+    int r = (m + n - 2 - slot) >> 1;
+    int blk = r >> 3;
+    auto load = [&](int b) __attribute__((always_inline)) {
+        const int w = b * cm.G + lane;
+        return (b >= 0 && w < words) ? codes[w] : 0u;
+    };
+    uint32_t held = load(blk), ahead = load(blk - 1);
+    int L = 0;
+    while (r > 0 || slot != 0) {
+        // up to 16 steps into one record word (all values scalar)
+        uint32_t acc = 0;
+        int k = 0;
+        for (; k < 16 && (r > 0 || slot != 0); ++k) {
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)held, sigma >> 1);
+            uint32_t code = (word >> ((r & 7) * 4 + 2 * slot)) & 3u;
+            code = code == 3u ? 2u : code;
+            if (code == 0u) {
+                r -= 1;
+            } else {
+                r -= slot == 0;
+                slot ^= 1;
+                sigma += code == 1u ? 1 : -1;
+            }
+            acc |= code << (2 * k);
+            if ((r >> 3) != blk) {
+                blk = r >> 3;
+                held = ahead;
+                ahead = load(blk - 1);
+            }
+        }
+        if (lane == 0) rec[L >> 4] = acc;
+        L += k;
+    }
+    return L;
+}
+
+// Row layout: each lane holds one word of the current block of 64, reloaded
+// when the path leaves it.
+__device__ __forceinline__ int walk_rows(const CodeMap& cm, const uint32_t* codes, int words, int m, int n,
+                                         uint32_t* rec, int lane) {
+    int i = m - 1, j = n - 1;
+    int cur = -1;
+    uint32_t held = 0;
+    int L = 0;
+    while (i > 0 || j > 0) {
+        uint32_t acc = 0;
+        int k = 0;
+        for (; k < 16 && (i > 0 || j > 0); ++k) {
+            int64_t b64;
+            int ln, sh;
+            cm.locate64(i, j, b64, ln, sh);
+            const int base = (int)b64;
+            if (base != cur) {
+                const int w = base + lane;
+                held = w < words ? codes[w] : 0u;
+                cur = base;
+            }
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)held, ln);
+            uint32_t code = (word >> sh) & 3u;
+            code = code == 3u ? 2u : code;
+            i -= code != 2u;
+            j -= code != 1u;
+            acc |= code << (2 * k);
+        }
+        if (lane == 0) rec[L >> 4] = acc;
+        L += k;
+    }
+    return L;
+}
+
 __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     extern __shared__ int32_t sbw[];
     const int tid = threadIdx.x;
@@ -99,6 +194,8 @@ __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     int32_t* rhi = rlo + m;
     int32_t* clo = rhi + m;
     int32_t* chi = clo + n;
+    uint32_t* rec = reinterpret_cast<uint32_t*>(chi + n);          // [(m + n) / 16 + 1] step record
+    int32_t* scan = reinterpret_cast<int32_t*>(rec + (m + n) / 16 + 1);   // [kBwdThreads + 1]
     uint32_t* scodes = reinterpret_cast<uint32_t*>(sbw + a.runs_ints);
     float* sser = reinterpret_cast<float*>(scodes + a.stage_cap);
     CodeMap cm;
@@ -110,43 +207,57 @@ __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     const float* xs = a.x + xoff;
     const float* ys = a.y + yoff;
     if (staged) copy_to_lds(scodes, gcodes, words, tid, kBwdThreads);
-    if (sstaged) {
-        copy_to_lds(sser, xs, (int64_t)m * D, tid, kBwdThreads);
-        copy_to_lds(sser + m * D, ys, (int64_t)n * D, tid, kBwdThreads);
-    }
     __syncthreads();
 
     if (tid < kWave) {
-        // wave 0 walks with wave-uniform (scalar) position: each lane holds one word of the
-        // current block of 64 (reloaded when the path leaves it) and a step reads its word
-        // from the lane that holds it, with no LDS round trip; lane 0 writes the runs
         const int lane = tid;
-        int i = m - 1, j = n - 1;
-        if (lane == 0) { rhi[i] = j; chi[j] = i; }
-        int64_t cur = -1;
-        uint32_t held = 0;
-        while (i > 0 || j > 0) {
-            int64_t base;
-            int ln, sh;
-            cm.locate64(i, j, base, ln, sh);
-            if (base != cur) {
-                const int64_t w = base + lane;
-                held = w < words ? (staged ? scodes[w] : gcodes[w]) : 0u;
-                cur = base;
-            }
-            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)held, ln);
-            const int code = (word >> sh) & 3;
-            int pi = i, pj = j;
-            if (code == 0) { pi = i - 1; pj = j - 1; }
-            else if (code == 1) { pi = i - 1; }
-            else { pj = j - 1; }
-            if (lane == 0) {
-                if (pi != i) { rlo[i] = j; rhi[pi] = pj; }
-                if (pj != j) { clo[j] = i; chi[pj] = pi; }
-            }
+        int L;
+        // the walk of wave 0, all positions and codes wave-uniform (scalar registers); the
+        // codes from LDS or global memory (separate instantiations keep LDS reads LDS reads)
+        if (staged)
+            L = cm.diag ? walk_diag(cm, scodes, (int)words, m, n, rec, lane)
+                        : walk_rows(cm, scodes, (int)words, m, n, rec, lane);
+        else
+            L = cm.diag ? walk_diag(cm, gcodes, (int)words, m, n, rec, lane)
+                        : walk_rows(cm, gcodes, (int)words, m, n, rec, lane);
+        if (lane == 0) scan[kBwdThreads] = L;
+    } else if (sstaged) {
+        copy_to_lds(sser, xs, (int64_t)m * D, tid - kWave, kBwdThreads - kWave);
+        copy_to_lds(sser + m * D, ys, (int64_t)n * D, tid - kWave, kBwdThreads - kWave);
+    }
+    __syncthreads();
+
+    {   // decode the record into the runs: thread t takes steps [s0, s1)
+        const int L = scan[kBwdThreads];
+        const int per = (L + kBwdThreads - 1) / kBwdThreads;
+        const int s0 = min(L, tid * per), s1 = min(L, s0 + per);
+        auto step_code = [&](int st) __attribute__((always_inline)) { return (rec[st >> 4] >> ((st & 15) * 2)) & 3u; };
+        int di = 0, dj = 0;
+        for (int st = s0; st < s1; ++st) {
+            const uint32_t c = step_code(st);
+            di += c != 2u;
+            dj += c != 1u;
+        }
+        // exclusive block scan of the packed decrements (each below 2^16)
+        scan[tid] = (di << 16) | dj;
+        __syncthreads();
+        for (int o = 1; o < kBwdThreads; o <<= 1) {
+            const int add = tid >= o ? scan[tid - o] : 0;
+            __syncthreads();
+            scan[tid] += add;
+            __syncthreads();
+        }
+        const int incl = scan[tid];
+        const int excl = incl - ((di << 16) | dj);
+        int i = m - 1 - (excl >> 16), j = n - 1 - (excl & 0xffff);
+        for (int st = s0; st < s1; ++st) {
+            const uint32_t c = step_code(st);
+            const int pi = c != 2u ? i - 1 : i, pj = c != 1u ? j - 1 : j;
+            if (pi != i) { rlo[i] = j; rhi[pi] = pj; }
+            if (pj != j) { clo[j] = i; chi[pj] = pi; }
             i = pi; j = pj;
         }
-        if (lane == 0) { rlo[0] = 0; clo[0] = 0; }
+        if (tid == 0) { rhi[m - 1] = n - 1; chi[n - 1] = m - 1; rlo[0] = 0; clo[0] = 0; }
     }
     __syncthreads();
 
@@ -194,16 +305,21 @@ static int64_t bwd_series_cap(int maxm, int maxn, int maxd) {
     return f <= kBwdSeriesLdsFloats ? f : 0;
 }
 
+// LDS ints of the runs (rlo, rhi, clo, chi), the step record and the scan
+static int bwd_runs_ints(int maxm, int maxn) {
+    return 2 * (maxm + maxn) + (maxm + maxn) / 16 + 1 + kBwdThreads + 1;
+}
+
 size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words, int maxd) {
     const int64_t cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
-    return (size_t)(2 * (maxm + maxn)) * 4 + (size_t)cap * 4 + (size_t)bwd_series_cap(maxm, maxn, maxd) * 4;
+    return (size_t)bwd_runs_ints(maxm, maxn) * 4 + (size_t)cap * 4 + (size_t)bwd_series_cap(maxm, maxn, maxd) * 4;
 }
 
 hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_words, int maxd, int nitems,
                           int grid, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     DtwBwdArgs b = a;
-    b.runs_ints = 2 * (maxm + maxn);
+    b.runs_ints = bwd_runs_ints(maxm, maxn);
     // the kernel stages a pair's codes (series) only when they fit the reserved words
     b.stage_cap = max_words < kBwdCodeLdsWords ? max_words : kBwdCodeLdsWords;
     b.series_cap = bwd_series_cap(maxm, maxn, maxd);

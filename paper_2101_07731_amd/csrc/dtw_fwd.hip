@@ -176,6 +176,195 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Diagonal pairs with the point costs formed ahead of the recurrence (float,
+// uniform pairs).  A workgroup of eight waves takes one item (the P pairs of
+// one wave of dtw_diag_kernel, same lane layout): after the pairs are staged
+// and the costs of the first chunk of rounds formed, waves 1-7 form the
+// costs of chunk c + 1 (cells of both slots of every lane, +inf on killed
+// slots, spare lanes and cells outside the matrix) into one half of an LDS
+// double buffer while wave 0 runs the recurrence over chunk c from the other
+// half.  The serial chain of a round is then two cost reads, two 3-way
+// minima, two adds and two lane shifts; the argmin codes (when saved) are
+// written in diag_core's layout, so tc_dtw_backward reads them unchanged.
+// This mapping is for batches too small to fill the chip with one wave per
+// item, whose time is the latency of the serial chain.
+// ---------------------------------------------------------------------------
+constexpr int kCoopRounds = 32;   // rounds per chunk (a multiple of 8: code words never straddle chunks)
+constexpr int kCoopThreads = 512; // one recurrence wave and seven cost waves
+
+size_t diag_coop_lds_bytes(int m, int n, int W, int D, int P) {
+    return diag_lds_bytes(m, n, W, D, P) + (size_t)2 * kCoopRounds * kWave * 8;
+}
+
+template <int NCH, bool SAVE, bool WODD>
+__global__ __launch_bounds__(512) void dtw_diag_coop_kernel(DtwFwdArgs a) {
+    const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+    const int m = a.m, n = a.n, W = a.W, P = a.P, D = a.D;
+    const int out0 = blockIdx.x * P;
+    const int npair_here = min(P, a.npairs - out0);
+    DiagGeom g;
+    g.init(m, n, W);
+    const int G = g.G, h = g.h, R = g.R, LQ = g.LQ, LC = g.LC;
+    const int per_pair = (LQ + LC) * NCH;
+    const float INF = __builtin_inff();
+    for (int gg = 0; gg < npair_here; ++gg) {
+        const float* xs = a.x + (int64_t)(out0 + gg) * m * D;
+        const float* ys = a.y + (int64_t)(out0 + gg) * n * D;
+        const int sq = gg * per_pair;
+        stage_series<NCH>(sq, LQ, g.qfirst(), xs, m, D, INF, tid, blockDim.x);
+        stage_series<NCH>(sq + LQ * NCH, LC, g.cfirst(), ys, n, D, -INF, tid, blockDim.x);
+    }
+    float2* cbuf = reinterpret_cast<float2*>(lds4 + P * per_pair);   // [2][kCoopRounds][64]
+    const int nchunks = (R + kCoopRounds - 1) / kCoopRounds;
+    // Costs of the E and O cells of lane `ln` for rounds [r0, r1) of chunk c: one thread walks
+    // consecutive rounds, so the O step's candidate point is the next round's E point.
+    auto produce = [&](int c, int ln, int r0, int r1) __attribute__((always_inline)) {
+        float2* dst = cbuf + (c & 1) * kCoopRounds * kWave + ln;
+        const int rbase = c * kCoopRounds;
+        const int grp = ln / G, lg = ln - grp * G;
+        if (grp >= npair_here) {
+            for (int rr = r0; rr < r1; ++rr) dst[rr * kWave] = make_float2(INF, INF);
+            return;
+        }
+        const int qpos = grp * per_pair + (W - lg) + rbase;
+        const int cpos = grp * per_pair + LQ * NCH + lg + rbase;
+        const bool ke = WODD && lg == 0, ko = !WODD && lg == G - 1;
+        if (r0 >= r1) return;
+        // the next round's points are read before this round's arithmetic
+        float4 cc[NCH], qn[NCH], cnn[NCH];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            cc[k] = lds4[cpos + k * LC + r0];
+            qn[k] = lds4[qpos + k * LQ + r0];
+            cnn[k] = lds4[cpos + k * LC + r0 + 1];
+        }
+        for (int rr = r0; rr < r1; ++rr) {
+            float4 qv[NCH], cn[NCH];
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) {
+                qv[k] = qn[k];
+                cn[k] = cnn[k];
+            }
+            if (rr + 1 < r1) {
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) {
+                    qn[k] = lds4[qpos + k * LQ + rr + 1];
+                    cnn[k] = lds4[cpos + k * LC + rr + 2];
+                }
+            }
+            float2 v;
+            v.x = ke ? INF : point_cost<NCH>(qv, cc, 0.0f);
+            v.y = ko ? INF : point_cost<NCH>(qv, cn, 0.0f);
+            dst[rr * kWave] = v;
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) cc[k] = cn[k];
+        }
+    };
+    // the chunk's rounds split into nparts consecutive runs, part `part` of them
+    auto produce_part = [&](int c, int ln, int part, int nparts) __attribute__((always_inline)) {
+        const int rows = min(kCoopRounds, R - c * kCoopRounds);
+        const int per = (rows + nparts - 1) / nparts;
+        produce(c, ln, min(rows, part * per), min(rows, (part + 1) * per));
+    };
+    __syncthreads();
+    const int nw = blockDim.x / kWave;
+    produce_part(0, lane, wv, nw);
+    __syncthreads();
+    // recurrence state of wave 0
+    const int grp = lane / G, lg = lane - grp * G;
+    const bool spare = grp >= npair_here;
+    float vE = INF, vO = INF;
+    if (!spare && lg == h) vE = 0.0f;              // virtual D(-1,-1)
+    uint32_t* codes = nullptr;
+    if (SAVE && !spare) codes = a.codes + (int64_t)(out0 + grp) * a.codes_stride;
+    // the recurrence's wave is first in issue arbitration: the producers fill its dependency gaps
+    if (wv == 0) __builtin_amdgcn_s_setprio(3);
+    for (int c = 0; c < nchunks; ++c) {
+        if (wv == 0) {
+            const float2* src = cbuf + (c & 1) * kCoopRounds * kWave + lane;
+            const int rbase = c * kCoopRounds;
+            const int rows = __builtin_amdgcn_readfirstlane(min(kCoopRounds, R - rbase));
+            // groups of eight rounds; the next group's costs are read before this group's
+            // recurrence so that the LDS latency is off the serial chain
+            float2 cur[8], nxt[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cur[u] = src[min(u, rows - 1) * kWave];
+            for (int g0 = 0; g0 < rows; g0 += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) nxt[u] = src[min(g0 + 8 + u, rows - 1) * kWave];
+                uint32_t cw = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (g0 + u < rows) {
+                        // neighbour values by whole-wave rotations: lane 0 receives lane 63's odd
+                        // slot and lane 63 lane 0's even slot, which are +inf or feed a killed step
+                        // (a killed or spare slot has cost +inf: lane 63's odd slot without WODD,
+                        // lane 0's even slot with it)
+                        {   // E step: diag = own even slot, up = own odd slot, left = lane-1's odd slot
+                            const float left = __uint_as_float(wave_ror1(__float_as_uint(vO)));
+                            float best;
+                            if (SAVE) {
+                                uint32_t code;
+                                best = min3_code(vE, vO, left, code);
+                                cw |= code << (u * 4);
+                            } else {
+                                best = __uint_as_float(umin3(__float_as_uint(vE), __float_as_uint(vO),
+                                                             __float_as_uint(left)));
+                            }
+                            vE = cur[u].x + best;
+                        }
+                        {   // O step: diag = own odd slot, up = lane+1's even slot, left = own even slot
+                            const float up = __uint_as_float(wave_rol1(__float_as_uint(vE)));
+                            float best;
+                            if (SAVE) {
+                                uint32_t code;
+                                best = min3_code(vO, up, vE, code);
+                                cw |= code << (u * 4 + 2);
+                            } else {
+                                best = __uint_as_float(umin3(__float_as_uint(vO), __float_as_uint(up),
+                                                             __float_as_uint(vE)));
+                            }
+                            vO = cur[u].y + best;
+                        }
+                    }
+                }
+                if (SAVE && codes) codes[(int64_t)((rbase + g0) >> 3) * G + lg] = cw;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+            }
+        } else if (c + 1 < nchunks) {
+            produce_part(c + 1, lane, wv - 1, nw - 1);
+        }
+        __syncthreads();
+    }
+    if (wv == 0) {
+        const int sigma = (n - m) + 2 * h;             // cell (m-1, n-1) lies on diagonal n-m
+        if (!spare && lg == (sigma >> 1)) a.dist[out0 + grp] = (sigma & 1) ? vO : vE;
+    }
+}
+
+template <int NCH, bool SAVE>
+static void launch_coop_nch(const DtwFwdArgs& a, int grid, size_t lds, hipStream_t s) {
+    if (a.wodd) hipLaunchKernelGGL((dtw_diag_coop_kernel<NCH, SAVE, true>), dim3(grid), dim3(kCoopThreads), lds, s, a);
+    else hipLaunchKernelGGL((dtw_diag_coop_kernel<NCH, SAVE, false>), dim3(grid), dim3(kCoopThreads), lds, s, a);
+}
+
+// Uniform pairs, W_eff <= 63, a.P pairs per item, float; one workgroup per item.
+hipError_t launch_dtw_diag_coop(const DtwFwdArgs& a, bool save, int nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const size_t lds = diag_coop_lds_bytes(a.m, a.n, a.W, a.D, a.P);
+    switch (nch_pad(a.D)) {
+#define TC_COOP_CASE(N) \
+        case N: save ? launch_coop_nch<N, true>(a, nitems, lds, s) : launch_coop_nch<N, false>(a, nitems, lds, s); break;
+        TC_COOP_CASE(1) TC_COOP_CASE(2) TC_COOP_CASE(3) TC_COOP_CASE(4)
+        TC_COOP_CASE(6) TC_COOP_CASE(8) TC_COOP_CASE(12) TC_COOP_CASE(16)
+#undef TC_COOP_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Row mapping with K waves per pair (rows_core_pipe): persistent workgroups
 // of 64 K threads take pairs from a device counter.  LDS: K candidate rings,
 // the row buffer of the launch's longest candidate, K progress counters, the

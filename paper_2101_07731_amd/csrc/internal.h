@@ -106,6 +106,11 @@ hipError_t launch_dtw_bwd(const DtwBwdArgs& a, int maxm, int maxn, int64_t max_w
                           int grid, hipStream_t s);
 size_t bwd_lds_bytes(int maxm, int maxn, int64_t max_words, int maxd);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
+// Diagonal pairs with the point costs formed ahead of the recurrence by three more waves per item
+// (uniform pairs, float, W_eff <= 63): for batches of at most kCoopMaxItems items.
+constexpr int kCoopMaxItems = 1024;
+size_t diag_coop_lds_bytes(int m, int n, int W, int D, int P);
+hipError_t launch_dtw_diag_coop(const DtwFwdArgs& a, bool save, int nitems, hipStream_t s);
 
 // ------------------------------------------------------------- index build
 struct IndexBuildArgs {
