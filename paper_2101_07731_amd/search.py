@@ -118,32 +118,54 @@ def knn_workspace_bytes(index, queries, **kw):
     return L.lib().tc_dtw_knn_workspace_bytes(C.byref(index.ix), C.byref(Q.batch), C.byref(p))
 
 
-# Bound combinations and triggering thresholds tried by tune_cascade: the
-# grids the paper evaluates (e_TI in {0.05, 0.1, 0.2}, e_PC in {0.1, 0.5}).
-CASCADE_CHOICES = (
-    ("mv", None, None),
-    ("mv+pc", 0.1, None), ("mv+pc", 0.5, None),
-    ("mv+ti", None, 0.05), ("mv+ti", None, 0.1), ("mv+ti", None, 0.2),
-    ("mv+pc+ti", 0.1, 0.1), ("mv+pc+ti", 0.5, 0.2),
-)
+def _choices():
+    """The setup-stage grid of Sec. 6 / Sec. 7.1: LB_MV alone; LB_PC with
+    Lv in {2, 3} levels and e_PC in {0.1, 0.5}; LB_TI (P = 5 with TOP) with
+    e_TI in {0.05, 0.1, 0.2}; both advanced bounds at two trigger pairs and
+    both Lv.  Each choice is a dict of tc_dtw_knn_params fields plus
+    'bounds'; the box count K (pc_clusters) is passed to tune_cascade."""
+    out = [{"bounds": "mv"}]
+    for lv in (2, 3):
+        for e in (0.1, 0.5):
+            out.append({"bounds": "mv+pc", "pc_levels": lv, "trigger_pc": e})
+    for e in (0.05, 0.1, 0.2):
+        out.append({"bounds": "mv+ti", "trigger_ti": e})
+    for lv in (2, 3):
+        for epc, eti in ((0.1, 0.1), (0.5, 0.2)):
+            out.append({"bounds": "mv+pc+ti", "pc_levels": lv, "trigger_pc": epc, "trigger_ti": eti})
+    return tuple(out)
 
 
-def tune_cascade(index, queries, reps=2, choices=CASCADE_CHOICES, **kw):
-    """Setup-stage choice of the bounds and their triggering thresholds
-    (Sec. 6: e is chosen per dataset during setup): times the search of
-    `queries` (a sample) for every choice and returns (best, {choice: ms}).
-    Every choice returns the same neighbours; only the time differs.
-    Choices the library cannot run for these shapes (LB_TI beyond W_eff 63,
-    LB_PC / LB_TI on uneven lengths) are skipped."""
+CASCADE_CHOICES = _choices()
+
+# setup-stage choices already made, by (index, query shape, window and other parameters)
+_TUNED = {}
+
+
+def choice_name(c):
+    return " ".join("%s=%s" % (k, v) for k, v in sorted(c.items()))
+
+
+def tune_cascade(index, queries, reps=2, choices=CASCADE_CHOICES, cache=True, **kw):
+    """Setup-stage choice of the bounds and their parameters (Sec. 6: the
+    triggering threshold and the bound are chosen per dataset during setup;
+    Sec. 7.1 lists the grids): times the search of `queries` (a sample) for
+    every choice and returns (best choice dict, {choice name: ms}).  Every
+    choice returns the same neighbours; only the time differs.  The result
+    is cached by the index, the query shape and the other parameters, so a
+    later call with the same key returns it without timing (pass
+    cache=False to time again); apply it with knn(index, q, **best, **kw)."""
+    Q = SeriesSet(queries)
+    key = (int(index.buf.data_ptr()), int(index.count), Q.shape, Q.count if Q.shape is None else None,
+           tuple(sorted((k, str(v)) for k, v in kw.items())), tuple(choice_name(c) for c in choices))
+    if cache and key in _TUNED:
+        return _TUNED[key]
     times = {}
-    for bounds, e_pc, e_ti in choices:
-        extra = dict(kw)
-        if e_pc is not None:
-            extra["trigger_pc"] = e_pc
-        if e_ti is not None:
-            extra["trigger_ti"] = e_ti
+    for c in choices:
+        args = dict(kw)
+        args.update(c)
         try:
-            knn(index, queries, bounds=bounds, **extra)
+            knn(index, queries, **args)
         except L.TcDtwError as err:
             if err.status == L.ERR_UNSUPPORTED:
                 continue
@@ -152,9 +174,11 @@ def tune_cascade(index, queries, reps=2, choices=CASCADE_CHOICES, **kw):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            knn(index, queries, bounds=bounds, **extra)
+            knn(index, queries, **args)
         e1.record()
         torch.cuda.synchronize()
-        times[(bounds, e_pc, e_ti)] = e0.elapsed_time(e1) / reps
-    best = min(times, key=times.get)
+        times[choice_name(c)] = e0.elapsed_time(e1) / reps
+    by_name = {choice_name(c): c for c in choices}
+    best = dict(by_name[min(times, key=times.get)])
+    _TUNED[key] = (best, times)
     return best, times

@@ -411,17 +411,20 @@ def test_lb_ti_dense_matrix_wide_band(dev, P, top, case):
 
 
 def test_tune_cascade_picks_a_runnable_choice(dev):
-    """Setup-stage choice of bounds and triggers, also with a band wider than 63."""
+    """Setup-stage choice over the paper's grids (bounds, Lv, triggers), also
+    with a band wider than 63; the choice is cached by shape and parameters."""
     from paper_2101_07731_amd import search, synth
     Q, Cs = synth.cascade_knn(nq=20, nc=400, T=96, D=8, seed=31)
     ix = search.Index(torch.from_numpy(Cs).to(dev))
     Qd = torch.from_numpy(Q).to(dev)
     best, times = search.tune_cascade(ix, Qd, reps=1, frac=(1, 10))
-    assert best in times and len(times) == len(search.CASCADE_CHOICES)
-    idx, dist = search.knn(ix, Qd, frac=(1, 10), bounds=best[0],
-                           **{k: v for k, v in (("trigger_pc", best[1]), ("trigger_ti", best[2])) if v is not None})
+    assert search.choice_name(best) in times and len(times) == len(search.CASCADE_CHOICES)
+    assert search.tune_cascade(ix, Qd, reps=1, frac=(1, 10))[0] == best      # cached
+    idx, dist = search.knn(ix, Qd, frac=(1, 10), **best)
     check_against_oracle(idx.cpu().numpy(), dist.cpu().numpy(), Q, Cs, 1, 10)
     Ql, Cl = synth.long_knn(nq=3, nc=20, T=300, D=4)
     ixl = search.Index(torch.from_numpy(Cl).to(dev))
-    _, tl = search.tune_cascade(ixl, torch.from_numpy(Ql).to(dev), reps=1, frac=(1, 2))   # W = 150
+    bl, tl = search.tune_cascade(ixl, torch.from_numpy(Ql).to(dev), reps=1, frac=(1, 2), pc_clusters=16)   # W = 150
     assert len(tl) == len(search.CASCADE_CHOICES)
+    idx, dist = search.knn(ixl, torch.from_numpy(Ql).to(dev), frac=(1, 2), pc_clusters=16, **bl)
+    check_against_oracle(idx.cpu().numpy(), dist.cpu().numpy(), Ql, Cl, 1, 2)
