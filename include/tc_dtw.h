@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define TC_DTW_ABI_VERSION 5
+#define TC_DTW_ABI_VERSION 6
 
 typedef struct ihipStream_t* tc_dtw_stream; /* same type as hipStream_t; NULL = default stream */
 
@@ -276,25 +276,36 @@ tc_dtw_status tc_dtw_backward_run(const tc_dtw_pairs_plan* plan, const float* x,
  *          caller and read by every later call that takes the index; it
  *          must stay alive and unmodified while the index is used.
  *   out    HOST: receives the index description (plain data; copy freely).
+ * Banks of several dimensions: with refs->dims given, the references may
+ * have different D, each dimension forming one contiguous run of the set
+ * (a bank; at most TC_DTW_MAX_BANKS of them).  A search then compares each
+ * query only with the bank of its own D (DTW between series of different
+ * D is undefined); the bank table is in `out`.
  * The index is immutable after the build, so searches on different streams
- * may share it.  Errors: INVALID, UNSUPPORTED, WORKSPACE (buf too small),
- * DEVICE. */
+ * may share it.  Errors: INVALID, UNSUPPORTED (a dimension in two runs,
+ * more than TC_DTW_MAX_BANKS banks), WORKSPACE (buf too small), DEVICE. */
+#define TC_DTW_MAX_BANKS 8
+
 typedef struct {
     void* buf;
     size_t bytes;
     int32_t count;        /* number of candidate series */
-    int32_t dim;
+    int32_t dim;          /* D of every candidate; with banks, the largest D */
     int32_t uniform_len;  /* > 0 when every candidate has this length, else 0 */
     int32_t max_len;
     int32_t ntiles;       /* 64-candidate tiles of the element-major copy (uniform only) */
-    int32_t reserved0;
+    int32_t nbanks;       /* 0: one D for all candidates; else the bank table below */
     int64_t off_series;   /* byte offsets of the sections inside buf */
     int64_t off_tiles;
     int64_t off_gamma;
     int64_t off_meta;     /* int64 offsets[count], then int32 lengths[count] */
     int64_t off_range;    /* float[2]: smallest and largest value */
     int64_t total_len;    /* sum of the candidate lengths */
-    int64_t reserved[3];
+    int64_t off_dims;     /* banks: int32 dims[count] */
+    int64_t reserved[2];
+    int32_t bank_dim[TC_DTW_MAX_BANKS];    /* D of bank b */
+    int32_t bank_first[TC_DTW_MAX_BANKS];  /* its first candidate */
+    int32_t bank_count[TC_DTW_MAX_BANKS];  /* its number of candidates */
 } tc_dtw_index;
 
 size_t tc_dtw_index_bytes(const tc_dtw_batch* refs);
@@ -336,6 +347,12 @@ typedef struct {
                                query's points when the query arrives (Sec. 5).  Otherwise LB_PC, in
                                tc_dtw_knn and tc_dtw_lower_bounds, uses these boxes of the candidates'
                                points, built ahead of time (Sec. 8; see tc_dtw_build_cand_boxes) */
+    int32_t reuse_query_meta; /* searches of queries of uneven lengths or dims copy per-query
+                               metadata (offsets, lengths, dims, table offsets) from host memory
+                               into the workspace.  1: the workspace already holds that metadata
+                               from a previous call with the same queries shapes, params and index,
+                               so the call enqueues kernels only (and may be captured in a HIP
+                               graph); 0: copy it (default). */
 } tc_dtw_knn_params;
 
 void tc_dtw_knn_params_default(tc_dtw_knn_params* p);
@@ -401,13 +418,19 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
  * the k-th smallest distance with rigorous float32 error bounds, and every
  * candidate whose float32 DTW lies within those bounds of the k-th smallest
  * is re-scored in float64.
+ * With an index of several banks (see tc_dtw_build_index) the queries may
+ * have different D (queries->dims): each is searched against the bank of
+ * its D in the same launches (every stage is one launch over all queries,
+ * the work items of all banks mixed); nn_idx is the index in the whole
+ * reference set; pairs counts query-bank pairs only.  (LB_MV bounds; k = 1.)
  *   nn_idx   DEVICE int32[queries->count * k], row-major by query
  *   nn_dist  DEVICE float[queries->count * k] (float64 DTW rounded to float32)
  *   stats    HOST or NULL.  When given, the call waits for the stream and
  *            fills the counters and per-stage times.
- * Errors: INVALID (dims differ, k < 1 or k > candidates, bad parameters),
- * UNSUPPORTED (k > 32; k > 1 with uneven lengths; independent DTW outside
- * its limits or with LB_PC / LB_TI), WORKSPACE, DEVICE. */
+ * Errors: INVALID (dims differ, a query D with no bank, k < 1 or k >
+ * candidates, bad parameters), UNSUPPORTED (k > 32; k > 1 with uneven
+ * lengths or banks; independent DTW outside its limits or with LB_PC /
+ * LB_TI), WORKSPACE, DEVICE. */
 typedef struct {
     uint64_t pairs;          /* query-candidate pairs */
     uint64_t pruned_mv;      /* pairs skipped by LB_MV */

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcdtw.so")
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
 F64 = 1
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class TcDtwError(RuntimeError):
@@ -53,12 +53,17 @@ class Window(C.Structure):
     _fields_ = [("window", C.c_int32), ("frac_num", C.c_int32), ("frac_den", C.c_int32)]
 
 
+MAX_BANKS = 8
+
+
 class Index(C.Structure):
     _fields_ = [("buf", C.c_void_p), ("bytes", C.c_size_t), ("count", C.c_int32), ("dim", C.c_int32),
                 ("uniform_len", C.c_int32), ("max_len", C.c_int32), ("ntiles", C.c_int32),
-                ("reserved0", C.c_int32), ("off_series", C.c_int64), ("off_tiles", C.c_int64),
+                ("nbanks", C.c_int32), ("off_series", C.c_int64), ("off_tiles", C.c_int64),
                 ("off_gamma", C.c_int64), ("off_meta", C.c_int64), ("off_range", C.c_int64),
-                ("total_len", C.c_int64), ("reserved", C.c_int64 * 3)]
+                ("total_len", C.c_int64), ("off_dims", C.c_int64), ("reserved", C.c_int64 * 2),
+                ("bank_dim", C.c_int32 * MAX_BANKS), ("bank_first", C.c_int32 * MAX_BANKS),
+                ("bank_count", C.c_int32 * MAX_BANKS)]
 
 
 class CandBoxes(C.Structure):
@@ -73,7 +78,7 @@ class KnnParams(C.Structure):
                 ("pc_clusters", C.c_int32), ("pc_group", C.c_int32), ("pc_min_cell", C.c_float),
                 ("trigger_ti", C.c_float), ("trigger_pc", C.c_float), ("prune_margin", C.c_float),
                 ("seed_r", C.c_int32), ("k", C.c_int32), ("independent", C.c_int32),
-                ("pc_cand", C.POINTER(CandBoxes))]
+                ("pc_cand", C.POINTER(CandBoxes)), ("reuse_query_meta", C.c_int32)]
 
 
 class KnnStats(C.Structure):

@@ -14,7 +14,7 @@ struct IndexLayout {
     bool uniform;
     int count, dim, ulen, maxlen, ntiles;
     int64_t total_len;
-    size_t off_series, off_tiles, off_gamma, off_meta, off_range, bytes;
+    size_t off_series, off_tiles, off_gamma, off_meta, off_range, off_dims, bytes;
 };
 
 static IndexLayout index_layout(const HostSet& R) {
@@ -25,17 +25,45 @@ static IndexLayout index_layout(const HostSet& R) {
     L.ulen = R.uniform ? R.ulen : 0;
     L.maxlen = R.maxlen;
     L.total_len = 0;
-    for (int s = 0; s < R.count; ++s) L.total_len += R.length(s);
+    int64_t elems = 0;
+    for (int s = 0; s < R.count; ++s) {
+        L.total_len += R.length(s);
+        elems += (int64_t)R.length(s) * R.dimension(s);
+    }
     L.ntiles = R.uniform ? (R.count + 63) / 64 : 0;
     Carve c(nullptr, 0);
     auto at = [&](size_t bytes) { c.used = (c.used + 255) & ~(size_t)255; size_t o = c.used; c.used += bytes; return o; };
-    L.off_series = at((size_t)L.total_len * R.dim * 4);
+    L.off_series = at((size_t)elems * 4);
     L.off_tiles = at(R.uniform ? (size_t)L.ntiles * (((size_t)R.ulen * R.dim + 3) / 4 * 4) * 64 * 4 : 0);
     L.off_gamma = at((size_t)L.total_len * 4);
     L.off_meta = at((size_t)R.count * (8 + 8 + 4 + 8) + 8);
     L.off_range = at(8);
+    L.off_dims = at(R.mixed ? (size_t)R.count * 4 : 0);
     L.bytes = c.need();
     return L;
+}
+
+// Banks of an index with per-series dims: maximal runs of equal D, each D in one run.
+static tc_dtw_status index_banks(const HostSet& R, tc_dtw_index& out) {
+    out.nbanks = 0;
+    if (!R.mixed) return TC_DTW_OK;
+    int s = 0;
+    while (s < R.count) {
+        const int D = R.dimension(s);
+        int e = s;
+        while (e < R.count && R.dimension(e) == D) ++e;
+        for (int b = 0; b < out.nbanks; ++b)
+            if (out.bank_dim[b] == D)
+                return fail(TC_DTW_ERR_UNSUPPORTED, "references of one dimension must form one contiguous run");
+        if (out.nbanks == TC_DTW_MAX_BANKS)
+            return fail(TC_DTW_ERR_UNSUPPORTED, "an index holds at most TC_DTW_MAX_BANKS banks");
+        out.bank_dim[out.nbanks] = D;
+        out.bank_first[out.nbanks] = s;
+        out.bank_count[out.nbanks] = e - s;
+        ++out.nbanks;
+        s = e;
+    }
+    return TC_DTW_OK;
 }
 
 static tc_dtw_status check_index(const tc_dtw_index* ix) {
@@ -51,6 +79,8 @@ static tc_dtw_status check_params(const tc_dtw_knn_params* p) {
     if (p->k < 1) return fail(TC_DTW_ERR_INVALID, "k must be >= 1");
     if (p->k > kMaxK) return fail(TC_DTW_ERR_UNSUPPORTED, "k is limited to 32");
     if (p->independent != 0 && p->independent != 1) return fail(TC_DTW_ERR_INVALID, "independent must be 0 or 1");
+    if (p->reuse_query_meta != 0 && p->reuse_query_meta != 1)
+        return fail(TC_DTW_ERR_INVALID, "reuse_query_meta must be 0 or 1");
     if (p->independent && (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI)))
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI bound the dependent DTW only (independent DTW: LB_MV)");
     if (p->bounds & ~(TC_DTW_LB_MV | TC_DTW_LB_PC | TC_DTW_LB_TI))
@@ -328,17 +358,20 @@ static KnnDtwArgs list_args(const KnnPlan& K, const KnnPlanDev& d, bool seeds, b
 struct RaggedPlan {
     int nq = 0, nc = 0, D = 0, R = 0, maxm = 0, maxn = 0;
     bool plain = false, abandon = true;
+    bool banks = false;         // the index holds banks of several D
+    uint64_t pairs = 0;         // query-candidate pairs (query-bank pairs with banks)
     tc_dtw_window win{};
     std::vector<int64_t> q_off, t_off;
-    std::vector<int32_t> q_len;
+    std::vector<int32_t> q_len, q_dim, q_cb, q_ce;   // with banks: D and candidate range of each query
     int64_t tab_floats = 0;
     size_t o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_gcnt, o_prefix, o_items, o_counters,
-        o_key, o_stats, o_qoff, o_qlen, o_toff, o_tab, bytes;
+        o_key, o_stats, o_qoff, o_qlen, o_toff, o_tab, o_qdim, o_qcb, o_qce, bytes;
 };
 
 static bool is_ragged_search(const tc_dtw_index* ix, const tc_dtw_batch* qb) {
     if (!ix || !qb) return false;
-    return ix->uniform_len <= 0 || qb->len != nullptr || qb->offset != nullptr;
+    return ix->uniform_len <= 0 || ix->nbanks > 0 || qb->len != nullptr || qb->offset != nullptr ||
+           qb->dims != nullptr;
 }
 
 static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch* qb, const tc_dtw_knn_params* p,
@@ -346,9 +379,10 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     tc_dtw_status st;
     if ((st = check_index(ix)) != TC_DTW_OK) return st;
     if ((st = read_set(qb, "queries", Qs)) != TC_DTW_OK) return st;
-    if (Qs.mixed) return fail(TC_DTW_ERR_UNSUPPORTED, "a search needs one dim for all queries (dims must be NULL)");
+    if (Qs.mixed && ix->nbanks == 0)
+        return fail(TC_DTW_ERR_UNSUPPORTED, "queries of several dims need an index of several banks");
     if ((st = check_params(p)) != TC_DTW_OK) return st;
-    if (Qs.dim != ix->dim) return fail(TC_DTW_ERR_INVALID, "queries and index have different dims");
+    if (ix->nbanks == 0 && Qs.dim != ix->dim) return fail(TC_DTW_ERR_INVALID, "queries and index have different dims");
     if (p->bounds & (TC_DTW_LB_PC | TC_DTW_LB_TI))
         return fail(TC_DTW_ERR_UNSUPPORTED, "LB_PC and LB_TI need uniform query and candidate lengths");
     if (p->k > 1) return fail(TC_DTW_ERR_UNSUPPORTED, "k > 1 needs uniform query and candidate lengths");
@@ -356,7 +390,25 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     K = RaggedPlan();
     K.nq = Qs.count;
     K.nc = ix->count;
-    K.D = Qs.dim;
+    K.D = std::max(Qs.dim, ix->dim);   // the largest D sizes the LDS and the kernels' chunk count
+    K.banks = ix->nbanks > 0;
+    if (K.banks) {
+        K.q_dim.resize(K.nq);
+        K.q_cb.resize(K.nq);
+        K.q_ce.resize(K.nq);
+        for (int q = 0; q < K.nq; ++q) {
+            const int D = Qs.dimension(q);
+            int b = 0;
+            while (b < ix->nbanks && ix->bank_dim[b] != D) ++b;
+            if (b == ix->nbanks) return fail(TC_DTW_ERR_INVALID, "a query's dim has no bank in the index");
+            K.q_dim[q] = D;
+            K.q_cb[q] = ix->bank_first[b];
+            K.q_ce[q] = ix->bank_first[b] + ix->bank_count[b];
+            K.pairs += (uint64_t)ix->bank_count[b];
+        }
+    } else {
+        K.pairs = (uint64_t)K.nq * K.nc;
+    }
     K.win = p->window;
     K.plain = (p->bounds & TC_DTW_LB_MV) == 0;
     K.abandon = p->early_abandon != 0;
@@ -373,7 +425,7 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
         K.t_off[q] = K.tab_floats;
         int L = 0;
         while ((1 << L) <= m) ++L;   // floor(log2 m) + 1
-        K.tab_floats += 2LL * L * m * K.D;
+        K.tab_floats += 2LL * L * m * Qs.dimension(q);
     }
     const size_t lim = 163840;
     if (rknn_final_lds_bytes(K.maxn, K.D) > lim)
@@ -397,8 +449,40 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     K.o_qlen = at((size_t)K.nq * 4);
     K.o_toff = at((size_t)K.nq * 8);
     K.o_tab = at(K.plain ? 0 : (size_t)K.tab_floats * 4);
+    K.o_qdim = at(K.banks ? (size_t)K.nq * 4 : 0);
+    K.o_qcb = at(K.banks ? (size_t)K.nq * 4 : 0);
+    K.o_qce = at(K.banks ? (size_t)K.nq * 4 : 0);
     K.bytes = c.need();
     return TC_DTW_OK;
+}
+
+// Uploads the per-query metadata of a ragged search and points `r` at it.
+// With `copy` false the workspace already holds the metadata (params.reuse_query_meta).
+static hipError_t ragged_upload(const RaggedPlan& K, char* w, RaggedKnnArgs& r, hipStream_t s, bool copy = true) {
+    hipError_t e;
+    // pageable host memory: the copies are staged before the calls return
+    if (copy &&
+        ((e = hipMemcpyAsync(w + K.o_qoff, K.q_off.data(), K.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+         (e = hipMemcpyAsync(w + K.o_qlen, K.q_len.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+         (e = hipMemcpyAsync(w + K.o_toff, K.t_off.data(), K.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess))
+        return e;
+    r.q_off = reinterpret_cast<const int64_t*>(w + K.o_qoff);
+    r.q_len = reinterpret_cast<const int32_t*>(w + K.o_qlen);
+    r.t_off = reinterpret_cast<const int64_t*>(w + K.o_toff);
+    r.q_dim = r.q_cb = r.q_ce = nullptr;
+    if (K.banks) {
+        if (copy &&
+            ((e = hipMemcpyAsync(w + K.o_qdim, K.q_dim.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+             (e = hipMemcpyAsync(w + K.o_qcb, K.q_cb.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+             (e = hipMemcpyAsync(w + K.o_qce, K.q_ce.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess))
+            return e;
+        r.q_dim = reinterpret_cast<const int32_t*>(w + K.o_qdim);
+        r.q_cb = reinterpret_cast<const int32_t*>(w + K.o_qcb);
+        r.q_ce = reinterpret_cast<const int32_t*>(w + K.o_qce);
+        r.bank_max = 0;
+        for (int q = 0; q < K.nq; ++q) r.bank_max = std::max(r.bank_max, K.q_ce[q] - K.q_cb[q]);
+    }
+    return hipSuccess;
 }
 
 static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* queries, const tc_dtw_knn_params* p,
@@ -437,15 +521,12 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
     RaggedKnnArgs r;
     std::memset(&r, 0, sizeof r);
     r.Q = d.Q;
-    r.q_off = reinterpret_cast<const int64_t*>(w + K.o_qoff);
-    r.q_len = reinterpret_cast<const int32_t*>(w + K.o_qlen);
     r.C = d.C;
     r.c_off = c_off;
     r.c_len = c_len;
     r.nq = K.nq; r.nc = K.nc; r.D = K.D; r.maxm = K.maxm; r.maxn = K.maxn;
     r.window = K.win.window; r.num = K.win.frac_num; r.den = K.win.frac_den;
     r.tab = K.plain ? nullptr : reinterpret_cast<float*>(w + K.o_tab);
-    r.t_off = reinterpret_cast<const int64_t*>(w + K.o_toff);
     r.lb = d.lb;
     r.prefix = d.prefix; r.item_query = d.item_query; r.counter = d.counters + 1;
     r.key = d.key; r.stats = d.stats;
@@ -459,11 +540,10 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
         for (auto& x : ev) (void)hipEventCreate(&x);
     auto mark = [&](int i) { if (timed) (void)hipEventRecord(ev[i], s); };
     hipError_t e;
-    // per-query metadata (pageable host memory: the copies are staged before the calls return)
-    if ((e = hipMemcpyAsync(w + K.o_qoff, K.q_off.data(), K.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(w + K.o_qlen, K.q_len.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(w + K.o_toff, K.t_off.data(), K.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+    if ((e = ragged_upload(K, w, r, s, p->reuse_query_meta == 0)) != hipSuccess)
         return hip_fail(e, "query metadata upload");
+    d.q_cb = r.q_cb;
+    d.q_ce = r.q_ce;
     mark(0);
     if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
     if (!K.plain && (e = launch_rq_tables(r, s)) != hipSuccess) return hip_fail(e, "query tables");
@@ -517,7 +597,7 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "stats readback");
         std::memset(stats, 0, sizeof *stats);
-        stats->pairs = (uint64_t)K.nq * K.nc;
+        stats->pairs = K.pairs;
         stats->pruned_mv = h[kStPrunedMv];
         stats->dtw_started = h[kStDtwStarted];
         stats->dtw_abandoned = h[kStDtwAbandoned];
@@ -566,7 +646,9 @@ void tc_dtw_knn_params_default(tc_dtw_knn_params* p) {
 
 size_t tc_dtw_index_bytes(const tc_dtw_batch* refs) {
     HostSet R;
-    if (read_set(refs, "refs", R) != TC_DTW_OK || R.mixed) return 0;
+    if (read_set(refs, "refs", R) != TC_DTW_OK) return 0;
+    tc_dtw_index tmp;
+    if (index_banks(R, tmp) != TC_DTW_OK) return 0;
     return index_layout(R).bytes;
 }
 
@@ -575,8 +657,10 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
     HostSet R;
     tc_dtw_status st = read_set(refs, "refs", R);
     if (st != TC_DTW_OK) return st;
-    if (R.mixed) return fail(TC_DTW_ERR_UNSUPPORTED, "an index needs one dim for all references (dims must be NULL)");
     if (!buf || !out) return fail(TC_DTW_ERR_INVALID, "null index buffer or output");
+    tc_dtw_index banks;
+    std::memset(&banks, 0, sizeof banks);
+    if ((st = index_banks(R, banks)) != TC_DTW_OK) return st;
     const IndexLayout L = index_layout(R);
     if (bytes < L.bytes) return fail(TC_DTW_ERR_WORKSPACE, "index buffer smaller than tc_dtw_index_bytes()");
     if ((st = check_device()) != TC_DTW_OK) return st;
@@ -609,7 +693,7 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
         h_src[k] = R.offset(k);
         h_dst[k] = next;
         h_gam[k] = gnext;
-        next += (int64_t)h_len[k] * R.dim;
+        next += (int64_t)h_len[k] * R.dimension(k);
         gnext += h_len[k];
     }
     hipError_t e;
@@ -618,6 +702,12 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
         (e = hipMemcpyAsync(lens, h_len.data(), R.count * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(src_off, h_src.data(), R.count * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "index metadata upload");
+    if (R.mixed) {
+        int32_t* dims = reinterpret_cast<int32_t*>(base + L.off_dims);
+        if ((e = hipMemcpyAsync(dims, R.dims.data(), R.count * 4, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "index metadata upload");
+        a.dims = dims;
+    }
     a.dst_off = dst_off;
     a.gamma_off = gam_off;
     a.lens = lens;
@@ -637,6 +727,13 @@ tc_dtw_status tc_dtw_build_index(const tc_dtw_batch* refs, void* buf, size_t byt
     out->off_meta = (int64_t)L.off_meta;
     out->off_range = (int64_t)L.off_range;
     out->total_len = L.total_len;
+    out->off_dims = R.mixed ? (int64_t)L.off_dims : 0;
+    out->nbanks = banks.nbanks;
+    for (int b = 0; b < banks.nbanks; ++b) {
+        out->bank_dim[b] = banks.bank_dim[b];
+        out->bank_first[b] = banks.bank_first[b];
+        out->bank_count[b] = banks.bank_count[b];
+    }
     return ok();
 }
 
@@ -922,22 +1019,19 @@ tc_dtw_status tc_dtw_lower_bounds(const tc_dtw_index* ix, const tc_dtw_batch* qu
         RaggedKnnArgs a;
         std::memset(&a, 0, sizeof a);
         a.Q = Qr.data;
-        a.q_off = reinterpret_cast<const int64_t*>(w + R.o_qoff);
-        a.q_len = reinterpret_cast<const int32_t*>(w + R.o_qlen);
         a.C = reinterpret_cast<const float*>(base + ix->off_series);
         a.c_off = reinterpret_cast<const int64_t*>(base + ix->off_meta);
         a.c_len = reinterpret_cast<const int32_t*>(a.c_off + 2 * (int64_t)ix->count);
         a.nq = R.nq; a.nc = R.nc; a.D = R.D; a.maxm = R.maxm; a.maxn = R.maxn;
         a.window = R.win.window; a.num = R.win.frac_num; a.den = R.win.frac_den;
         a.tab = reinterpret_cast<float*>(w + R.o_tab);
-        a.t_off = reinterpret_cast<const int64_t*>(w + R.o_toff);
         a.lb = lb;
         a.status = status_word();
         hipError_t e;
-        if ((e = hipMemcpyAsync(w + R.o_qoff, R.q_off.data(), R.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(w + R.o_qlen, R.q_len.data(), R.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(w + R.o_toff, R.t_off.data(), R.nq * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
-            return hip_fail(e, "query metadata upload");
+        if ((e = ragged_upload(R, w, a, s)) != hipSuccess) return hip_fail(e, "query metadata upload");
+        // with banks, a query's bound is computed for its own bank only: +inf elsewhere
+        if (R.banks && (e = launch_fill_f32(lb, (int64_t)R.nq * R.nc, __builtin_inff(), s)) != hipSuccess)
+            return hip_fail(e, "bound fill");
         if ((e = launch_rq_tables(a, s)) != hipSuccess) return hip_fail(e, "query tables");
         if ((e = launch_rlb_mv(a, s)) != hipSuccess) return hip_fail(e, "lb_mv");
         return ok();

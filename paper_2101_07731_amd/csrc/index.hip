@@ -25,8 +25,8 @@ __global__ void k_range_init(uint32_t* rk) {
 // series offsets) into `series` (concatenated, same order) and reduces the
 // value range into rk[0] (min key) / rk[1] (max key).
 __global__ void k_index_series(const float* src, const int64_t* src_off, const int64_t* dst_off,
-                               const int32_t* lens, int count, int ulen, int D, int64_t total,
-                               float* series, uint32_t* rk) {
+                               const int32_t* lens, const int32_t* dims, int count, int ulen, int D,
+                               int64_t total, float* series, uint32_t* rk) {
     __shared__ uint32_t smin, smax;
     if (threadIdx.x == 0) { smin = 0xffffffffu; smax = 0u; }
     __syncthreads();
@@ -44,7 +44,7 @@ __global__ void k_index_series(const float* src, const int64_t* src_off, const i
     } else {
         // one block-stride loop per series (ragged)
         for (int s = blockIdx.x; s < count; s += gridDim.x) {
-            const int64_t n = (int64_t)lens[s] * D;
+            const int64_t n = (int64_t)lens[s] * (dims ? dims[s] : D);
             const float* a = src + src_off[s];
             float* b = series + dst_off[s];
             for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
@@ -89,9 +89,11 @@ __global__ void k_index_tiles(const float* series, int count, int E, int ntiles,
 // Candidate neighbour distances gamma_j = e(c_{j-1}, c_j), gamma_0 = 0 (Sec. 4.1,
 // triangle at the top of a window).  One thread per point.
 __global__ void k_index_gamma(const float* series, const int64_t* dst_off, const int32_t* lens,
-                              int count, int ulen, int D, const int64_t* goff, float* gamma) {
+                              const int32_t* dims, int count, int ulen, int Dall, const int64_t* goff,
+                              float* gamma) {
     for (int s = blockIdx.y; s < count; s += gridDim.y) {
         const int L = ulen > 0 ? ulen : lens[s];
+        const int D = dims ? dims[s] : Dall;
         const float* a = series + (ulen > 0 ? (int64_t)s * ulen * D : dst_off[s]);
         float* g = gamma + (ulen > 0 ? (int64_t)s * ulen : goff[s]);
         for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < L; j += gridDim.x * blockDim.x) {
@@ -120,7 +122,7 @@ __global__ void k_range_finish(uint32_t* rk, uint32_t* status) {
 
 hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_range_init, dim3(1), dim3(64), 0, s, a.range_keys);
-    hipLaunchKernelGGL(k_index_series, dim3(1024), dim3(256), 0, s, a.src, a.src_off, a.dst_off, a.lens,
+    hipLaunchKernelGGL(k_index_series, dim3(1024), dim3(256), 0, s, a.src, a.src_off, a.dst_off, a.lens, a.dims,
                        a.count, a.ulen, a.D, a.total_len, a.series, a.range_keys);
     if (a.ulen > 0 && a.tiles) {
         hipLaunchKernelGGL(k_index_tiles, dim3(2048), dim3(256), 0, s, a.series, a.count, a.ulen * a.D,
@@ -128,7 +130,7 @@ hipError_t launch_index_build(const IndexBuildArgs& a, hipStream_t s) {
     }
     const int gy = a.count < 65535 ? a.count : 65535;
     const int gx = (a.maxlen + 255) / 256;
-    hipLaunchKernelGGL(k_index_gamma, dim3(gx, gy), dim3(256), 0, s, a.series, a.dst_off, a.lens,
+    hipLaunchKernelGGL(k_index_gamma, dim3(gx, gy), dim3(256), 0, s, a.series, a.dst_off, a.lens, a.dims,
                        a.count, a.ulen, a.D, a.gamma_off, a.gamma);
     hipLaunchKernelGGL(k_range_finish, dim3(1), dim3(64), 0, s, a.range_keys, a.status);
     return hipGetLastError();

@@ -119,6 +119,7 @@ struct IndexBuildArgs {
     const int64_t* dst_off;   // ragged: offsets inside `series`
     const int32_t* lens;      // ragged: lengths
     const int64_t* gamma_off; // ragged: offsets inside `gamma`
+    const int32_t* dims;      // per-series D (banks of several dims), or null: D for every series
     int32_t count, ulen, D, maxlen, ntiles;
     int64_t total_len;
     float* series;
@@ -170,6 +171,8 @@ struct KnnPlanDev {
     unsigned long long* topk;   // [nq][k] keys of the k best candidates so far (k > 1), else null
     int32_t k;
     uint32_t* status;     // device status word (or null)
+    const int32_t* q_cb;  // banks of several dims: [nq] candidate range of each query, else null
+    const int32_t* q_ce;
 };
 // Element segments of the LB_MV launch (more when few query tiles would leave HBM idle).
 int lb_mv_segments(int ntiles, int nq, int E);
@@ -226,10 +229,14 @@ struct RaggedKnnArgs {
     const float* Q;
     const int64_t* q_off;      // [nq] float offsets of the queries
     const int32_t* q_len;      // [nq]
+    const int32_t* q_dim;      // [nq] D of each query (banks of several D), or null: D for all
+    const int32_t* q_cb;       // [nq] first candidate of the query's bank (with q_dim)
+    const int32_t* q_ce;       // [nq] one past its last candidate
+    int32_t bank_max;          // the largest bank (with q_dim)
     const float* C;            // index series
     const int64_t* c_off;      // [nc] float offsets inside the index series
     const int32_t* c_len;      // [nc]
-    int32_t nq, nc, D, maxm, maxn;
+    int32_t nq, nc, D, maxm, maxn;  // D: the largest D (with banks)
     int32_t window, num, den;  // window specification (per pair W_eff)
     float* tab;                // query sparse tables
     const int64_t* t_off;      // [nq] float offsets of each query's tables
@@ -253,6 +260,8 @@ struct RaggedKnnArgs {
     uint32_t* status;          // device status word (or null)
 };
 hipError_t launch_rq_tables(const RaggedKnnArgs& a, hipStream_t s);
+// p[0 .. n) = v
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_rlb_mv(const RaggedKnnArgs& a, hipStream_t s);
 hipError_t launch_rknn_dtw(const RaggedKnnArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_rknn_finalize(const RaggedKnnArgs& a, hipStream_t s);
@@ -366,9 +375,9 @@ hipError_t launch_list_items(const int32_t* cnt, int cnt_uniform, int nq, int pe
                              int32_t* item_query, int32_t* counter, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s);
 
-inline int nchunks(int D) { return (D + 3) / 4; }
+__host__ __device__ inline int nchunks(int D) { return (D + 3) / 4; }
 // Supported chunk counts (template instantiations); D is padded up to one of them.
-inline int nch_pad(int D) {
+__host__ __device__ inline int nch_pad(int D) {
     int c = nchunks(D);
     if (c <= 4) return c;
     if (c <= 6) return 6;

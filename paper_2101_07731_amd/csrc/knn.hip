@@ -203,6 +203,7 @@ __global__ __launch_bounds__(256) void k_lb_sum(const float* __restrict__ part, 
 // per query; ties between equal bounds in any order).
 template <int RMAX>
 __global__ __launch_bounds__(64) void k_topr(const float* __restrict__ lb, int nc, int R,
+                                             const int32_t* __restrict__ q_cb, const int32_t* __restrict__ q_ce,
                                              int32_t* __restrict__ seeds) {
     const int q = blockIdx.x, lane = threadIdx.x;
     float v[RMAX];
@@ -222,15 +223,17 @@ __global__ __launch_bounds__(64) void k_topr(const float* __restrict__ lb, int n
             }
         }
     };
-    int r = lane;
-    for (; r + 3 * kWave < nc; r += 4 * kWave) {   // four loads in flight per lane
+    // with banks of several dims only the query's bank [cb, ce) holds candidates
+    const int cb = q_cb ? q_cb[q] : 0, ce = q_cb ? q_ce[q] : nc;
+    int r = cb + lane;
+    for (; r + 3 * kWave < ce; r += 4 * kWave) {   // four loads in flight per lane
         float x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) x[u] = row[r + u * kWave];
 #pragma unroll
         for (int u = 0; u < 4; ++u) insert(x[u], r + u * kWave);
     }
-    for (; r < nc; r += kWave) insert(row[r], r);
+    for (; r < ce; r += kWave) insert(row[r], r);
     for (int k = 0; k < R; ++k) {
         float bv = v[0];
         int bi = id[0];
@@ -262,6 +265,7 @@ constexpr int kCompactRounds = 4;
 constexpr int kCompactPer = 256 * kCompactRounds;
 
 __global__ __launch_bounds__(256) void k_compact(const float* __restrict__ lb, int nc,
+                                                 const int32_t* __restrict__ q_cb, const int32_t* __restrict__ q_ce,
                                                  const int32_t* __restrict__ seeds, int R,
                                                  const unsigned long long* __restrict__ key,
                                                  double keep, double gate_e2, int use_gate,
@@ -280,7 +284,8 @@ __global__ __launch_bounds__(256) void k_compact(const float* __restrict__ lb, i
 #pragma unroll
     for (int it = 0; it < kCompactRounds; ++it) {
         const int r = blockIdx.x * kCompactPer + it * 256 + threadIdx.x;
-        const bool valid = r < nc;
+        // with banks of several dims only the query's own bank holds candidates
+        const bool valid = r < nc && (!q_cb || (r >= q_cb[q] && r < q_ce[q]));
         bool seed = false;
         for (int k = 0; k < R; ++k) seed |= (seeds[(int64_t)q * R + k] == r);
         const double v = (valid && lb) ? (double)lb[(int64_t)q * nc + r] : 0.0;
@@ -928,15 +933,17 @@ hipError_t launch_lb_mv(const KnnPlanDev& p, float* lb, hipStream_t s) {
 }
 
 hipError_t launch_topr(const KnnPlanDev& p, hipStream_t s) {
-    if (p.R <= 8) hipLaunchKernelGGL(k_topr<8>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.seeds);
-    else hipLaunchKernelGGL(k_topr<kMaxSeeds>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.seeds);
+    if (p.R <= 8)
+        hipLaunchKernelGGL(k_topr<8>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.q_cb, p.q_ce, p.seeds);
+    else
+        hipLaunchKernelGGL(k_topr<kMaxSeeds>, dim3(p.nq), dim3(64), 0, s, p.lb, p.nc, p.R, p.q_cb, p.q_ce, p.seeds);
     return hipGetLastError();
 }
 
 hipError_t launch_compact(const KnnPlanDev& p, double keep, double gate_e2, int use_gate, hipStream_t s) {
     dim3 grid((p.nc + kCompactPer - 1) / kCompactPer, p.nq);
-    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, p.lb, p.nc, p.seeds, p.R, p.key, keep, gate_e2,
-                       use_gate, p.list, p.cnt, p.glist, p.gcnt, p.cap, p.stats);
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, p.lb, p.nc, p.q_cb, p.q_ce, p.seeds, p.R, p.key, keep,
+                       gate_e2, use_gate, p.list, p.cnt, p.glist, p.gcnt, p.cap, p.stats);
     return hipGetLastError();
 }
 

@@ -16,6 +16,11 @@
 //    best-so-far keys work as in the uniform search.
 //  * The float64 re-scoring bounds each pair's relative float32 error by
 //    the largest of the query's pairs.
+//  * Banks of several dimensions (q_dim set): each query is compared with
+//    the candidates of its own D only, a contiguous range [q_cb, q_ce) of
+//    the index; bounds outside it are +inf (never seeds, always pruned), and
+//    the DTW and re-scoring kernels, instantiated for the largest D, run
+//    each item with the chunk count of its own D.
 #include <algorithm>
 
 #include "dtw_core.h"
@@ -66,7 +71,7 @@ __device__ __forceinline__ float dp_gamma_dev(int m, int n, int nch) {
 // query: max levels [L][m][D], then min levels [L][m][D].
 __global__ __launch_bounds__(256) void k_rq_tables(RaggedKnnArgs a) {
     const int q = blockIdx.x;
-    const int m = a.q_len[q], D = a.D;
+    const int m = a.q_len[q], D = a.q_dim ? a.q_dim[q] : a.D;
     const int L = levels_of(m);
     const int64_t md = (int64_t)m * D;
     const float* src = a.Q + a.q_off[q];
@@ -114,9 +119,10 @@ template <int NCH, bool VEC>
 __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
     const int q = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= a.nc) return;   // whole waves
-    const int m = a.q_len[q], n = a.c_len[c], D = a.D;
+    // with banks of several dims the grid covers the largest bank and each query its own
+    const int c = (a.q_dim ? a.q_cb[q] : 0) + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= (a.q_dim ? a.q_ce[q] : a.nc)) return;   // whole waves
+    const int m = a.q_len[q], n = a.c_len[c], D = a.q_dim ? a.q_dim[q] : a.D;
     const int W = weff_dev(m, n, a.window, a.num, a.den);
     const int L = levels_of(m);
     const int64_t md = (int64_t)m * D;
@@ -124,6 +130,7 @@ __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
     const float* mn = mx + (int64_t)L * md;
     const float* cs = a.C + a.c_off[c];
     const int D4 = D >> 2;
+    const bool vec = VEC && (D & 3) == 0;   // with banks of several D, decided per query
     float acc = 0.0f;
     for (int j = lane; j < n; j += kWave) {
         const int lo = max(0, j - W), hi = min(m - 1, j + W);
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
         const int h2 = hi - (1 << k) + 1;
         const float* xk = mx + k * md;
         const float* nk = mn + k * md;
-        if (VEC) {
+        if (vec) {
             float4 x1[NCH], x2[NCH], n1[NCH], n2[NCH], cv[NCH];
 #pragma unroll
             for (int t = 0; t < NCH; ++t) {
@@ -175,6 +182,25 @@ __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
 }
 
 // ----------------------------------------------------------------- DTW
+// The DP of one item with K chunks of 4 dimensions (K <= the kernel's NCH).
+template <int K>
+__device__ __forceinline__ float rknn_pair(const RaggedKnnArgs& a, int q, int ref, int m, int n, int W, int D,
+                                           int lane, const Abandon& ab, bool& aband, int& blocks) {
+    if (a.abandon)
+        return rows_core<float, K, false, true>(0, a.Q + a.q_off[q], a.C + a.c_off[ref], m, n, W, D, lane,
+                                                nullptr, ab, aband, &blocks);
+    return rows_core<float, K, false, false>(0, a.Q + a.q_off[q], a.C + a.c_off[ref], m, n, W, D, lane,
+                                             nullptr, ab, aband, &blocks);
+}
+
+template <int K, int NCH>
+__device__ __forceinline__ void rknn_pair_if(int nch, float& v, const RaggedKnnArgs& a, int q, int ref, int m,
+                                             int n, int W, int D, int lane, const Abandon& ab, bool& aband,
+                                             int& blocks) {
+    if constexpr (K <= NCH)
+        if (nch == K) v = rknn_pair<K>(a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+}
+
 // Persistent one-wave blocks over the list items (one pair per item).
 template <int NCH>
 __global__ __launch_bounds__(64) void k_rknn_dtw(RaggedKnnArgs a) {
@@ -194,19 +220,26 @@ __global__ __launch_bounds__(64) void k_rknn_dtw(RaggedKnnArgs a) {
         }
         const int m = __builtin_amdgcn_readfirstlane(a.q_len[q]);
         const int n = __builtin_amdgcn_readfirstlane(a.c_len[ref]);
+        const int D = a.q_dim ? __builtin_amdgcn_readfirstlane(a.q_dim[q]) : a.D;
+        const int nch = a.q_dim ? nch_pad(D) : NCH;
         const int W = weff_dev(m, n, a.window, a.num, a.den);
-        const float gamma = dp_gamma_dev(m, n, NCH);
+        const float gamma = dp_gamma_dev(m, n, nch);
         __syncthreads();
         Abandon ab{a.key + (int64_t)q * kKeyStride, gamma, ~0ull};
         bool aband = false;
         int blocks = 0;
-        float v;
-        if (a.abandon)
-            v = rows_core<float, NCH, false, true>(0, a.Q + a.q_off[q], a.C + a.c_off[ref], m, n, W, a.D, lane,
-                                                   nullptr, ab, aband, &blocks);
-        else
-            v = rows_core<float, NCH, false, false>(0, a.Q + a.q_off[q], a.C + a.c_off[ref], m, n, W, a.D, lane,
-                                                    nullptr, ab, aband, &blocks);
+        float v = __builtin_inff();
+        if (nch == NCH) {
+            v = rknn_pair<NCH>(a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+        } else {   // banks of several D: the item's own chunk count
+            rknn_pair_if<1, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+            rknn_pair_if<2, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+            rknn_pair_if<3, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+            rknn_pair_if<4, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+            rknn_pair_if<6, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+            rknn_pair_if<8, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+            rknn_pair_if<12, NCH>(nch, v, a, q, ref, m, n, W, D, lane, ab, aband, blocks);
+        }
         if (lane == (m - 1) % kRowBlock) {
             float out = __builtin_inff();
             if (!aband) {
@@ -235,10 +268,28 @@ __global__ __launch_bounds__(64) void k_rknn_dtw(RaggedKnnArgs a) {
 // survivors, then float64 re-scoring (row mapping) of every candidate
 // within (1 + g) / (1 - g) of it, g the largest DP error bound of the
 // query's pairs; the smallest float64 value wins, ties to the lowest index.
+template <int K>
+__device__ __forceinline__ double rknn_rescore(const RaggedKnnArgs& a, int q, int r, int m, int n, int W, int D,
+                                               int lane) {
+    Abandon ab{nullptr, 0.0f, 0};
+    bool aband = false;
+    return rows_core<double, K, false, false>(0, a.Q + a.q_off[q], a.C + a.c_off[r], m, n, W, D, lane, nullptr,
+                                              ab, aband);
+}
+
+template <int K, int NCH>
+__device__ __forceinline__ void rknn_rescore_if(int nch, double& v, const RaggedKnnArgs& a, int q, int r, int m,
+                                                int n, int W, int D, int lane) {
+    if constexpr (K <= NCH)
+        if (nch == K) v = rknn_rescore<K>(a, q, r, m, n, W, D, lane);
+}
+
 template <int NCH>
 __global__ __launch_bounds__(64) void k_rknn_finalize(RaggedKnnArgs a) {
     const int q = blockIdx.x, lane = threadIdx.x;
     const int m = __builtin_amdgcn_readfirstlane(a.q_len[q]);
+    const int D = a.q_dim ? __builtin_amdgcn_readfirstlane(a.q_dim[q]) : a.D;
+    const int nch = a.q_dim ? nch_pad(D) : NCH;
     float mn = __builtin_inff();
     const int ns = a.R, nl = a.list_cnt[q];
     for (int k = lane; k < ns; k += kWave)
@@ -246,7 +297,7 @@ __global__ __launch_bounds__(64) void k_rknn_finalize(RaggedKnnArgs a) {
     for (int k = lane; k < nl; k += kWave) mn = __builtin_fminf(mn, a.list_dist[(int64_t)q * a.cap + k]);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fminf(mn, __shfl_xor(mn, o));
-    const double g = (double)dp_gamma_dev(m, a.maxn, NCH);
+    const double g = (double)dp_gamma_dev(m, a.maxn, nch);
     const double thr = (double)mn * ((1.0 + g) / (1.0 - g) * (1.0 + 1e-9));
     double best = __builtin_inf();
     int bestidx = 0x7fffffff;
@@ -269,10 +320,18 @@ __global__ __launch_bounds__(64) void k_rknn_finalize(RaggedKnnArgs a) {
                 const int n = __builtin_amdgcn_readfirstlane(a.c_len[r]);
                 const int W = weff_dev(m, n, a.window, a.num, a.den);
                 __syncthreads();
-                Abandon ab{nullptr, 0.0f, 0};
-                bool aband = false;
-                double v = rows_core<double, NCH, false, false>(0, a.Q + a.q_off[q], a.C + a.c_off[r], m, n, W,
-                                                                a.D, lane, nullptr, ab, aband);
+                double v = __builtin_inf();
+                if (nch == NCH) {
+                    v = rknn_rescore<NCH>(a, q, r, m, n, W, D, lane);
+                } else {
+                    rknn_rescore_if<1, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                    rknn_rescore_if<2, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                    rknn_rescore_if<3, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                    rknn_rescore_if<4, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                    rknn_rescore_if<6, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                    rknn_rescore_if<8, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                    rknn_rescore_if<12, NCH>(nch, v, a, q, r, m, n, W, D, lane);
+                }
                 v = __shfl(v, (m - 1) % kRowBlock);
                 ++rescored;
                 if (v < best || (v == best && r < bestidx)) { best = v; bestidx = r; }
@@ -285,7 +344,8 @@ __global__ __launch_bounds__(64) void k_rknn_finalize(RaggedKnnArgs a) {
         atomicAdd(&a.stats[kStRescored], (unsigned long long)rescored);
         int nseeds = 0;
         for (int k = 0; k < ns; ++k) nseeds += a.seeds[(int64_t)q * ns + k] >= 0;
-        const int pruned = a.nc - nseeds - nl;
+        const int bank = a.q_dim ? a.q_ce[q] - a.q_cb[q] : a.nc;
+        const int pruned = bank - nseeds - nl;
         if (pruned > 0) atomicAdd(&a.stats[kStPrunedMv], (unsigned long long)pruned);
     }
 }
@@ -296,9 +356,20 @@ hipError_t launch_rq_tables(const RaggedKnnArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    if (blocks > 0) hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_rlb_mv(const RaggedKnnArgs& a, hipStream_t s) {
-    const dim3 grid((a.nc + 3) / 4, a.nq);
-    if (a.D % 4 != 0) {
+    const dim3 grid(((a.q_dim ? a.bank_max : a.nc) + 3) / 4, a.nq);
+    if (a.D % 4 != 0 && !a.q_dim) {
         hipLaunchKernelGGL((k_rlb_mv<1, false>), grid, dim3(256), 0, s, a);
     } else {
         switch (nch_pad(a.D)) {

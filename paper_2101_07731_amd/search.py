@@ -112,6 +112,51 @@ def knn(index, queries, stats=False, workspace=None, k=1, **kw):
     return idx, dist, sd
 
 
+class GraphedSearch:
+    """A whole search (every stage of the cascade, tc_dtw_knn) captured once in
+    a CUDA (HIP) graph for fixed shapes; `replay` reruns it with no host work.
+    New queries of the same shapes go into `.queries_flat` (the flat buffer of
+    the captured batch).  Queries of uneven lengths or dims work too: the
+    warm-up call copies their metadata into the workspace and the captured
+    call reuses it (params.reuse_query_meta)."""
+
+    def __init__(self, index, queries, k=1, **kw):
+        self.Q = SeriesSet(queries)
+        self.queries_flat = self.Q.flat
+        self.index = index
+        lib = L.lib()
+        dev = self.Q.flat.device
+        p = params(k=k, **kw)
+        wsb = lib.tc_dtw_knn_workspace_bytes(C.byref(index.ix), C.byref(self.Q.batch), C.byref(p))
+        if wsb == 0:
+            L.check(lib.tc_dtw_knn(C.byref(index.ix), C.byref(self.Q.batch), C.byref(p), None, None, None, None,
+                                   0, _stream()))
+        self.ws = _workspace(wsb, dev)
+        shape = (self.Q.count,) if k == 1 else (self.Q.count, k)
+        self.idx = torch.empty(shape, dtype=torch.int32, device=dev)
+        self.dist = torch.empty(shape, dtype=torch.float32, device=dev)
+
+        def call(reuse):
+            p.reuse_query_meta = 1 if reuse else 0
+            L.check(lib.tc_dtw_knn(C.byref(index.ix), C.byref(self.Q.batch), C.byref(p),
+                                   C.c_void_p(self.idx.data_ptr()), C.c_void_p(self.dist.data_ptr()), None,
+                                   C.c_void_p(self.ws.data_ptr()), wsb, _stream()))
+
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):   # warm-up outside the capture (writes the query metadata)
+            call(False)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            call(True)
+
+    def replay(self):
+        self.graph.replay()
+        return self.idx, self.dist
+
+
 def knn_workspace_bytes(index, queries, **kw):
     Q = SeriesSet(queries)
     p = params(**kw)

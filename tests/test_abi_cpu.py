@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     lib = L.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.tc_dtw_abi_version() == 5
+    assert lib.tc_dtw_abi_version() == 6
 
 
 def _batch(count=2, dim=3, ulen=8, data=0x1000):
@@ -122,14 +122,38 @@ def test_mixed_dims_and_plans_validated_on_the_host():
     assert st == L.ERR_INVALID
 
 
-def test_search_calls_need_one_dim():
+def test_index_banks_validated_on_the_host():
+    """References of several dims form banks: each dim one contiguous run,
+    at most eight banks; queries of a dim without a bank are refused."""
     lib = L.lib()
-    lens = (C.c_int32 * 2)(5, 9)
-    dx = (C.c_int32 * 2)(2, 3)
-    refs = L.Batch(0x1000, None, lens, 2, 0, 0, dx)
+    lens = (C.c_int32 * 3)(5, 9, 7)
+    dx = (C.c_int32 * 3)(2, 3, 2)                  # dim 2 in two runs
+    refs = L.Batch(0x1000, None, lens, 3, 0, 0, dx)
     assert lib.tc_dtw_index_bytes(C.byref(refs)) == 0
     st = lib.tc_dtw_build_index(C.byref(refs), C.c_void_p(0x2000), 1 << 20, C.byref(L.Index()), None)
     assert st == L.ERR_UNSUPPORTED
+    n = 9
+    lens9 = (C.c_int32 * n)(*([5] * n))
+    d9 = (C.c_int32 * n)(*range(1, n + 1))          # nine banks
+    refs9 = L.Batch(0x1000, None, lens9, n, 0, 0, d9)
+    assert lib.tc_dtw_index_bytes(C.byref(refs9)) == 0
+    dok = (C.c_int32 * 3)(2, 2, 3)
+    assert lib.tc_dtw_index_bytes(C.byref(L.Batch(0x1000, None, lens, 3, 0, 0, dok))) > 0
+    # a hand-made index description with banks of dims 2 and 3: a query of dim 4 has no bank
+    ix = L.Index()
+    ix.buf, ix.bytes, ix.count, ix.dim, ix.uniform_len, ix.max_len = 0x3000, 1 << 20, 3, 3, 0, 9
+    ix.nbanks = 2
+    ix.bank_dim[0], ix.bank_first[0], ix.bank_count[0] = 2, 0, 2
+    ix.bank_dim[1], ix.bank_first[1], ix.bank_count[1] = 3, 2, 1
+    p = L.KnnParams()
+    lib.tc_dtw_knn_params_default(C.byref(p))
+    qd = (C.c_int32 * 2)(2, 4)
+    ql = (C.c_int32 * 2)(6, 6)
+    qb = L.Batch(0x4000, None, ql, 2, 0, 0, qd)
+    assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(qb), C.byref(p)) == 0
+    st = lib.tc_dtw_knn(C.byref(ix), C.byref(qb), C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), None,
+                        C.c_void_p(0x7000), 1 << 20, None)
+    assert st == L.ERR_INVALID and b"no bank" in lib.tc_dtw_last_error()
 
 
 def test_k_validated_on_the_host():

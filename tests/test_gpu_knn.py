@@ -428,3 +428,28 @@ def test_tune_cascade_picks_a_runnable_choice(dev):
     assert len(tl) == len(search.CASCADE_CHOICES)
     idx, dist = search.knn(ixl, torch.from_numpy(Ql).to(dev), frac=(1, 2), pc_clusters=16, **bl)
     check_against_oracle(idx.cpu().numpy(), dist.cpu().numpy(), Ql, Cl, 1, 2)
+
+
+def test_graphed_search_replays_match_eager(dev):
+    """The whole cascade captured in a HIP graph (search.GraphedSearch): three
+    replays, with eager searches and synchronisations between them and new
+    queries copied in before the last, each equal to the eager result."""
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.cascade_knn(nq=24, nc=500, T=80, D=6, seed=70)
+    Q2, _ = synth.cascade_knn(nq=24, nc=1, T=80, D=6, seed=71)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    for bounds in ("mv", "mv+pc+ti"):
+        say("graphed search", bounds)
+        g = search.GraphedSearch(ix, torch.from_numpy(Q).to(dev), frac=(1, 10), bounds=bounds)
+        ei, ed = search.knn(ix, torch.from_numpy(Q).to(dev), frac=(1, 10), bounds=bounds)
+        for rep in range(3):
+            if rep == 2:
+                g.queries_flat.copy_(torch.from_numpy(Q2).to(dev).reshape(g.queries_flat.shape))
+                ei, ed = search.knn(ix, torch.from_numpy(Q2).to(dev), frac=(1, 10), bounds=bounds)
+            gi, gd = g.replay()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(gi.cpu().numpy(), ei.cpu().numpy())
+            np.testing.assert_array_equal(gd.cpu().numpy(), ed.cpu().numpy())
+            search.knn(ix, torch.from_numpy(Q[:5]).to(dev), frac=(1, 10))   # eager work between replays
+            torch.cuda.synchronize()
+    check_against_oracle(gi.cpu().numpy(), gd.cpu().numpy(), Q2, Cs, 1, 10)

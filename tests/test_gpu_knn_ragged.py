@@ -109,3 +109,114 @@ def test_bank_workload_sampled(dev, bank_workload, D):
     ri, rd = O.knn_exhaustive([Q[k]], Cs, num=1, den=10, threads=16)
     assert idx[k] == ri[0]
     assert dist[k] == np.float32(rd[0])
+
+
+def _banked(rng, dims, per_bank, lo, hi):
+    refs, first = [], {}
+    for D in dims:
+        first[D] = len(refs)
+        refs += bank(rng, per_bank, lo, hi, D)
+    return refs, first
+
+
+@pytest.mark.parametrize("bounds", ["mv", "plain"])
+def test_banks_of_several_dims_in_one_call(dev, bounds):
+    """An index over banks of d = 1, 3, 4, 8 (each a contiguous run, lengths
+    uneven) and queries of mixed d in ONE search call: every query gets the
+    oracle's nearest neighbour within the bank of its d (index in the whole
+    set), ties to the lowest index; the pair count covers query-bank pairs."""
+    from paper_2101_07731_amd import search
+    rng = np.random.default_rng(140)
+    dims = (1, 3, 4, 8)
+    refs, first = _banked(rng, dims, 40, 6, 120)
+    refs[first[3] + 9] = refs[first[3] + 2].copy()            # a tie inside a bank
+    Q, Qd = [], []
+    for k in range(14):
+        D = dims[k % len(dims)]
+        Q += bank(rng, 1, 6, 120, D)
+        Qd.append(D)
+    Q.append(refs[first[4] + 5].copy())                         # distance 0 to a reference
+    Qd.append(4)
+    say("banks one call", bounds)
+    ix = search.Index([torch.from_numpy(c).to(dev) for c in refs])
+    assert ix.ix.nbanks == len(dims)
+    idx, dist, st = search.knn(ix, [torch.from_numpy(q).to(dev) for q in Q], frac=(1, 10), bounds=bounds,
+                               stats=True)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert st["pairs"] == len(Q) * 40
+    assert st["pruned_mv"] + st["dtw_started"] == st["pairs"]
+    for qi, (q, D) in enumerate(zip(Q, Qd)):
+        members = refs[first[D]:first[D] + 40]
+        ri, rd = O.knn_exhaustive([q], members, num=1, den=10)
+        assert idx[qi] == first[D] + ri[0], (qi, D)
+        assert dist[qi] == np.float32(rd[0])
+    assert dist[-1] == 0.0 and idx[-1] == first[4] + 5
+
+
+def test_banks_lower_bounds(dev):
+    """The LB_MV matrix over banks: +inf outside a query's bank, the bank's
+    own bound inside (as a search of that bank alone)."""
+    from paper_2101_07731_amd import search
+    rng = np.random.default_rng(141)
+    refs, first = _banked(rng, (2, 5), 30, 10, 90)
+    Q = bank(rng, 3, 10, 90, 2) + bank(rng, 2, 10, 90, 5)
+    ix = search.Index([torch.from_numpy(c).to(dev) for c in refs])
+    lb = search.lower_bounds(ix, [torch.from_numpy(q).to(dev) for q in Q], kind="mv", frac=(1, 10)).cpu().numpy()
+    for qi, q in enumerate(Q):
+        D = q.shape[1]
+        lo = first[D]
+        assert np.all(np.isinf(np.delete(lb[qi], np.arange(lo, lo + 30))))
+        ixb = search.Index([torch.from_numpy(c).to(dev) for c in refs[lo:lo + 30]])
+        lbb = search.lower_bounds(ixb, [torch.from_numpy(q).to(dev)], kind="mv", frac=(1, 10)).cpu().numpy()
+        np.testing.assert_array_equal(lb[qi, lo:lo + 30], lbb[0])
+
+
+def test_bank_workload_one_call_sampled(dev, bank_workload):
+    """The uneven workload's five banks (4096 references each, d = 2 ... 32)
+    in one index and its 256 queries of mixed d in one search call: the same
+    neighbours as the per-bank searches for every query, and the oracle's for
+    the shortest query of each bank."""
+    from paper_2101_07731_amd import search
+    banks, queries = bank_workload
+    order = sorted(banks)
+    refs, first = [], {}
+    for D in order:
+        first[D] = len(refs)
+        refs += banks[D]
+    ix = search.Index([torch.from_numpy(c).to(dev) for c in refs])
+    Qs = [q for _, q in queries]
+    say("bank workload one call", len(refs), len(Qs))
+    idx, dist, st = search.knn(ix, [torch.from_numpy(q).to(dev) for q in Qs], frac=(1, 10), stats=True)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert st["pairs"] == 256 * 4096
+    for D in order:
+        sel = [k for k, (d, _) in enumerate(queries) if d == D]
+        ixb = search.Index([torch.from_numpy(c).to(dev) for c in banks[D]])
+        ib, db = search.knn(ixb, [torch.from_numpy(Qs[k]).to(dev) for k in sel], frac=(1, 10))
+        np.testing.assert_array_equal(idx[sel], ib.cpu().numpy() + first[D])
+        np.testing.assert_array_equal(dist[sel], db.cpu().numpy())
+        k = sel[int(np.argmin([Qs[t].shape[0] for t in sel]))]
+        ri, rd = O.knn_exhaustive([Qs[k]], banks[D], num=1, den=10, threads=16)
+        assert idx[k] == first[D] + ri[0] and dist[k] == np.float32(rd[0])
+
+
+def test_graphed_bank_search_replays_match_eager(dev):
+    """The one-call search over banks of several dims (queries of uneven
+    lengths and mixed d) captured in a HIP graph: the captured call reuses the
+    query metadata the warm-up call wrote; three replays equal the eager
+    result."""
+    from paper_2101_07731_amd import search
+    rng = np.random.default_rng(142)
+    refs, first = _banked(rng, (2, 8), 30, 10, 90)
+    Q = bank(rng, 4, 10, 90, 2) + bank(rng, 3, 10, 90, 8)
+    ix = search.Index([torch.from_numpy(c).to(dev) for c in refs])
+    Qd = [torch.from_numpy(q).to(dev) for q in Q]
+    g = search.GraphedSearch(ix, Qd, frac=(1, 10), bounds="mv")
+    ei, ed = search.knn(ix, Qd, frac=(1, 10), bounds="mv")
+    for _ in range(3):
+        gi, gd = g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(gi.cpu().numpy(), ei.cpu().numpy())
+        np.testing.assert_array_equal(gd.cpu().numpy(), ed.cpu().numpy())
+        search.knn(ix, Qd[:2], frac=(1, 10))
+        torch.cuda.synchronize()
