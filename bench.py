@@ -464,10 +464,23 @@ def main():
             stf.update(search.knn(ix, Qd, stats=True, **kwf)[2])
 
         msf = _events_ms(full, 3)
+        # per-pair costs in this search: LB_PC (its stage less the LB_TI launch), LB_TI, and the
+        # survivors' DTW (the seeds, seed_r = 4 per query, run in their own stage)
+        dtw_pairs = max(1, stf["dtw_started"] - 4 * nq)
+        us_pc = (stf["stage_ms"][4] - stf["lb_ti_ms"]) * 1e3 / max(1, stf["evaluated_pc"])
+        us_ti = stf["lb_ti_ms"] * 1e3 / max(1, stf["evaluated_ti"])
+        us_dtw = stf["stage_ms"][5] * 1e3 / dtw_pairs
         out["full_cascade"] = {"bounds": "mv+pc+ti", "queries_per_s": round(nq / (msf * 1e-3), 2),
                                "pruned_pc": stf["pruned_pc"], "pruned_ti": stf["pruned_ti"],
                                "pct_dtw_pruned": round(100.0 * (1 - stf["dtw_started"] / stf["pairs"]), 3),
-                               "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3)}
+                               "stage_ms_lb_pc_ti": round(stf["stage_ms"][4], 3),
+                               "stage_ms_lb_ti": round(stf["lb_ti_ms"], 3),
+                               "evaluated_pc": stf["evaluated_pc"], "evaluated_ti": stf["evaluated_ti"],
+                               "dtw_pairs": dtw_pairs,
+                               "ns_per_pair": {"lb_pc": round(us_pc * 1e3, 3), "lb_ti": round(us_ti * 1e3, 3),
+                                               "dtw": round(us_dtw * 1e3, 3)},
+                               "per_pair_vs_dtw": {"lb_pc": round(us_pc / us_dtw, 3),
+                                                   "lb_ti": round(us_ti / us_dtw, 3)}}
     if "cand_boxes" in extras:
         note("cand_boxes")
         # LB_PC (e = 0.5, so that it runs on more pairs) with the query's boxes built per query

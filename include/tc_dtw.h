@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define TC_DTW_ABI_VERSION 6
+#define TC_DTW_ABI_VERSION 7
 
 typedef struct ihipStream_t* tc_dtw_stream; /* same type as hipStream_t; NULL = default stream */
 
@@ -442,6 +442,9 @@ typedef struct {
     uint64_t cells;          /* DTW cells evaluated (abandoned pairs counted up to the abandoning step) */
     uint64_t rescored;       /* float64 re-scorings */
     float stage_ms[8];       /* prep, lb_mv, seed, compact, lb_pc+lb_ti, dtw, finalize, total */
+    uint64_t evaluated_pc;   /* pairs whose LB_PC was evaluated (uniform searches) */
+    uint64_t evaluated_ti;   /* pairs whose LB_TI was evaluated (uniform searches) */
+    float lb_ti_ms;          /* the LB_TI launch's share of stage_ms[4] */
 } tc_dtw_knn_stats;
 
 size_t tc_dtw_knn_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* queries,

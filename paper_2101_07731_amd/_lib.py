@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcdtw.so")
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_DEVICE = range(5)
 F64 = 1
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 
 class TcDtwError(RuntimeError):
@@ -85,7 +85,8 @@ class KnnStats(C.Structure):
     _fields_ = [("pairs", C.c_uint64), ("pruned_mv", C.c_uint64), ("pruned_pc", C.c_uint64),
                 ("pruned_ti", C.c_uint64), ("dtw_started", C.c_uint64), ("dtw_abandoned", C.c_uint64),
                 ("dtw_completed", C.c_uint64), ("cells", C.c_uint64), ("rescored", C.c_uint64),
-                ("stage_ms", C.c_float * 8)]
+                ("stage_ms", C.c_float * 8), ("evaluated_pc", C.c_uint64), ("evaluated_ti", C.c_uint64),
+                ("lb_ti_ms", C.c_float)]
 
 
 LB_MV, LB_PC, LB_TI = 1, 2, 4

@@ -773,7 +773,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     dd.clear[2] = x.pti;
     const KnnPlanDev d = dd;
 
-    hipEvent_t ev[8];
+    hipEvent_t ev[10];   // stage marks 0-7; 8-9 around the LB_TI launch
     const bool timed = stats != nullptr;
     if (timed)
         for (auto& x : ev) (void)hipEventCreate(&x);
@@ -819,6 +819,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
             PcArgs a = pc_args(K, d, x, ix, p);
             a.in_list = d.glist; a.in_cnt = d.gcnt; a.in_uniform = 0;
             a.out_lb = x.glb; a.key = d.key;
+            a.evaluated = d.stats + kStEvalPc;
             // query-side boxes: waves over 64 listed candidates of a query; candidate-side: one pair per wave
             const int per = K.cand ? 1 : kWave;
             if ((e = launch_list_items(d.gcnt, 0, K.nq, per, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
@@ -840,10 +841,13 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         if (K.ti) {
             TiArgs a = ti_args(K, d, x, ix, p);
             a.in_list = x.tlist; a.out_lb = x.tout; a.lb_in = x.tlb; a.key = d.key;
+            a.evaluated = d.stats + kStEvalTi;
+            if (timed) (void)hipEventRecord(ev[8], s);
             if ((e = launch_list_items(x.tcnt, 0, K.nq, 1, d.prefix, d.item_query, a.counter, s)) != hipSuccess)
                 return hip_fail(e, "ti items");
             const int ti_blocks = persistent_blocks(ti_lds_bytes(K.m, K.n, K.D, p->ti_period, K.W), (int64_t)K.nq * K.cap);
             if ((e = launch_lb_ti(a, ti_blocks, s)) != hipSuccess) return hip_fail(e, "lb_ti");
+            if (timed) (void)hipEventRecord(ev[9], s);
             RouteArgs r2 = r;
             r2.in_list = x.tlist; r2.in_cnt = x.tcnt; r2.lb_prev = x.tlb; r2.lb_new = x.tout;
             r2.next_list = nullptr; r2.pruned = x.pti;
@@ -895,6 +899,8 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         stats->dtw_completed = h[kStDtwStarted] - h[kStDtwAbandoned];
         stats->cells = h[kStCells];
         stats->rescored = h[kStRescored];
+        stats->evaluated_pc = h[kStEvalPc];
+        stats->evaluated_ti = h[kStEvalTi];
         for (int i = 0; i < 7; ++i) {
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
@@ -903,6 +909,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
         float tot = 0.0f;
         (void)hipEventElapsedTime(&tot, ev[0], ev[7]);
         stats->stage_ms[7] = tot;
+        if (K.gate && K.ti) (void)hipEventElapsedTime(&stats->lb_ti_ms, ev[8], ev[9]);
         for (auto& x : ev) (void)hipEventDestroy(x);
     }
     return ok();

@@ -16,6 +16,7 @@
 //    before the clamp at zero; the sum of the squared column minima is
 //    scaled by 1 - (n + 5) u and rounded down.
 #include <algorithm>
+#include <type_traits>
 
 #include "bounds_common.h"
 
@@ -144,69 +145,77 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
     const bool cand = a.cand != 0;
     const int D = a.D, n = cand ? a.m : a.n, K = a.K, w = a.w;
     const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
+    unsigned long long evaluated = 0;   // pairs this wave evaluated
+    const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.nq]);
+    const int B = item_batch(total);
     for (;;) {
-        const int item = wave_next_item(a.counter);
-        if (item >= a.prefix[a.nq]) break;
-        const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
-        const int e = item - __builtin_amdgcn_readfirstlane(a.prefix[q]);
-        const int ref = a.in_list ? __builtin_amdgcn_readfirstlane((int)a.in_list[(int64_t)q * a.cap + e]) : e;
-        float bsf = __builtin_inff();
-        if (a.key) {
-            bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
-            // selective deployment: only pairs with LB_MV > e^2 bsf
-            const float mv = a.lb_mv[(int64_t)q * a.nc + ref];
-            if (wave_uniform(!((double)mv > a.e2 * (double)bsf))) {
-                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
-                continue;
-            }
-        }
-        // the evaluated points, and the series whose boxes they are measured against
-        const float* c = cand ? a.Q + (int64_t)q * n * D : a.C + (int64_t)ref * n * D;
-        const int owner = cand ? ref : q;
-        const float* bxq = a.boxes + (int64_t)owner * a.ngroups * K * D * 2;
-        const int32_t* nbq = a.nbox + (int64_t)owner * a.ngroups;
-        const double stop = a.key ? (double)bsf / a.keep : __builtin_inf();
-        float acc = 0.0f;
-        for (int j0 = 0; j0 < n; j0 += kWave) {
-            const int j = j0 + lane;
-            if (j < n) {
-                const int g = j / w;
-                const int nb = nbq[g];
-                const float* bg = bxq + (int64_t)g * K * D * 2;
-                float cv[DMAX];
-#pragma unroll
-                for (int p = 0; p < DMAX; ++p) cv[p] = p < D ? c[(int64_t)j * D + p] : 0.0f;
-                float best = __builtin_inff();
-                for (int b = 0; b < nb; ++b) {
-                    // the box's (lo, hi) pairs, all loads issued before any use (dimensions
-                    // past D re-read dimension 0 and are skipped below)
-                    const float2* bb = reinterpret_cast<const float2*>(bg + b * D * 2);
-                    float2 lh[DMAX];
-#pragma unroll
-                    for (int p = 0; p < DMAX; ++p) lh[p] = bb[p < D ? p : 0];
-                    float s = 0.0f;
-#pragma unroll
-                    for (int p = 0; p < DMAX; ++p) {
-                        if (p < D) {
-                            const float t = __builtin_fmaxf(__builtin_fmaxf(lh[p].x - cv[p], cv[p] - lh[p].y), 0.0f);
-                            s = __builtin_fmaf(t, t, s);
-                        }
-                    }
-                    best = __builtin_fminf(best, s);
+        const int base = wave_next_batch(a.counter, B);
+        if (base >= total) break;
+        const int bend = min(base + B, total);
+        for (int item = base; item < bend; ++item) {
+            const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
+            const int e = item - __builtin_amdgcn_readfirstlane(a.prefix[q]);
+            const int ref = a.in_list ? __builtin_amdgcn_readfirstlane((int)a.in_list[(int64_t)q * a.cap + e]) : e;
+            float bsf = __builtin_inff();
+            if (a.key) {
+                bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
+                // selective deployment: only pairs with LB_MV > e^2 bsf
+                const float mv = a.lb_mv[(int64_t)q * a.nc + ref];
+                if (wave_uniform(!((double)mv > a.e2 * (double)bsf))) {
+                    if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
+                    continue;
                 }
-                acc += best;
             }
-            if (a.key && j0 + kWave < n) {
-                float tot = acc;
+            // the evaluated points, and the series whose boxes they are measured against
+            const float* c = cand ? a.Q + (int64_t)q * n * D : a.C + (int64_t)ref * n * D;
+            const int owner = cand ? ref : q;
+            const float* bxq = a.boxes + (int64_t)owner * a.ngroups * K * D * 2;
+            const int32_t* nbq = a.nbox + (int64_t)owner * a.ngroups;
+            const double stop = a.key ? (double)bsf / a.keep : __builtin_inf();
+            float acc = 0.0f;
+            for (int j0 = 0; j0 < n; j0 += kWave) {
+                const int j = j0 + lane;
+                if (j < n) {
+                    const int g = j / w;
+                    const int nb = nbq[g];
+                    const float* bg = bxq + (int64_t)g * K * D * 2;
+                    float cv[DMAX];
 #pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
-                if (wave_uniform((double)tot * defl > stop)) break;
+                    for (int p = 0; p < DMAX; ++p) cv[p] = p < D ? c[(int64_t)j * D + p] : 0.0f;
+                    float best = __builtin_inff();
+                    for (int b = 0; b < nb; ++b) {
+                        // the box's (lo, hi) pairs, all loads issued before any use (dimensions
+                        // past D re-read dimension 0 and are skipped below)
+                        const float2* bb = reinterpret_cast<const float2*>(bg + b * D * 2);
+                        float2 lh[DMAX];
+#pragma unroll
+                        for (int p = 0; p < DMAX; ++p) lh[p] = bb[p < D ? p : 0];
+                        float s = 0.0f;
+#pragma unroll
+                        for (int p = 0; p < DMAX; ++p) {
+                            if (p < D) {
+                                const float t = __builtin_fmaxf(__builtin_fmaxf(lh[p].x - cv[p], cv[p] - lh[p].y), 0.0f);
+                                s = __builtin_fmaf(t, t, s);
+                            }
+                        }
+                        best = __builtin_fminf(best, s);
+                    }
+                    acc += best;
+                }
+                if (a.key && j0 + kWave < n) {
+                    float tot = acc;
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
+                    if (wave_uniform((double)tot * defl > stop)) break;
+                }
             }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+            if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
+            ++evaluated;
         }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
     }
+    if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
 }
 
 // ------------------------------------------------------------------- K6
@@ -246,6 +255,7 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
     const int D = a.D, n = a.n, K = a.K, w = a.w, G = a.ngroups;
     const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
     const bool vec = EXACT && (reinterpret_cast<uintptr_t>(a.C) & 15) == 0;
+    unsigned long long evaluated = 0;   // pairs this wave evaluated
     for (;;) {
         const int item = wave_next_item(a.counter);
         if (item >= a.prefix[a.nq]) break;
@@ -264,7 +274,9 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
             }
             stop = (double)bsf / a.keep;
         }
-        if (__ballot(live) == 0) continue;
+        const uint64_t lv = __ballot(live);
+        if (lv == 0) continue;
+        evaluated += (unsigned long long)__popcll(lv);
         const float* cs = a.C + (int64_t)ref * n * D;
         const float* bq = a.boxes + (int64_t)q * G * K * D * 2;
         const int32_t* nbq = a.nbox + (int64_t)q * G;
@@ -307,6 +319,7 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
         }
         if (live) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
     }
+    if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
 }
 
 // dst[r * NCH + k] = chunk k of point r * rstride of the series at src, for
@@ -332,16 +345,30 @@ __device__ __forceinline__ void stage_point_chunks(float4* dst, const float* __r
 // LB_TI (LB_TIP with optional TOP, Sec. 4.1-4.2, Fig. 3) of one listed
 // pair per wave.  Lane k (and k + 64 with two slots) holds band offset k,
 // i.e. cell (i, i - W + k) of row i.  The cell of row i+1 on the same
-// column is offset k - 1, so both the (L, U) pair (Eqs. 7-8) and the
-// running column minimum of max(0, L) move one lane down per row (DPP
-// shift); a column's minimum is final when it leaves offset 0.  Exact rows
-// (i = 0 and i mod P = 0) compute e(q_i, c_j) (query point broadcast from
-// LDS, candidate point per lane); the top cell of each row takes the
-// precomputed e(q_i, c_{i+W}) under TOP, else Eqs. 9-10 from its left
-// neighbour with gamma_j = e(c_{j-1}, c_j) from the index.
-// TOP and the point width (NCH float4 chunks, zero-padded) are template
-// parameters, so the row loop has no runtime branch on them and an exact
-// row's distance is NCH unrolled 16-byte LDS reads per point.
+// column is offset k - 1, so a cell's state and the running column minimum
+// of max(0, L) move one lane down per row (DPP shift); a column's minimum
+// is final when it leaves offset 0.
+//
+// A cell keeps (V, Y) = (L + U, 2U) instead of (L, U).  Eqs. 7-8 take the
+// step d = |q_i - q_{i-1}| as L' = max(L - d, d - U), U' = U + d, so
+// V' = max(V, 2d) and Y' = Y + 2d: one maximum and one addition per cell,
+// each reading its operand straight from the neighbouring lane, and
+// L' = V' - Y'/2 only enters the safe value V' - (1 + s) Y'/2 (one fused
+// multiply-add).  Doubling is exact, so Y rounds exactly as U would.
+// Eqs. 9-10 for the top cell without TOP have the same form with gamma_j
+// and the left neighbour's (V, Y).
+// Exact rows (i = 0 and i mod P = 0) compute e(q_i, c_j) (query point
+// broadcast from LDS, candidate point per lane) and set V = Y = 2e (the
+// hardware square root, see ti_exact_sides);
+// the top cell of each row takes the precomputed e(q_i, c_{i+W}) under
+// TOP.  TOP and the point width (NCH float4 chunks, zero-padded) are
+// template parameters.
+//
+// Rows run in three phases: the first W + 1 rows and the rows whose band
+// reaches past the candidate's end test every lane for a cell; between
+// them every band offset is a cell, so a lane's mask is fixed and a
+// leaving column always has one.  There, the P - 1 rows between two exact
+// rows form one branch-free loop.
 template <int SLOTS, bool TOP, int NCH>
 __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     const int lane = threadIdx.x;
@@ -349,225 +376,302 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     // LDS, staged per pair so that the row loop never waits on global memory:
     float4* cst = lds4;                                // [n][NCH] candidate points
     float4* qex = cst + (int64_t)n * NCH;              // [exact rows][NCH] query points of the exact rows
-    // [m + 1] (query step, TOP distance) of each row, read as one 8-byte pair per row;
-    // entry m is padding, read once past the last row
+    // [m + 2] per row i: (2 d_i, 2 t_i) with t_i the TOP distance e(q_i, c_{i+W}) or, without
+    // TOP, gamma_{i+W}; entries m and m + 1 are padding, read ahead past the last row
     float2* tdq = reinterpret_cast<float2*>(qex + (int64_t)ti_exact_rows(m, P) * NCH);
-    float* gcs = reinterpret_cast<float*>(tdq + m + 1);   // [n] candidate steps
     const int KB = 2 * W + 1;                          // band offsets 0 .. 2W
     const float INF = __builtin_inff();
+    const uint32_t INF_BITS = 0x7f800000u;
     const double u = 1.0 / 16777216.0;
     // longest recursion chain since an exact value (rows, plus one top step per row without TOP)
     const int rmax = P > 0 ? (TOP ? P - 1 : 2 * (P - 1) + 1) : (TOP ? m : 2 * m + 1);
-    const float slack = (float)((0.5 * D + 5.0 + rmax) * u * 1.02);
+    // safe value V - (1 + s) Y / 2 with s = (1.5 D + 20 + r_max) u 1.02, the factor rounded up
+    const float k1h = 0.5f * rup(1.0 + (1.5 * D + 20.0 + rmax) * u * 1.02);
     const double defl = 1.0 - (double)(n + 5) * u * 1.001;
     const int kt = KB - 1;                             // top offset
     const int kl = kt > 0 ? kt - 1 : 0;                // its left neighbour
+    // rows [ib, ie): every offset 0 .. 2W of the row is a column of the candidate (i >= W, i + W < n)
+    // and the column leaving offset 0 had a cell (i >= W + 1); without TOP, the top cell also
+    // needs a left neighbour (W >= 1)
+    const int ib = min(m, W + 1);
+    const int ie = (!TOP && W == 0) ? ib : max(ib, min(m, n - W));
+    unsigned long long evaluated = 0;   // pairs this wave evaluated
+    const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.nq]);
+    const int B = item_batch(total);
     for (;;) {
-        const int item = wave_next_item(a.counter);
-        if (item >= a.prefix[a.nq]) break;
-        const int q = a.item_query[item];
-        const int e = item - a.prefix[q];
-        const int ref = a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e;
-        if (a.key) {
-            // selective deployment: only pairs whose bound so far exceeds e^2 bsf
-            const float cur = a.lb_in[(int64_t)q * a.cap + e];
-            const float bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
-            if (wave_uniform(!((double)cur > a.e2 * (double)bsf))) {
-                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;
-                continue;
+        const int base = wave_next_batch(a.counter, B);
+        if (base >= total) break;
+        const int bend = min(base + B, total);
+        for (int item = base; item < bend; ++item) {
+            const int q = a.item_query[item];
+            const int e = item - a.prefix[q];
+            const int ref = a.in_list ? (int)a.in_list[(int64_t)q * a.cap + e] : e;
+            if (a.key) {
+                // selective deployment: only pairs whose bound so far exceeds e^2 bsf
+                const float cur = a.lb_in[(int64_t)q * a.cap + e];
+                const float bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
+                if (wave_uniform(!((double)cur > a.e2 * (double)bsf))) {
+                    if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;
+                    continue;
+                }
             }
-        }
-        const float* qs = a.Q + (int64_t)q * m * D;
-        const float* cs = a.C + (int64_t)ref * n * D;
-        // points as whole 16-byte chunks when D is a multiple of 4 and both series are aligned
-        const bool vec = (D & 3) == 0 && ((reinterpret_cast<uintptr_t>(qs) | reinterpret_cast<uintptr_t>(cs)) & 15) == 0;
-        __syncthreads();
-        {
-            const float* qsp = a.qstep + (int64_t)q * m;
-            int i = lane;
-            for (; i + 3 * kWave < m; i += 4 * kWave) {
-                float v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = qsp[i + u * kWave];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) tdq[i + u * kWave].x = v[u];
-            }
-            for (; i < m; i += kWave) tdq[i].x = qsp[i];
-            if (lane == 0) tdq[m] = make_float2(0.0f, INF);
-        }
-        copy_to_lds(gcs, a.gamma + (int64_t)ref * n, n, lane, kWave);
-        stage_point_chunks<NCH>(cst, cs, n, 1, D, vec, lane);
-        // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
-        stage_point_chunks<NCH>(qex, qs, ti_exact_rows(m, P), P > 0 ? P : 0, D, vec, lane);
-        if (TOP) {
-            // e(q_i, c_{i+W}): query chunks of several rows in flight, candidate chunks from LDS;
-            // components summed in index order (padding adds exact zeros)
+            const float* qs = a.Q + (int64_t)q * m * D;
+            const float* cs = a.C + (int64_t)ref * n * D;
+            // points as whole 16-byte chunks when D is a multiple of 4 and both series are aligned
+            const bool vec = (D & 3) == 0 && ((reinterpret_cast<uintptr_t>(qs) | reinterpret_cast<uintptr_t>(cs)) & 15) == 0;
             __syncthreads();
-            constexpr int RU = NCH <= 2 ? 4 : (NCH <= 4 ? 2 : 1);
-            for (int i0 = lane; i0 < m; i0 += RU * kWave) {
-                float4 qv[RU][NCH];
-#pragma unroll
-                for (int r = 0; r < RU; ++r) {
-                    const int i = i0 + r * kWave;
-#pragma unroll
-                    for (int k = 0; k < NCH; ++k)
-                        qv[r][k] = i < m ? point_chunk(qs + (int64_t)i * D, k, D, vec) : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-#pragma unroll
-                for (int r = 0; r < RU; ++r) {
-                    const int i = i0 + r * kWave;
-                    if (i >= m) break;
-                    const int j = i + W;
-                    float d = INF;
-                    if (j < n) {
-                        float s = 0.0f;
-#pragma unroll
-                        for (int k = 0; k < NCH; ++k) {
-                            const float4 c = cst[j * NCH + k];
-                            float t = qv[r][k].x - c.x; s = __builtin_fmaf(t, t, s);
-                            t = qv[r][k].y - c.y; s = __builtin_fmaf(t, t, s);
-                            t = qv[r][k].z - c.z; s = __builtin_fmaf(t, t, s);
-                            t = qv[r][k].w - c.w; s = __builtin_fmaf(t, t, s);
-                        }
-                        d = __builtin_sqrtf(s);
-                    }
-                    tdq[i].y = d;
-                }
-            }
-        }
-        __syncthreads();
-        float L[SLOTS], U[SLOTS], cm[SLOTS];
-        int jrow[SLOTS];     // column of this lane's cell in the current row
-        bool ink[SLOTS];     // the lane holds a band offset (k <= 2W)
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            L[s] = -INF; U[s] = INF; cm[s] = INF;
-            jrow[s] = lane + 64 * s - W;
-            ink[s] = lane + 64 * s < KB;
-        }
-        float acc = 0.0f;
-        int since = 0;       // rows since the last exact row (exact rows: i = 0 and i mod P = 0)
-        int exr = 0;         // staged query point of the next exact row (qex[i / P])
-        // the row's query step and top distance, read one row ahead
-        float di_next, top_next;
-        {
-            const float2 t0 = tdq[0];
-            di_next = t0.x;
-            top_next = TOP ? t0.y : INF;
-        }
-        for (int i = 0; i < m; ++i) {
-            const bool exact_row = (i == 0) || (P > 0 && since == 0);
-            const float di = di_next;
-            const float topv = top_next;
             {
-                const float2 t1 = tdq[i + 1];
-                di_next = t1.x;
-                if (TOP) top_next = t1.y;
-            }
-            // row i-1 values of the same column (offset k+1)
-            float Ln[SLOTS], Un[SLOTS], cmn[SLOTS];
-            if (SLOTS == 1) {
-                // L, U by rotation: what lane 63 receives moves down only into the top
-                // offset, which every row overwrites (TOP, exact rows, Eqs. 9-10) unless
-                // its column lies outside the candidate, where it stays a non-cell
-                Ln[0] = __uint_as_float(wave_rol1(__float_as_uint(L[0])));
-                Un[0] = __uint_as_float(wave_rol1(__float_as_uint(U[0])));
-                cmn[0] = wave_shl1(INF, cm[0]);
-            } else {
-                Ln[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(L[SLOTS - 1]), 0)), L[0]);
-                Un[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(U[SLOTS - 1]), 0)), U[0]);
-                cmn[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(cm[SLOTS - 1]), 0)), cm[0]);
-                Ln[SLOTS - 1] = wave_shl1(-INF, L[SLOTS - 1]);
-                Un[SLOTS - 1] = wave_shl1(INF, U[SLOTS - 1]);
-                cmn[SLOTS - 1] = wave_shl1(INF, cm[SLOTS - 1]);
-            }
-            // the column at offset 0 of row i-1 is not in row i's band: its minimum is final
-            // (lane 0 holds it and keeps the sum, no scalar round trip; the other lanes' sums
-            // are never read, and +inf, also before the first row, means no cell)
-            const float leaving = cm[0] < INF ? cm[0] : 0.0f;
-            acc = __builtin_fmaf(leaving, leaving, acc);
-            // Lanes that are not cells (columns outside [0, n), offsets past 2W) carry values
-            // that only ever reach other non-cells (the cell below keeps the column), so every
-            // lane evaluates the same arithmetic and only the column minimum is masked.
-            if (exact_row) {
+                const float* qsp = a.qstep + (int64_t)q * m;
+                const float* gam = a.gamma + (int64_t)ref * n;
+                int i = lane;
+                for (; i + 3 * kWave < m; i += 4 * kWave) {
+                    float v[4], g[4];
 #pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    const int jc = min(max(jrow[s], 0), n - 1);
-                    const float4* qrow = qex + exr * NCH;
-                    const float4* crow = cst + jc * NCH;
-                    float sacc = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < NCH; ++k) {
-                        const float4 qv = qrow[k], cv = crow[k];
-                        float t;
-                        t = qv.x - cv.x; sacc = __builtin_fmaf(t, t, sacc);
-                        t = qv.y - cv.y; sacc = __builtin_fmaf(t, t, sacc);
-                        t = qv.z - cv.z; sacc = __builtin_fmaf(t, t, sacc);
-                        t = qv.w - cv.w; sacc = __builtin_fmaf(t, t, sacc);
+                    for (int r = 0; r < 4; ++r) {
+                        v[r] = qsp[i + r * kWave];
+                        g[r] = (!TOP && i + r * kWave + W < n) ? gam[i + r * kWave + W] : 0.0f;
                     }
-                    L[s] = U[s] = __builtin_sqrtf(sacc);
-                }
-                ++exr;
-            } else {
 #pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    const bool istop = lane + 64 * s == kt;
-                    const float lo = __builtin_fmaxf(Ln[s] - di, di - Un[s]);   // Eq. 7
-                    const float hi = Un[s] + di;                                 // Eq. 8
-                    L[s] = (TOP && istop) ? topv : lo;
-                    U[s] = (TOP && istop) ? topv : hi;
+                    for (int r = 0; r < 4; ++r) tdq[i + r * kWave] = make_float2(2.0f * v[r], 2.0f * g[r]);
                 }
+                for (; i < m; i += kWave) {
+                    const float v = qsp[i], g = (!TOP && i + W < n) ? gam[i + W] : 0.0f;
+                    tdq[i] = make_float2(2.0f * v, 2.0f * g);
+                }
+                if (lane < 2) tdq[m + lane] = make_float2(0.0f, INF);
             }
-            if (!TOP && !exact_row) {
-                // top cell from (i, j-1), Eqs. 9-10 (exact when it has no left neighbour)
-                const bool hi_slot = (kl >> 6) != 0;
-                const float Lsel = hi_slot ? L[SLOTS - 1] : L[0];
-                const float Usel = hi_slot ? U[SLOTS - 1] : U[0];
-                const float Ll = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Lsel), kl & 63));
-                const float Ul = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Usel), kl & 63));
-                const int j = i - W + kt;
-                if (lane == (kt & 63) && j >= 0 && j < n) {
-                    float lo, hi;
-                    if (kt >= 1 && j >= 1) {
-                        const float gj = gcs[j];
-                        lo = __builtin_fmaxf(Ll - gj, gj - Ul);          // Eq. 9
-                        hi = Ul + gj;                                    // Eq. 10
-                    } else {
-                        float sacc = 0.0f;
-                        for (int p = 0; p < D; ++p) {
-                            const float t = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
-                            sacc = __builtin_fmaf(t, t, sacc);
+            stage_point_chunks<NCH>(cst, cs, n, 1, D, vec, lane);
+            // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
+            stage_point_chunks<NCH>(qex, qs, ti_exact_rows(m, P), P > 0 ? P : 0, D, vec, lane);
+            if (TOP) {
+                // e(q_i, c_{i+W}): query chunks of several rows in flight, candidate chunks from LDS;
+                // components summed in index order (padding adds exact zeros)
+                __syncthreads();
+                constexpr int RU = NCH <= 2 ? 2 : 1;
+                for (int i0 = lane; i0 < m; i0 += RU * kWave) {
+                    float4 qv[RU][NCH];
+#pragma unroll
+                    for (int r = 0; r < RU; ++r) {
+                        const int i = i0 + r * kWave;
+#pragma unroll
+                        for (int k = 0; k < NCH; ++k)
+                            qv[r][k] = i < m ? point_chunk(qs + (int64_t)i * D, k, D, vec) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int r = 0; r < RU; ++r) {
+                        const int i = i0 + r * kWave;
+                        if (i >= m) break;
+                        const int j = i + W;
+                        float d = INF;
+                        if (j < n) {
+                            float s = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < NCH; ++k) {
+                                const float4 c = cst[j * NCH + k];
+                                float t = qv[r][k].x - c.x; s = __builtin_fmaf(t, t, s);
+                                t = qv[r][k].y - c.y; s = __builtin_fmaf(t, t, s);
+                                t = qv[r][k].z - c.z; s = __builtin_fmaf(t, t, s);
+                                t = qv[r][k].w - c.w; s = __builtin_fmaf(t, t, s);
+                            }
+                            d = __builtin_sqrtf(s);
                         }
-                        lo = hi = __builtin_sqrtf(sacc);
+                        tdq[i].y = 2.0f * d;
                     }
-#pragma unroll
-                    for (int s = 0; s < SLOTS; ++s)
-                        if (s == (kt >> 6)) { L[s] = lo; U[s] = hi; }
                 }
             }
+            __syncthreads();
+            float V[SLOTS], Y[SLOTS];
+            uint32_t cm[SLOTS];  // running column minimum, >= 0 or +inf (no cell yet): kept as bits
+            int32_t bias[SLOTS]; // bits: 0 for band offsets (k <= 2W), those of +inf past them
+            bool istop[SLOTS];
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
-                const bool cell = ink[s] && (unsigned)jrow[s] < (unsigned)n;
-                // a safe lower bound of the Euclidean point distance, clamped at 0
-                const float safe = __builtin_fmaxf(__builtin_fmaf(-slack, U[s], L[s]), 0.0f);
-                // column minima are >= 0 or +inf: minimum on the bit patterns
-                cm[s] = __uint_as_float(min(__float_as_uint(cmn[s]), __float_as_uint(cell ? safe : INF)));
-                jrow[s] += 1;
+                V[s] = 0.0f; Y[s] = 0.0f; cm[s] = INF_BITS;
+                bias[s] = lane + 64 * s < KB ? 0 : (int32_t)INF_BITS;
+                istop[s] = lane + 64 * s == kt;
             }
-            since = (since + 1 == P) ? 0 : since + 1;
-        }
-        // columns still in the band after the last row
-        float tail = 0.0f;
+            float acc = 0.0f;
+            int exr = 0;         // staged query point of the next exact row (qex[i / P])
+
+            // Row i with t = tdq[i].  GEN: test every lane for a cell of the candidate (first and
+            // last rows); EXACT: an exact row.  Lanes that are not cells carry values that only ever
+            // reach other non-cells (the cell below keeps the column) or the top offset, which
+            // every row overwrites, so every lane evaluates the same arithmetic and only the column
+            // minimum is masked (a safe value raised to +inf).
+            auto row = [&](int i, float2 t, auto gen_tag, auto exact_tag) __attribute__((always_inline)) {
+                constexpr bool GEN = decltype(gen_tag)::value;
+                constexpr bool EXACT = decltype(exact_tag)::value;
+                // row i-1 state of the same column (offset k+1); what lane 63 of the last slot
+                // receives moves down only into non-cells or the top offset
+                float Vn[SLOTS], Yn[SLOTS];
+                uint32_t cmn[SLOTS];
+                if (SLOTS == 1) {
+                    Vn[0] = wave_rol1_f(V[0]);
+                    Yn[0] = wave_rol1_f(Y[0]);
+                    cmn[0] = wave_shl1_u32(0xffffffffu, cm[0]);
+                } else {
+                    Vn[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(V[SLOTS - 1]), 0)), V[0]);
+                    Yn[0] = wave_shl1(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(Y[SLOTS - 1]), 0)), Y[0]);
+                    cmn[0] = wave_shl1_u32((uint32_t)__builtin_amdgcn_readlane((int)cm[SLOTS - 1], 0), cm[0]);
+                    Vn[SLOTS - 1] = wave_shl1(0.0f, V[SLOTS - 1]);
+                    Yn[SLOTS - 1] = wave_shl1(0.0f, Y[SLOTS - 1]);
+                    cmn[SLOTS - 1] = wave_shl1_u32(0xffffffffu, cm[SLOTS - 1]);
+                }
+                // the column at offset 0 of row i-1 is not in row i's band: its minimum is final
+                // (lane 0 holds it and keeps the sum; the other lanes' sums are never read)
+                {
+                    const float lv = __uint_as_float(cm[0]);
+                    const float leaving = GEN ? (cm[0] < INF_BITS ? lv : 0.0f) : lv;
+                    acc = __builtin_fmaf(leaving, leaving, acc);
+                }
+                if (EXACT) {
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const int k = lane + 64 * s;
-            const int j = m - 1 - W + k;
-            if (k < KB && j >= 0 && j < n && cm[s] < INF) tail += cm[s] * cm[s];
-        }
+                    for (int s = 0; s < SLOTS; ++s) {
+                        const int jr = i - W + lane + 64 * s;
+                        const int jc = GEN ? min(max(jr, 0), n - 1) : min(jr, n - 1);
+                        const float4* qrow = qex + exr * NCH;
+                        const float4* crow = cst + jc * NCH;
+                        float sacc = 0.0f;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) tail += __shfl_xor(tail, o);
-        if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)(acc + tail) * defl);
+                        for (int k = 0; k < NCH; ++k) {
+                            const float4 qv = qrow[k], cv = crow[k];
+                            float d;
+                            d = qv.x - cv.x; sacc = __builtin_fmaf(d, d, sacc);
+                            d = qv.y - cv.y; sacc = __builtin_fmaf(d, d, sacc);
+                            d = qv.z - cv.z; sacc = __builtin_fmaf(d, d, sacc);
+                            d = qv.w - cv.w; sacc = __builtin_fmaf(d, d, sacc);
+                        }
+                        float lo, hi;
+                        ti_exact_sides(sacc, lo, hi);
+                        V[s] = lo + hi;
+                        Y[s] = hi + hi;
+                    }
+                    ++exr;
+                } else {
+                    float v[SLOTS], y[SLOTS];
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        v[s] = umax_f(Vn[s], t.x);            // Eqs. 7-8: L + U
+                        y[s] = Yn[s] + t.x;                   // Eq. 8, doubled
+                    }
+                    float tv = t.y, ty = t.y;
+                    if (!TOP) {
+                        // the top cell from its left neighbour (i, j-1) of this row, Eqs. 9-10
+                        // (2 gamma_j of the top column j = i + W is the row's t.y)
+                        const float vsel = (SLOTS > 1 && (kl >> 6) != 0) ? v[SLOTS - 1] : v[0];
+                        const float ysel = (SLOTS > 1 && (kl >> 6) != 0) ? y[SLOTS - 1] : y[0];
+                        const float Vl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vsel), kl & 63));
+                        const float Yl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ysel), kl & 63));
+                        tv = umax_f(Vl, t.y);
+                        ty = Yl + t.y;
+                    }
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        V[s] = istop[s] ? tv : v[s];
+                        Y[s] = istop[s] ? ty : y[s];
+                    }
+                    if (!TOP && GEN && kt == 0) {
+                        // no left neighbour (W = 0): the top cell is exact
+                        const int j = i + W;
+                        if (lane == 0 && j < n) {
+                            float sacc = 0.0f;
+                            for (int p = 0; p < D; ++p) {
+                                const float d = qs[(int64_t)i * D + p] - cs[(int64_t)j * D + p];
+                                sacc = __builtin_fmaf(d, d, sacc);
+                            }
+                            float lo, hi;
+                            ti_exact_sides(sacc, lo, hi);
+                            V[0] = lo + hi;
+                            Y[0] = hi + hi;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    int32_t b = bias[s];
+                    if (GEN) {
+                        const int jr = i - W + lane + 64 * s;
+                        b = (bias[s] == 0 && (unsigned)jr < (unsigned)n) ? 0 : (int32_t)INF_BITS;
+                    }
+                    // a safe lower bound of the Euclidean point distance clamped at 0, as bits: the
+                    // signed maximum with 0 maps every negative value to 0; with the bits of +inf
+                    // (a lane that is no cell) it gives +inf or more, which no column minimum takes
+                    const float sv = __builtin_fmaf(-k1h, Y[s], V[s]);
+                    cm[s] = min(cmn[s], (uint32_t)max(__float_as_int(sv), b));
+                }
+            };
+            using T1 = std::integral_constant<bool, true>;
+            using F0 = std::integral_constant<bool, false>;
+            // Every loop reads the next row's values ahead; `since` counts the rows after the last
+            // exact one (the exact rows are i = 0 and, for P > 0, the multiples of P).
+            int i = 0;
+            int since = 0;
+            float2 tn = tdq[0];
+            auto gen_row = [&]() __attribute__((always_inline)) {
+                const float2 t = tn;
+                tn = tdq[i + 1];
+                if (i == 0 || since == 0) row(i, t, T1{}, T1{});
+                else row(i, t, T1{}, F0{});
+                since = (P > 0 && since + 1 == P) ? 0 : since + 1;
+                ++i;
+            };
+            // non-exact rows up to `stop`: four, two, then one per step, with no test per row
+            auto plain_rows = [&](int stop) __attribute__((always_inline)) {
+                for (; i + 4 <= stop; i += 4) {
+                    const float2 t1 = tdq[i + 1], t2 = tdq[i + 2], t3 = tdq[i + 3];
+                    row(i, tn, F0{}, F0{});
+                    row(i + 1, t1, F0{}, F0{});
+                    row(i + 2, t2, F0{}, F0{});
+                    tn = tdq[i + 4];
+                    row(i + 3, t3, F0{}, F0{});
+                }
+                if (i + 2 <= stop) {
+                    const float2 t1 = tdq[i + 1];
+                    row(i, tn, F0{}, F0{});
+                    tn = tdq[i + 2];
+                    row(i + 1, t1, F0{}, F0{});
+                    i += 2;
+                }
+                if (i < stop) {
+                    const float2 t = tn;
+                    tn = tdq[i + 1];
+                    row(i, t, F0{}, F0{});
+                    ++i;
+                }
+            };
+            while (i < ib) gen_row();
+            if (i < ie) {
+                // between the edges: blocks of an exact row and the P - 1 rows after it
+                int next = P > 0 ? i + (since == 0 ? 0 : P - since) : ie;   // the next exact row
+                plain_rows(min(next, ie));
+                while (i < ie) {
+                    const float2 t = tn;
+                    tn = tdq[i + 1];
+                    row(i, t, F0{}, T1{});
+                    ++i;
+                    plain_rows(min(i + P - 1, ie));
+                }
+                since = P > 0 ? i % P : 1;
+            }
+            while (i < m) gen_row();
+            // columns still in the band after the last row
+            float tail = 0.0f;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int k = lane + 64 * s;
+                const int j = m - 1 - W + k;
+                if (k < KB && j >= 0 && j < n && cm[s] < INF_BITS) {
+                    const float v = __uint_as_float(cm[s]);
+                    tail += v * v;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) tail += __shfl_xor(tail, o);
+            if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)(acc + tail) * defl);
+            ++evaluated;
+        }
     }
+    if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
 }
 
 // ---------------------------------------------------------------- routing
@@ -671,7 +775,7 @@ hipError_t launch_lb_pc(const PcArgs& a, int nblocks, hipStream_t s) {
 size_t ti_lds_bytes(int m, int n, int D, int P, int W) {
     if (2 * W + 1 > 2 * kWave) return ti_cols_lds_bytes(m);
     const size_t nch = (size_t)nch_pad(D);
-    return ((size_t)n * nch + (size_t)ti_exact_rows(m, P) * nch) * 16 + (size_t)(m + 1) * 8 + (size_t)n * 4 + 16;
+    return ((size_t)n * nch + (size_t)ti_exact_rows(m, P) * nch) * 16 + (size_t)(m + 2) * 8 + 16;
 }
 
 template <int SLOTS, int NCH>

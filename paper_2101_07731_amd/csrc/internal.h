@@ -142,7 +142,7 @@ constexpr int kNumCounters = 8;
 constexpr int kNumStats = 16;
 enum {
     kStPrunedMv = 0, kStPrunedPc, kStPrunedTi, kStDtwStarted, kStDtwAbandoned, kStRescored,
-    kStCells
+    kStCells, kStEvalPc, kStEvalTi
 };
 
 // Device pointers of one search (uniform lengths).
@@ -321,6 +321,7 @@ struct PcArgs {
     const unsigned long long* key;   // null: dense mode (no gate, no early stop)
     const float* lb_mv;        // [nq][nc] (search mode)
     double e2, keep;
+    unsigned long long* evaluated;   // null, or a count of the pairs whose bound was evaluated
 };
 
 struct TiArgs {
@@ -338,6 +339,7 @@ struct TiArgs {
     int32_t* counter;
     const unsigned long long* key;
     double e2;
+    unsigned long long* evaluated;   // null, or a count of the pairs whose bound was evaluated
 };
 
 struct RouteArgs {

@@ -4,10 +4,10 @@
 // Column mapping: a wave walks the candidate in blocks of 64 consecutive
 // columns, lane l owning column j = j0 + l, and runs the rows of the
 // block's band, max(0, j0 - W) .. min(m - 1, j0 + 63 + W), wave-uniformly.
-// A column keeps its (L, U) pair and its running minimum of max(0, L) in
-// its own lane from row to row, so Eqs. 7-8 (row i-1 to row i on the same
-// column) need no exchange between lanes; a lane takes part in rows
-// j - W .. j + W only.
+// A column keeps its state (V = L + U, U) and its running minimum of
+// max(0, L) in its own lane from row to row, so Eqs. 7-8 (row i-1 to row i
+// on the same column: V' = max(V, 2d), U' = U + d) need no exchange between
+// lanes; a lane takes part in rows j - W .. j + W only.
 //  * Exact rows (i = 0, and i mod P = 0 for P > 0) are wave-uniform: the
 //    query point q_i is read with scalar loads and the lane's candidate
 //    point c_j stays in registers for the whole block.
@@ -17,8 +17,9 @@
 //    (i, j - 1) in the same row, which is lane l - 1 (for lane 0, the
 //    previous block's last column, kept from that block's row j0 - W).
 // Every cell sees the same float32 operations in the same order as in
-// k_lb_ti, so the per-cell values and the rounding allowance are the same;
-// only the order of the final sum differs (covered by the deflation).
+// k_lb_ti (which keeps 2U instead of U, an exact scaling), so the per-cell
+// values and the rounding allowance are the same; only the order of the
+// final sum differs (covered by the deflation).
 //
 // Rows run in three phases per block: columns starting (some lanes before
 // their first row), every lane inside its band (no per-lane tests), and
@@ -27,10 +28,11 @@
 
 namespace tcdtw {
 
-extern __shared__ float2 lds_ti_cols[];
+extern __shared__ float4 lds_ti_cols[];
 
+// sum of squares of q - c (components in index order)
 template <int NCH>
-__device__ __forceinline__ float exact_dist(const const_as_float* qp, int D, const float4 (&c)[NCH]) {
+__device__ __forceinline__ float exact_sq(const const_as_float* qp, int D, const float4 (&c)[NCH]) {
     float s = 0.0f;
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
@@ -43,138 +45,152 @@ __device__ __forceinline__ float exact_dist(const const_as_float* qp, int D, con
             s = __builtin_fmaf(d, d, s);
         }
     }
-    return __builtin_sqrtf(s);
+    return s;
 }
 
 template <bool TOP, int NCH>
 __global__ __launch_bounds__(64) void k_lb_ti_cols(TiArgs a) {
     const int lane = threadIdx.x;
     const int m = a.m, n = a.n, D = a.D, W = a.W, P = a.P;
-    float2* tdq = lds_ti_cols;                         // [m] (query step, TOP distance) of each row
+    float4* tdq = lds_ti_cols;                         // [m] (d_i, 2 d_i, TOP distance t_i, 2 t_i) per row
     const float INF = __builtin_inff();
     const uint32_t INF_BITS = 0x7f800000u;
     const double u = 1.0 / 16777216.0;
     // longest recursion chain since an exact value (rows, plus one top step per row without TOP)
     const int rmax = P > 0 ? (TOP ? P - 1 : 2 * (P - 1) + 1) : (TOP ? m : 2 * m + 1);
-    const float slack = (float)((0.5 * D + 5.0 + rmax) * u * 1.02);
+    // safe value V - (1 + s) U with s = (1.5 D + 20 + r_max) u 1.02, the factor rounded up
+    const float k1 = rup(1.0 + (1.5 * D + 20.0 + rmax) * u * 1.02);
     const double defl = 1.0 - (double)(n + 5) * u * 1.001;
+    unsigned long long evaluated = 0;   // pairs this wave evaluated
+    const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.nq]);
+    const int B = item_batch(total);
     for (;;) {
-        const int item = wave_next_item(a.counter);
-        if (item >= a.prefix[a.nq]) break;
-        const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
-        const int e = item - __builtin_amdgcn_readfirstlane(a.prefix[q]);
-        const int ref = a.in_list ? __builtin_amdgcn_readfirstlane((int)a.in_list[(int64_t)q * a.cap + e]) : e;
-        if (a.key) {
-            // selective deployment: only pairs whose bound so far exceeds e^2 bsf
-            const float cur = a.lb_in[(int64_t)q * a.cap + e];
-            const float bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
-            if (wave_uniform(!((double)cur > a.e2 * (double)bsf))) {
-                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;
-                continue;
-            }
-        }
-        const float* qs = a.Q + (int64_t)q * m * D;
-        const float* cs = a.C + (int64_t)ref * n * D;
-        const float* gam = a.gamma + (int64_t)ref * n;
-        const bool qvec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(qs) & 15) == 0;
-        const bool cvec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(cs) & 15) == 0;
-        __syncthreads();
-        for (int i = lane; i < m; i += kWave) {
-            float top = INF;
-            if (TOP && i + W < n) {
-                float4 qv[NCH], cv[NCH];
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) {
-                    qv[k] = point_chunk(qs + (int64_t)i * D, k, D, qvec);
-                    cv[k] = point_chunk(cs + (int64_t)(i + W) * D, k, D, cvec);
+        const int base = wave_next_batch(a.counter, B);
+        if (base >= total) break;
+        const int bend = min(base + B, total);
+        for (int item = base; item < bend; ++item) {
+            const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
+            const int e = item - __builtin_amdgcn_readfirstlane(a.prefix[q]);
+            const int ref = a.in_list ? __builtin_amdgcn_readfirstlane((int)a.in_list[(int64_t)q * a.cap + e]) : e;
+            if (a.key) {
+                // selective deployment: only pairs whose bound so far exceeds e^2 bsf
+                const float cur = a.lb_in[(int64_t)q * a.cap + e];
+                const float bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
+                if (wave_uniform(!((double)cur > a.e2 * (double)bsf))) {
+                    if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;
+                    continue;
                 }
-                float s = 0.0f;
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) {
-                    float t;
-                    t = qv[k].x - cv[k].x; s = __builtin_fmaf(t, t, s);
-                    t = qv[k].y - cv[k].y; s = __builtin_fmaf(t, t, s);
-                    t = qv[k].z - cv[k].z; s = __builtin_fmaf(t, t, s);
-                    t = qv[k].w - cv[k].w; s = __builtin_fmaf(t, t, s);
-                }
-                top = __builtin_sqrtf(s);
             }
-            tdq[i] = make_float2(a.qstep[(int64_t)q * m + i], top);
-        }
-        __syncthreads();
-        const const_as_float* qsc = (const const_as_float*)qs;
-        float acc = 0.0f;
-        float carryL = 0.0f, carryU = 0.0f;   // column j0 - 1 at row j0 - W (for Eqs. 9-10)
-        for (int j0 = 0; j0 < n; j0 += kWave) {
-            const int j = j0 + lane;
-            const bool col = j < n;
-            float4 c[NCH];
+            const float* qs = a.Q + (int64_t)q * m * D;
+            const float* cs = a.C + (int64_t)ref * n * D;
+            const float* gam = a.gamma + (int64_t)ref * n;
+            const bool qvec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(qs) & 15) == 0;
+            const bool cvec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(cs) & 15) == 0;
+            __syncthreads();
+            for (int i = lane; i < m; i += kWave) {
+                float top = INF;
+                if (TOP && i + W < n) {
+                    float4 qv[NCH], cv[NCH];
 #pragma unroll
-            for (int k = 0; k < NCH; ++k) c[k] = point_chunk(cs + (int64_t)min(j, n - 1) * D, k, D, cvec);
-            const float gj = (!TOP && col && j >= 1) ? gam[j] : 0.0f;
-            float L = 0.0f, U = 0.0f;
-            uint32_t cm = INF_BITS;           // running minimum of the column, >= 0 or +inf: min on the bits
-            const int ilo = max(0, j0 - W), ihi = min(m - 1, j0 + kWave - 1 + W);
-            const int jlast = min(n, j0 + kWave) - 1;  // the block's last column
-            // rows where columns start (up to the last column's first row), where every
-            // column of the block is inside its band, and where columns end
-            const int a_end = min(ihi, jlast - W);
-            const int b_end = min(ihi, j0 + W);
-            const int carry_row = j0 + kWave - W;      // the next block's first top row
-            int since = P > 0 ? ilo % P : 1;
-            float2 t = tdq[ilo];
-            int i = ilo;
-            auto step = [&](bool generic) __attribute__((always_inline)) {
-                const float di = t.x, topv = t.y;
-                if (i < ihi) t = tdq[i + 1];           // one row ahead
-                const bool exact = (i == 0) || (P > 0 && since == 0);
-                const int r = i - (j - W);            // row index inside the column's band, 0 .. 2W
-                if (exact) {
-                    L = U = exact_dist<NCH>(qsc + (int64_t)i * D, D, c);
-                } else {
-                    const float lo = __builtin_fmaxf(L - di, di - U);   // Eq. 7
-                    const float hi = U + di;                            // Eq. 8
-                    if (generic && TOP) {
-                        L = r == 0 ? topv : lo;
-                        U = r == 0 ? topv : hi;
-                    } else {
-                        L = lo;
-                        U = hi;
+                    for (int k = 0; k < NCH; ++k) {
+                        qv[k] = point_chunk(qs + (int64_t)i * D, k, D, qvec);
+                        cv[k] = point_chunk(cs + (int64_t)(i + W) * D, k, D, cvec);
                     }
-                    if (generic && !TOP) {
-                        // the top cell from its left neighbour in the same row, Eqs. 9-10
-                        const float Ll = wave_shr1(carryL, L), Ul = wave_shr1(carryU, U);
-                        if (r == 0) {
-                            L = __builtin_fmaxf(Ll - gj, gj - Ul);
-                            U = Ul + gj;
+                    float s = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < NCH; ++k) {
+                        float t;
+                        t = qv[k].x - cv[k].x; s = __builtin_fmaf(t, t, s);
+                        t = qv[k].y - cv[k].y; s = __builtin_fmaf(t, t, s);
+                        t = qv[k].z - cv[k].z; s = __builtin_fmaf(t, t, s);
+                        t = qv[k].w - cv[k].w; s = __builtin_fmaf(t, t, s);
+                    }
+                    top = __builtin_sqrtf(s);
+                }
+                const float di = a.qstep[(int64_t)q * m + i];
+                tdq[i] = make_float4(di, 2.0f * di, top, 2.0f * top);
+            }
+            __syncthreads();
+            const const_as_float* qsc = (const const_as_float*)qs;
+            float acc = 0.0f;
+            float carryV = 0.0f, carryU = 0.0f;   // column j0 - 1 at row j0 - W (for Eqs. 9-10)
+            for (int j0 = 0; j0 < n; j0 += kWave) {
+                const int j = j0 + lane;
+                const bool col = j < n;
+                float4 c[NCH];
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) c[k] = point_chunk(cs + (int64_t)min(j, n - 1) * D, k, D, cvec);
+                const float gj = (!TOP && col && j >= 1) ? gam[j] : 0.0f;
+                const float gj2 = 2.0f * gj;
+                float V = 0.0f, U = 0.0f;
+                uint32_t cm = INF_BITS;           // running minimum of the column, >= 0 or +inf: min on the bits
+                const int ilo = max(0, j0 - W), ihi = min(m - 1, j0 + kWave - 1 + W);
+                const int jlast = min(n, j0 + kWave) - 1;  // the block's last column
+                // rows where columns start (up to the last column's first row), where every
+                // column of the block is inside its band, and where columns end
+                const int a_end = min(ihi, jlast - W);
+                const int b_end = min(ihi, j0 + W);
+                const int carry_row = j0 + kWave - W;      // the next block's first top row
+                int since = P > 0 ? ilo % P : 1;
+                float4 t = tdq[ilo];
+                int i = ilo;
+                auto step = [&](bool generic) __attribute__((always_inline)) {
+                    const float4 tc = t;
+                    if (i < ihi) t = tdq[i + 1];           // one row ahead
+                    const bool exact = (i == 0) || (P > 0 && since == 0);
+                    const int r = i - (j - W);            // row index inside the column's band, 0 .. 2W
+                    if (exact) {
+                        float lo;
+                        ti_exact_sides(exact_sq<NCH>(qsc + (int64_t)i * D, D, c), lo, U);
+                        V = lo + U;
+                    } else {
+                        const float v = umax_f(V, tc.y);            // Eqs. 7-8: L + U
+                        const float w = U + tc.x;                   // Eq. 8
+                        if (generic && TOP) {
+                            V = r == 0 ? tc.w : v;
+                            U = r == 0 ? tc.z : w;
+                        } else {
+                            V = v;
+                            U = w;
+                        }
+                        if (generic && !TOP) {
+                            // the top cell from its left neighbour in the same row, Eqs. 9-10
+                            const float Vl = wave_shr1(carryV, V), Ul = wave_shr1(carryU, U);
+                            if (r == 0) {
+                                V = umax_f(Vl, gj2);
+                                U = Ul + gj;
+                            }
                         }
                     }
+                    // the safe value clamped at 0 on its bits (negative values have negative bits)
+                    const uint32_t safe = (uint32_t)max(__float_as_int(__builtin_fmaf(-k1, U, V)), 0);
+                    const bool act = !generic || (col && (unsigned)r <= (unsigned)(2 * W));
+                    cm = min(cm, act ? safe : INF_BITS);
+                    if (!TOP && i == carry_row) {
+                        carryV = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(V), kWave - 1));
+                        carryU = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(U), kWave - 1));
+                    }
+                    since = (since + 1 == P) ? 0 : since + 1;
+                };
+                for (; i <= a_end; ++i) step(true);
+                if (jlast == j0 + kWave - 1)
+                    for (; i <= b_end; ++i) step(false);
+                for (; i <= ihi; ++i) step(true);
+                if (col && cm < INF_BITS) {
+                    const float v = __uint_as_float(cm);
+                    acc = __builtin_fmaf(v, v, acc);
                 }
-                const float safe = __builtin_fmaxf(__builtin_fmaf(-slack, U, L), 0.0f);
-                const bool act = !generic || (col && (unsigned)r <= (unsigned)(2 * W));
-                cm = min(cm, act ? __float_as_uint(safe) : INF_BITS);
-                if (!TOP && i == carry_row) {
-                    carryL = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L), kWave - 1));
-                    carryU = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(U), kWave - 1));
-                }
-                since = (since + 1 == P) ? 0 : since + 1;
-            };
-            for (; i <= a_end; ++i) step(true);
-            if (jlast == j0 + kWave - 1)
-                for (; i <= b_end; ++i) step(false);
-            for (; i <= ihi; ++i) step(true);
-            if (col && cm != INF_BITS) {
-                const float v = __uint_as_float(cm);
-                acc = __builtin_fmaf(v, v, acc);
             }
-        }
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
+            for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+            if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
+            ++evaluated;
+        }
     }
+    if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
 }
 
-size_t ti_cols_lds_bytes(int m) { return (size_t)m * 8 + 16; }
+size_t ti_cols_lds_bytes(int m) { return (size_t)m * 16 + 16; }
 
 template <bool TOP>
 static hipError_t launch_ti_cols_top(const TiArgs& a, int nblocks, hipStream_t s) {

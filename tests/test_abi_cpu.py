@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     lib = L.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.tc_dtw_abi_version() == 6
+    assert lib.tc_dtw_abi_version() == 7
 
 
 def _batch(count=2, dim=3, ulen=8, data=0x1000):

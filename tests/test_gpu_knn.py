@@ -356,6 +356,34 @@ def test_lb_ti_dense_matrix(dev, P, top, frac):
     np.testing.assert_array_less(lo - 1e-30, lb + 1e-30)
 
 
+TI_SHAPES = [(40, 40, 0, 3), (40, 40, 1, 6), (50, 64, 7, 6), (64, 50, 3, 13), (12, 12, 5, 6), (8, 8, 7, 4),
+             (96, 96, 31, 8), (96, 96, 32, 8), (150, 150, 63, 5)]
+
+
+@pytest.mark.parametrize("P,top", [(5, 1), (5, 0), (1, 0), (0, 0), (0, 1), (2, 1), (7, 0)])
+@pytest.mark.parametrize("shape", TI_SHAPES, ids=["m%d_n%d_w%d_d%d" % s for s in TI_SHAPES])
+def test_lb_ti_band_offset_shapes(dev, P, top, shape):
+    """The one-wave LB_TI kernel (bands of up to 127 offsets) over the shapes
+    that decide its row phases: W = 0 and 1, m < n and m > n (W_eff = |m - n|),
+    series too short for rows with every offset inside the candidate, one and
+    two offsets per lane, and point widths of one to four chunks; against the
+    oracle, never above it and never below the per-cell allowance."""
+    from paper_2101_07731_amd import search, synth
+    m, n, w, D = shape
+    Q, Cs = synth.cascade_knn(nq=4, nc=12, T=max(m, n), D=D, seed=43 + m + n + w)
+    Q = np.ascontiguousarray(Q[:, :m])
+    Cs = np.ascontiguousarray(Cs[:, :n])
+    W = O.window_eff(m, n, w)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_ti shapes", P, top, shape, "W", W)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="ti", window=w, frac=None, ti_period=P,
+                             ti_top=top).cpu().numpy().astype(np.float64)
+    ref = np.array([[O.lb_ti(q, c, W, P=P, top=top) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12) + 1e-30)
+    lo = np.array([[ti_lower_allowance(q, c, W, P, top) for c in Cs] for q in Q])
+    np.testing.assert_array_less(lo - 1e-30, lb + 1e-30)
+
+
 @pytest.mark.parametrize("bounds", ["mv+pc", "mv+ti", "mv+pc+ti"])
 @pytest.mark.parametrize("frac", [(1, 20), (1, 10), (1, 5)])
 def test_cascade_with_advanced_bounds(dev, bounds, frac):

@@ -9,8 +9,9 @@ def ti_lower_allowance(q, c, W, P, top):
     """The smallest value the float32 LB_TI may return for (q, c): per band
     cell the oracle's float64 triangle bounds (L, U) with L lowered by twice
     the kernel's allowance s U (the allowance it subtracts, plus at most as
-    much float32 drift of the recursion), s = (D/2 + 5 + r_max) u 1.02 with
-    r_max the longest chain of recursion steps since an exact value; the
+    much float32 drift of the recursion in its (V = L + U, U) form),
+    s = (1.5 D + 20 + r_max) u 1.02 with r_max the longest chain of
+    recursion steps since an exact value; the
     column minima of max(0, .) squared and summed, then lowered by the
     float32 summation error and the kernel's final deflation, 2 (n + 5) u."""
     m, D = q.shape
@@ -20,7 +21,7 @@ def ti_lower_allowance(q, c, W, P, top):
         rmax = P - 1 if top else 2 * (P - 1) + 1
     else:
         rmax = m if top else 2 * m + 1
-    s = (0.5 * D + 5.0 + rmax) * u * 1.02
+    s = (1.5 * D + 20.0 + rmax) * u * 1.02
     Lo, Hi = O.ti_cells(q, c, W, P=P, top=top)
     cell = np.maximum(Lo - 2.0 * 1.01 * s * Hi, 0.0)
     col = np.nanmin(np.where(np.isnan(Lo), np.inf, cell), axis=0)
