@@ -147,7 +147,7 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
     const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
     unsigned long long evaluated = 0;   // pairs this wave evaluated
     const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.nq]);
-    const int B = item_batch(total);
+    const int B = item_batch(total, 16);
     for (;;) {
         const int base = wave_next_batch(a.counter, B);
         if (base >= total) break;
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     const int ie = (!TOP && W == 0) ? ib : max(ib, min(m, n - W));
     unsigned long long evaluated = 0;   // pairs this wave evaluated
     const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.nq]);
-    const int B = item_batch(total);
+    const int B = item_batch(total, 16);
     for (;;) {
         const int base = wave_next_batch(a.counter, B);
         if (base >= total) break;

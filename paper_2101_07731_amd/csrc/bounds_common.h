@@ -58,12 +58,13 @@ __device__ __forceinline__ uint32_t wave_shl1_u32(uint32_t old, uint32_t v) {
 }
 
 // Persistent one-wave loops over many small work items (one pair each) take
-// them in batches of consecutive items, one atomic per batch: thousands of
-// waves taking single items from one counter serialise on it.  About 16
+// them in batches of B consecutive items, one atomic per batch: thousands of
+// waves taking single items from one counter serialise on it.  About `per`
 // batches per wave keep the end balanced.
-__device__ __forceinline__ int item_batch(int total) {
-    return max(1, min(32, total / ((int)gridDim.x * 16)));
+__device__ __forceinline__ int item_batch(int total, int per) {
+    return max(1, min(32, total / ((int)gridDim.x * per)));
 }
+// First item of the wave's next batch of B (same rules as wave_next_item).
 __device__ __forceinline__ int wave_next_batch(int* counter, int B) {
     int v = 0;
     if ((threadIdx.x & 63) == 0) v = atomicAdd(counter, B);

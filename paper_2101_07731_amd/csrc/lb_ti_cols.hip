@@ -4,9 +4,9 @@
 // Column mapping: a wave walks the candidate in blocks of 64 consecutive
 // columns, lane l owning column j = j0 + l, and runs the rows of the
 // block's band, max(0, j0 - W) .. min(m - 1, j0 + 63 + W), wave-uniformly.
-// A column keeps its state (V = L + U, U) and its running minimum of
+// A column keeps its state (V, Y) = (L + U, 2U) and its running minimum of
 // max(0, L) in its own lane from row to row, so Eqs. 7-8 (row i-1 to row i
-// on the same column: V' = max(V, 2d), U' = U + d) need no exchange between
+// on the same column: V' = max(V, 2d), Y' = Y + 2d) need no exchange between
 // lanes; a lane takes part in rows j - W .. j + W only.
 //  * Exact rows (i = 0, and i mod P = 0 for P > 0) are wave-uniform: the
 //    query point q_i is read with scalar loads and the lane's candidate
@@ -17,9 +17,8 @@
 //    (i, j - 1) in the same row, which is lane l - 1 (for lane 0, the
 //    previous block's last column, kept from that block's row j0 - W).
 // Every cell sees the same float32 operations in the same order as in
-// k_lb_ti (which keeps 2U instead of U, an exact scaling), so the per-cell
-// values and the rounding allowance are the same; only the order of the
-// final sum differs (covered by the deflation).
+// k_lb_ti, so the per-cell values and the rounding allowance are the same;
+// only the order of the final sum differs (covered by the deflation).
 //
 // Rows run in three phases per block: columns starting (some lanes before
 // their first row), every lane inside its band (no per-lane tests), and
@@ -28,7 +27,7 @@
 
 namespace tcdtw {
 
-extern __shared__ float4 lds_ti_cols[];
+extern __shared__ float2 lds_ti_cols[];
 
 // sum of squares of q - c (components in index order)
 template <int NCH>
@@ -52,18 +51,18 @@ template <bool TOP, int NCH>
 __global__ __launch_bounds__(64) void k_lb_ti_cols(TiArgs a) {
     const int lane = threadIdx.x;
     const int m = a.m, n = a.n, D = a.D, W = a.W, P = a.P;
-    float4* tdq = lds_ti_cols;                         // [m] (d_i, 2 d_i, TOP distance t_i, 2 t_i) per row
+    float2* tdq = lds_ti_cols;                         // [m] (2 d_i, 2 t_i) per row, t_i the TOP distance
     const float INF = __builtin_inff();
     const uint32_t INF_BITS = 0x7f800000u;
     const double u = 1.0 / 16777216.0;
     // longest recursion chain since an exact value (rows, plus one top step per row without TOP)
     const int rmax = P > 0 ? (TOP ? P - 1 : 2 * (P - 1) + 1) : (TOP ? m : 2 * m + 1);
-    // safe value V - (1 + s) U with s = (1.5 D + 20 + r_max) u 1.02, the factor rounded up
-    const float k1 = rup(1.0 + (1.5 * D + 20.0 + rmax) * u * 1.02);
+    // safe value V - (1 + s) Y / 2 with s = (1.5 D + 20 + r_max) u 1.02, the factor rounded up
+    const float k1h = 0.5f * rup(1.0 + (1.5 * D + 20.0 + rmax) * u * 1.02);
     const double defl = 1.0 - (double)(n + 5) * u * 1.001;
     unsigned long long evaluated = 0;   // pairs this wave evaluated
     const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.nq]);
-    const int B = item_batch(total);
+    const int B = item_batch(total, 16);
     for (;;) {
         const int base = wave_next_batch(a.counter, B);
         if (base >= total) break;
@@ -108,12 +107,12 @@ __global__ __launch_bounds__(64) void k_lb_ti_cols(TiArgs a) {
                     top = __builtin_sqrtf(s);
                 }
                 const float di = a.qstep[(int64_t)q * m + i];
-                tdq[i] = make_float4(di, 2.0f * di, top, 2.0f * top);
+                tdq[i] = make_float2(2.0f * di, 2.0f * top);
             }
             __syncthreads();
             const const_as_float* qsc = (const const_as_float*)qs;
             float acc = 0.0f;
-            float carryV = 0.0f, carryU = 0.0f;   // column j0 - 1 at row j0 - W (for Eqs. 9-10)
+            float carryV = 0.0f, carryY = 0.0f;   // column j0 - 1 at row j0 - W (for Eqs. 9-10)
             for (int j0 = 0; j0 < n; j0 += kWave) {
                 const int j = j0 + lane;
                 const bool col = j < n;
@@ -122,7 +121,7 @@ __global__ __launch_bounds__(64) void k_lb_ti_cols(TiArgs a) {
                 for (int k = 0; k < NCH; ++k) c[k] = point_chunk(cs + (int64_t)min(j, n - 1) * D, k, D, cvec);
                 const float gj = (!TOP && col && j >= 1) ? gam[j] : 0.0f;
                 const float gj2 = 2.0f * gj;
-                float V = 0.0f, U = 0.0f;
+                float V = 0.0f, Y = 0.0f;
                 uint32_t cm = INF_BITS;           // running minimum of the column, >= 0 or +inf: min on the bits
                 const int ilo = max(0, j0 - W), ihi = min(m - 1, j0 + kWave - 1 + W);
                 const int jlast = min(n, j0 + kWave) - 1;  // the block's last column
@@ -132,49 +131,98 @@ __global__ __launch_bounds__(64) void k_lb_ti_cols(TiArgs a) {
                 const int b_end = min(ihi, j0 + W);
                 const int carry_row = j0 + kWave - W;      // the next block's first top row
                 int since = P > 0 ? ilo % P : 1;
-                float4 t = tdq[ilo];
+                float2 t = tdq[ilo];
                 int i = ilo;
                 auto step = [&](bool generic) __attribute__((always_inline)) {
-                    const float4 tc = t;
+                    const float2 tc = t;
                     if (i < ihi) t = tdq[i + 1];           // one row ahead
                     const bool exact = (i == 0) || (P > 0 && since == 0);
                     const int r = i - (j - W);            // row index inside the column's band, 0 .. 2W
                     if (exact) {
-                        float lo;
-                        ti_exact_sides(exact_sq<NCH>(qsc + (int64_t)i * D, D, c), lo, U);
-                        V = lo + U;
+                        float lo, hi;
+                        ti_exact_sides(exact_sq<NCH>(qsc + (int64_t)i * D, D, c), lo, hi);
+                        V = lo + hi;
+                        Y = hi + hi;
                     } else {
-                        const float v = umax_f(V, tc.y);            // Eqs. 7-8: L + U
-                        const float w = U + tc.x;                   // Eq. 8
+                        const float v = umax_f(V, tc.x);            // Eqs. 7-8: L + U
+                        const float y = Y + tc.x;                   // Eq. 8, doubled
                         if (generic && TOP) {
-                            V = r == 0 ? tc.w : v;
-                            U = r == 0 ? tc.z : w;
+                            V = r == 0 ? tc.y : v;
+                            Y = r == 0 ? tc.y : y;
                         } else {
                             V = v;
-                            U = w;
+                            Y = y;
                         }
                         if (generic && !TOP) {
                             // the top cell from its left neighbour in the same row, Eqs. 9-10
-                            const float Vl = wave_shr1(carryV, V), Ul = wave_shr1(carryU, U);
+                            const float Vl = wave_shr1(carryV, V), Yl = wave_shr1(carryY, Y);
                             if (r == 0) {
                                 V = umax_f(Vl, gj2);
-                                U = Ul + gj;
+                                Y = Yl + gj2;
                             }
                         }
                     }
                     // the safe value clamped at 0 on its bits (negative values have negative bits)
-                    const uint32_t safe = (uint32_t)max(__float_as_int(__builtin_fmaf(-k1, U, V)), 0);
+                    const uint32_t safe = (uint32_t)max(__float_as_int(__builtin_fmaf(-k1h, Y, V)), 0);
                     const bool act = !generic || (col && (unsigned)r <= (unsigned)(2 * W));
                     cm = min(cm, act ? safe : INF_BITS);
                     if (!TOP && i == carry_row) {
                         carryV = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(V), kWave - 1));
-                        carryU = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(U), kWave - 1));
+                        carryY = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Y), kWave - 1));
                     }
                     since = (since + 1 == P) ? 0 : since + 1;
                 };
+                // a row of the full band: every lane is inside its column's band
+                auto plain = [&](float2 tc) __attribute__((always_inline)) {
+                    V = umax_f(V, tc.x);                            // Eqs. 7-8: L + U
+                    Y = Y + tc.x;                                   // Eq. 8, doubled
+                    cm = min(cm, (uint32_t)max(__float_as_int(__builtin_fmaf(-k1h, Y, V)), 0));
+                };
+                // plain rows up to `stop` (exclusive): four, two, then one per step
+                auto plain_rows = [&](int stop) __attribute__((always_inline)) {
+                    for (; i + 4 <= stop; i += 4) {
+                        const float2 t1 = tdq[i + 1], t2 = tdq[i + 2], t3 = tdq[i + 3];
+                        plain(t);
+                        plain(t1);
+                        plain(t2);
+                        t = tdq[i + 4];
+                        plain(t3);
+                    }
+                    if (i + 2 <= stop) {
+                        const float2 t1 = tdq[i + 1];
+                        plain(t);
+                        t = tdq[i + 2];
+                        plain(t1);
+                        i += 2;
+                    }
+                    if (i < stop) {
+                        const float2 tc = t;
+                        t = tdq[i + 1];
+                        plain(tc);
+                        ++i;
+                    }
+                };
                 for (; i <= a_end; ++i) step(true);
-                if (jlast == j0 + kWave - 1)
-                    for (; i <= b_end; ++i) step(false);
+                if (jlast == j0 + kWave - 1 && i <= b_end) {
+                    // the first row of the full band is the carry row (Eqs. 9-10 without TOP)
+                    step(true);
+                    ++i;
+                    // then blocks of an exact row and the plain rows up to the next one
+                    const int e1 = b_end + 1;
+                    const int next = (i == 0 || (P > 0 && since == 0)) ? i : (P > 0 ? i + P - since : e1);
+                    plain_rows(min(next, e1));
+                    while (i < e1) {
+                        t = tdq[i + 1];
+                        float lo, hi;
+                        ti_exact_sides(exact_sq<NCH>(qsc + (int64_t)i * D, D, c), lo, hi);
+                        V = lo + hi;
+                        Y = hi + hi;
+                        cm = min(cm, (uint32_t)max(__float_as_int(__builtin_fmaf(-k1h, Y, V)), 0));
+                        ++i;
+                        plain_rows(P > 0 ? min(i + P - 1, e1) : e1);
+                    }
+                    since = P > 0 ? i % P : 1;
+                }
                 for (; i <= ihi; ++i) step(true);
                 if (col && cm < INF_BITS) {
                     const float v = __uint_as_float(cm);
@@ -190,7 +238,7 @@ __global__ __launch_bounds__(64) void k_lb_ti_cols(TiArgs a) {
     if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
 }
 
-size_t ti_cols_lds_bytes(int m) { return (size_t)m * 16 + 16; }
+size_t ti_cols_lds_bytes(int m) { return (size_t)(m + 2) * 8 + 16; }
 
 template <bool TOP>
 static hipError_t launch_ti_cols_top(const TiArgs& a, int nblocks, hipStream_t s) {
