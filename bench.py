@@ -278,6 +278,12 @@ def extra_long_knn(dev, reps=3):
                      "pruned_mv": st["pruned_mv"], "pruned_pc": st["pruned_pc"], "pruned_ti": st["pruned_ti"],
                      "dtw_gcups": round(st["cells"] / (st["stage_ms"][5] * 1e-3) / 1e9, 2),
                      "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, st["stage_ms"])}}
+        if "ti" in bounds:
+            # per-pair cost of LB_TI against the survivors' DTW (seeds, 4 per query, run apart)
+            us_ti = st["lb_ti_ms"] * 1e3 / max(1, st["evaluated_ti"])
+            us_dtw = st["stage_ms"][5] * 1e3 / max(1, st["dtw_started"] - 4 * Q.shape[0])
+            out[name].update({"evaluated_ti": st["evaluated_ti"], "stage_ms_lb_ti": round(st["lb_ti_ms"], 3),
+                              "lb_ti_per_pair_vs_dtw": round(us_ti / us_dtw, 3)})
     return out
 
 

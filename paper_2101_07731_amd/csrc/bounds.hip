@@ -374,7 +374,8 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
     const int lane = threadIdx.x;
     const int m = a.m, n = a.n, D = a.D, W = a.W, P = a.P;
     // LDS, staged per pair so that the row loop never waits on global memory:
-    float4* cst = lds4;                                // [n][NCH] candidate points
+    // [NCH][n] candidate points, chunk-major: a row's lanes read consecutive 16-byte words
+    float4* cst = lds4;
     float4* qex = cst + (int64_t)n * NCH;              // [exact rows][NCH] query points of the exact rows
     // [m + 2] per row i: (2 d_i, 2 t_i) with t_i the TOP distance e(q_i, c_{i+W}) or, without
     // TOP, gamma_{i+W}; entries m and m + 1 are padding, read ahead past the last row
@@ -440,7 +441,22 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 }
                 if (lane < 2) tdq[m + lane] = make_float2(0.0f, INF);
             }
-            stage_point_chunks<NCH>(cst, cs, n, 1, D, vec, lane);
+            {
+                // chunk-major staging: word t holds chunk t / n of point t % n
+                const int total = n * NCH;
+                auto at = [&](int t) __attribute__((always_inline)) {
+                    return point_chunk(cs + (int64_t)(t % n) * D, t / n, D, vec);
+                };
+                int t = lane;
+                for (; t + 7 * kWave < total; t += 8 * kWave) {
+                    float4 v[8];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v[r] = at(t + r * kWave);
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) cst[t + r * kWave] = v[r];
+                }
+                for (; t < total; t += kWave) cst[t] = at(t);
+            }
             // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
             stage_point_chunks<NCH>(qex, qs, ti_exact_rows(m, P), P > 0 ? P : 0, D, vec, lane);
             if (TOP) {
@@ -467,7 +483,7 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                             float s = 0.0f;
 #pragma unroll
                             for (int k = 0; k < NCH; ++k) {
-                                const float4 c = cst[j * NCH + k];
+                                const float4 c = cst[k * n + j];
                                 float t = qv[r][k].x - c.x; s = __builtin_fmaf(t, t, s);
                                 t = qv[r][k].y - c.y; s = __builtin_fmaf(t, t, s);
                                 t = qv[r][k].z - c.z; s = __builtin_fmaf(t, t, s);
@@ -530,11 +546,11 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                         const int jr = i - W + lane + 64 * s;
                         const int jc = GEN ? min(max(jr, 0), n - 1) : min(jr, n - 1);
                         const float4* qrow = qex + exr * NCH;
-                        const float4* crow = cst + jc * NCH;
+                        const float4* crow = cst + jc;
                         float sacc = 0.0f;
 #pragma unroll
                         for (int k = 0; k < NCH; ++k) {
-                            const float4 qv = qrow[k], cv = crow[k];
+                            const float4 qv = qrow[k], cv = crow[k * n];
                             float d;
                             d = qv.x - cv.x; sacc = __builtin_fmaf(d, d, sacc);
                             d = qv.y - cv.y; sacc = __builtin_fmaf(d, d, sacc);
