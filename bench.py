@@ -96,7 +96,7 @@ def parse():
     ap.add_argument("--workload", default="cascade", choices=sorted(WORKLOADS))
     ap.add_argument("--bounds", default="mv")
     ap.add_argument("--frac", default=None, help="window fraction num/den, e.g. 1/10")
-    ap.add_argument("--cpu-queries", type=int, default=24, help="queries in the oracle's timed sample")
+    ap.add_argument("--cpu-queries", type=int, default=300, help="queries in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", nargs="*", default=None, choices=EXTRAS, metavar="NAME",
                     help="also time further workloads: all of them with no name, else the named ones "
