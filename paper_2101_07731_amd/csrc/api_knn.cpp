@@ -314,9 +314,10 @@ static float dp_gamma(int m, int n, int D) {
     return (float)(1.01 * (double)(m + n + 4 * nch_pad(D) + 2) * kUnit);
 }
 
-static int persistent_blocks(size_t lds, int64_t max_items) {
-    // one-wave blocks: up to 6 per SIMD (register file), fewer when LDS runs out
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(24, 163840 / std::max<size_t>(lds, 1)));
+static int persistent_blocks(size_t lds, int64_t max_items, int max_per_cu = 24) {
+    // one-wave blocks: up to 6 per SIMD (register file; max_per_cu for lighter kernels), fewer
+    // when LDS runs out
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(max_per_cu, 163840 / std::max<size_t>(lds, 1)));
     int64_t nb = (int64_t)256 * per_cu;
     if (max_items < nb) nb = std::max<int64_t>(max_items, 1);
     return (int)nb;
@@ -809,7 +810,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     if (K.gate) {
         // Sec. 6: advanced bounds only for gated pairs; LB_PC first, then LB_TI
         if ((e = launch_copy_i32(d.cnt, x.cntmv, K.nq, s)) != hipSuccess) return hip_fail(e, "snapshot");
-        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * K.cap);
+        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * K.cap, 32);   // 8 waves per SIMD
         RouteArgs r;
         std::memset(&r, 0, sizeof r);
         r.nq = K.nq; r.nc = K.nc; r.cap = K.cap;

@@ -281,41 +281,63 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
         const float* bq = a.boxes + (int64_t)q * G * K * D * 2;
         const int32_t* nbq = a.nbox + (int64_t)q * G;
         float acc = 0.0f;
-        for (int g = 0; g < G; ++g) {
-            const int nb = __builtin_amdgcn_readfirstlane(nbq[g]);
-            const float* bg = bq + (int64_t)g * K * D * 2;
-            const int j1 = min(n, (g + 1) * w);
-            const const_as_float* bc = (const const_as_float*)bg;
-            // two points against two boxes per step: four independent chains, and each box's
-            // scalar load serves two points
-            for (int j = g * w; j < j1; j += 2) {
-                const bool two = j + 1 < j1;
-                float4 c0[NCH], c1[NCH];
+        // The candidate's points in pairs (j, j+1) inside a group; the next pair's points are
+        // loaded while the current pair is measured against its group's boxes (two points
+        // against two boxes per step: four independent chains, and each box's scalar load
+        // serves two points).
+        auto load2 = [&](int jj, int jj1, float4 (&x0)[NCH], float4 (&x1)[NCH]) __attribute__((always_inline)) {
+            const int jb = jj + 1 < jj1 ? jj + 1 : jj;
 #pragma unroll
-                for (int k = 0; k < NCH; ++k) {
-                    c0[k] = point_chunk(cs + (int64_t)j * D, k, D, vec);
-                    c1[k] = point_chunk(cs + (int64_t)(two ? j + 1 : j) * D, k, D, vec);
-                }
-                float m0 = __builtin_inff(), m1 = __builtin_inff();
-                int b = 0;
-                for (; b + 1 < nb; b += 2) {
-                    const const_as_float* b0 = bc + b * D * 2;
-                    const const_as_float* b1 = b0 + D * 2;
-                    m0 = __builtin_fminf(m0, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c0), box_dist<NCH, EXACT>(b1, D, c0)));
-                    m1 = __builtin_fminf(m1, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c1), box_dist<NCH, EXACT>(b1, D, c1)));
-                }
-                if (b < nb) {
-                    const const_as_float* b0 = bc + b * D * 2;
-                    m0 = __builtin_fminf(m0, box_dist<NCH, EXACT>(b0, D, c0));
-                    m1 = __builtin_fminf(m1, box_dist<NCH, EXACT>(b0, D, c1));
-                }
-                acc += m0;
-                if (two) acc += m1;
+            for (int k = 0; k < NCH; ++k) {
+                x0[k] = point_chunk(cs + (int64_t)jj * D, k, D, vec);
+                x1[k] = point_chunk(cs + (int64_t)jb * D, k, D, vec);
             }
-            // the partial sum is already a bound: stop once it proves every live pair prunable
-            if (a.key && (g & 7) == 7 && g + 1 < G &&
+        };
+        int g = 0, j = 0, j1 = min(n, w);
+        float4 c0[NCH], c1[NCH];
+        load2(0, j1, c0, c1);
+        for (;;) {
+            int jn = j + 2, gn = g, j1n = j1;
+            if (jn >= j1) {
+                gn = g + 1;
+                jn = gn * w;
+                j1n = min(n, jn + w);
+            }
+            const bool more = gn < G;
+            float4 p0[NCH], p1[NCH];
+            load2(more ? jn : 0, more ? j1n : 1, p0, p1);   // (past the end: point 0, unused)
+            const int nb = __builtin_amdgcn_readfirstlane(nbq[g]);
+            const const_as_float* bc = (const const_as_float*)(bq + (int64_t)g * K * D * 2);
+            const bool two = j + 1 < j1;
+            float m0 = __builtin_inff(), m1 = __builtin_inff();
+            int b = 0;
+            for (; b + 1 < nb; b += 2) {
+                const const_as_float* b0 = bc + b * D * 2;
+                const const_as_float* b1 = b0 + D * 2;
+                m0 = __builtin_fminf(m0, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c0), box_dist<NCH, EXACT>(b1, D, c0)));
+                m1 = __builtin_fminf(m1, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c1), box_dist<NCH, EXACT>(b1, D, c1)));
+            }
+            if (b < nb) {
+                const const_as_float* b0 = bc + b * D * 2;
+                m0 = __builtin_fminf(m0, box_dist<NCH, EXACT>(b0, D, c0));
+                m1 = __builtin_fminf(m1, box_dist<NCH, EXACT>(b0, D, c1));
+            }
+            acc += m0;
+            if (two) acc += m1;
+            // group g done: the partial sum is already a bound; stop once it proves every live
+            // pair prunable
+            if (gn != g && a.key && (g & 7) == 7 && more &&
                 __ballot(live && !((double)acc * defl > stop)) == 0)
                 break;
+            if (!more) break;
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) {
+                c0[k] = p0[k];
+                c1[k] = p1[k];
+            }
+            j = jn;
+            g = gn;
+            j1 = j1n;
         }
         if (live) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)acc * defl);
     }
