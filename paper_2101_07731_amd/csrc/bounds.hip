@@ -464,20 +464,25 @@ __global__ __launch_bounds__(64) void k_lb_ti(TiArgs a) {
                 if (lane < 2) tdq[m + lane] = make_float2(0.0f, INF);
             }
             {
-                // chunk-major staging: word t holds chunk t / n of point t % n
-                const int total = n * NCH;
-                auto at = [&](int t) __attribute__((always_inline)) {
-                    return point_chunk(cs + (int64_t)(t % n) * D, t / n, D, vec);
-                };
-                int t = lane;
-                for (; t + 7 * kWave < total; t += 8 * kWave) {
-                    float4 v[8];
+                // chunk-major staging: cst[k * n + r] is chunk k of point r; SU points per lane
+                // (eight chunks at narrow points) in flight
+                constexpr int SU = NCH <= 2 ? 4 : (NCH <= 4 ? 2 : 1);
+                int r = lane;
+                for (; r + (SU - 1) * kWave < n; r += SU * kWave) {
+                    float4 v[NCH][SU];
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) v[r] = at(t + r * kWave);
+                    for (int k = 0; k < NCH; ++k)
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) cst[t + r * kWave] = v[r];
+                        for (int u = 0; u < SU; ++u) v[k][u] = point_chunk(cs + (int64_t)(r + u * kWave) * D, k, D, vec);
+#pragma unroll
+                    for (int k = 0; k < NCH; ++k)
+#pragma unroll
+                        for (int u = 0; u < SU; ++u) cst[k * n + r + u * kWave] = v[k][u];
                 }
-                for (; t < total; t += kWave) cst[t] = at(t);
+                for (; r < n; r += kWave) {
+#pragma unroll
+                    for (int k = 0; k < NCH; ++k) cst[k * n + r] = point_chunk(cs + (int64_t)r * D, k, D, vec);
+                }
             }
             // exact rows are i = 0 and (P > 0) the multiples of P: row i's point at qex[i / P]
             stage_point_chunks<NCH>(qex, qs, ti_exact_rows(m, P), P > 0 ? P : 0, D, vec, lane);
