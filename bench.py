@@ -51,10 +51,12 @@ DTW_KERNEL_SOURCES = ("knn.hip", "dtw_core.h", "device_common.h")
 STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "total")
 
 EXTRAS = ("full_cascade", "cand_boxes", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency",
-          "batched_pairs", "dtw_loss", "long_knn", "ragged_banks", "lb_mv_streaming", "plain_gpu", "windows")
-# measured on every run: the batched and forward+backward pair rates of the metric, and the plain
-# (no bounds) method on the same GPU
-DEFAULT_EXTRAS = ("plain_gpu", "windows", "batched_pairs", "dtw_loss")
+          "batched_pairs", "dtw_loss", "long_knn", "ragged_banks", "lb_mv_streaming", "plain_gpu", "windows",
+          "trajectories")
+# measured on every run: the batched and forward+backward pair rates of the metric, the plain
+# (no bounds) method on the same GPU, the other windows, and the trajectory workload on which the
+# advanced bounds prune
+DEFAULT_EXTRAS = ("plain_gpu", "windows", "batched_pairs", "dtw_loss", "trajectories")
 
 
 def source_digest(names=DTW_KERNEL_SOURCES):
@@ -328,6 +330,43 @@ def extra_cascade_setup(dev, ix, Qd, T, reps=3):
     return out
 
 
+def extra_trajectories(dev, reps=3):
+    """Trajectory 1-NN (synth.trajectory_knn: 1000 queries x 10000 references,
+    length 182, d = 3, window 10%), data on which the point-clustering bound
+    (Sec. 5) prunes pairs that LB_MV cannot: LB_MV alone, each advanced bound
+    behind it at the default triggers, the setup-stage choice (Sec. 6) made on
+    100 queries, and the plain method, with the pairs each bound pruned."""
+    import torch
+    from paper_2101_07731_amd import search, synth
+    Q, Cs = synth.trajectory_knn()
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    out = {"workload": "1000 x 10000, length 182, d=3, 20 classes of smooth curves, noise 0.5, window 10% (W=18)",
+           "paper_table3_context": "CPU, UEA Charactertrajectories (d = 3, length 182), W = 20: LB_MV 16.98x / "
+                                   "89% of DTWs skipped, TC-DTW 25.31x / 99% over the plain method"}
+    best, _ = search.tune_cascade(ix, Qd[:100], frac=(1, 10))
+    out["setup_choice"] = search.choice_name(best)
+    runs = [("plain", dict(bounds="plain")), ("mv", dict(bounds="mv")), ("mv+pc", dict(bounds="mv+pc")),
+            ("mv+ti", dict(bounds="mv+ti")), ("mv+pc+ti", dict(bounds="mv+pc+ti")), ("setup_choice", best)]
+    for name, kw in runs:
+        st = {}
+
+        def run(kw=kw, st=st):
+            st.update(search.knn(ix, Qd, frac=(1, 10), stats=True, **kw)[2])
+
+        ms = _events_ms(run, reps if name != "plain" else 1)
+        out[name] = {"queries_per_s": round(Q.shape[0] / (ms * 1e-3), 1), "ms": round(ms, 3),
+                     "pct_dtw_pruned": round(100 * (1 - st["dtw_started"] / st["pairs"]), 3),
+                     "pruned": {"mv": st["pruned_mv"], "pc": st["pruned_pc"], "ti": st["pruned_ti"]},
+                     "evaluated": {"pc": st["evaluated_pc"], "ti": st["evaluated_ti"]},
+                     "stage_ms": {n: round(v, 4) for n, v in zip(STAGES, st["stage_ms"])}}
+    for name in ("mv+pc", "mv+pc+ti", "setup_choice"):
+        out["speedup_%s_vs_mv" % name] = round(out["mv"]["ms"] / out[name]["ms"], 3)
+    out["speedup_mv_vs_plain"] = round(out["plain"]["ms"] / out["mv"]["ms"], 3)
+    out["speedup_setup_choice_vs_plain"] = round(out["plain"]["ms"] / out["setup_choice"]["ms"], 3)
+    return out
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -570,7 +609,7 @@ def main():
         out["cascade_setup"] = extra_cascade_setup(dev, ix, Qd, T)
     for name, fn in (("batched_pairs", extra_batched_pairs), ("dtw_loss", extra_fwd_bwd),
                      ("long_knn", extra_long_knn), ("ragged_banks", extra_ragged_banks),
-                     ("lb_mv_streaming", extra_lb_mv_streaming)):
+                     ("lb_mv_streaming", extra_lb_mv_streaming), ("trajectories", extra_trajectories)):
         if name in extras:
             note(name)
             out[name] = fn(dev)

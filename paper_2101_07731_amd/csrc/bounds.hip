@@ -249,7 +249,7 @@ __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const
     return s;
 }
 
-template <int NCH, bool EXACT>
+template <int NCH, bool EXACT, int PPS>
 __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
     const int lane = threadIdx.x;
     const int D = a.D, n = a.n, K = a.K, w = a.w, G = a.ngroups;
@@ -281,49 +281,53 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
         const float* bq = a.boxes + (int64_t)q * G * K * D * 2;
         const int32_t* nbq = a.nbox + (int64_t)q * G;
         float acc = 0.0f;
-        // The candidate's points in pairs (j, j+1) inside a group; the next pair's points are
-        // loaded while the current pair is measured against its group's boxes (two points
-        // against two boxes per step: four independent chains, and each box's scalar load
-        // serves two points).
-        auto load2 = [&](int jj, int jj1, float4 (&x0)[NCH], float4 (&x1)[NCH]) __attribute__((always_inline)) {
-            const int jb = jj + 1 < jj1 ? jj + 1 : jj;
+        // The candidate's points in runs of PPS (j .. j+PPS-1) inside a group; the next run's
+        // points are loaded while the current run is measured against its group's boxes (PPS
+        // points against two boxes per step: 2 PPS independent chains, and each box's scalar
+        // load serves PPS points).
+        auto load_run = [&](int jj, int jj1, float4 (&x)[PPS][NCH]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int k = 0; k < NCH; ++k) {
-                x0[k] = point_chunk(cs + (int64_t)jj * D, k, D, vec);
-                x1[k] = point_chunk(cs + (int64_t)jb * D, k, D, vec);
+            for (int u = 0; u < PPS; ++u) {
+                const int jb = jj + u < jj1 ? jj + u : jj;
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) x[u][k] = point_chunk(cs + (int64_t)jb * D, k, D, vec);
             }
         };
         int g = 0, j = 0, j1 = min(n, w);
-        float4 c0[NCH], c1[NCH];
-        load2(0, j1, c0, c1);
+        float4 c[PPS][NCH];
+        load_run(0, j1, c);
         for (;;) {
-            int jn = j + 2, gn = g, j1n = j1;
+            int jn = j + PPS, gn = g, j1n = j1;
             if (jn >= j1) {
                 gn = g + 1;
                 jn = gn * w;
                 j1n = min(n, jn + w);
             }
             const bool more = gn < G;
-            float4 p0[NCH], p1[NCH];
-            load2(more ? jn : 0, more ? j1n : 1, p0, p1);   // (past the end: point 0, unused)
+            float4 p[PPS][NCH];
+            load_run(more ? jn : 0, more ? j1n : 1, p);   // (past the end: point 0, unused)
             const int nb = __builtin_amdgcn_readfirstlane(nbq[g]);
             const const_as_float* bc = (const const_as_float*)(bq + (int64_t)g * K * D * 2);
-            const bool two = j + 1 < j1;
-            float m0 = __builtin_inff(), m1 = __builtin_inff();
+            float mm[PPS];
+#pragma unroll
+            for (int u = 0; u < PPS; ++u) mm[u] = __builtin_inff();
             int b = 0;
             for (; b + 1 < nb; b += 2) {
                 const const_as_float* b0 = bc + b * D * 2;
                 const const_as_float* b1 = b0 + D * 2;
-                m0 = __builtin_fminf(m0, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c0), box_dist<NCH, EXACT>(b1, D, c0)));
-                m1 = __builtin_fminf(m1, __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c1), box_dist<NCH, EXACT>(b1, D, c1)));
+#pragma unroll
+                for (int u = 0; u < PPS; ++u)
+                    mm[u] = __builtin_fminf(mm[u], __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c[u]),
+                                                                   box_dist<NCH, EXACT>(b1, D, c[u])));
             }
             if (b < nb) {
                 const const_as_float* b0 = bc + b * D * 2;
-                m0 = __builtin_fminf(m0, box_dist<NCH, EXACT>(b0, D, c0));
-                m1 = __builtin_fminf(m1, box_dist<NCH, EXACT>(b0, D, c1));
+#pragma unroll
+                for (int u = 0; u < PPS; ++u) mm[u] = __builtin_fminf(mm[u], box_dist<NCH, EXACT>(b0, D, c[u]));
             }
-            acc += m0;
-            if (two) acc += m1;
+#pragma unroll
+            for (int u = 0; u < PPS; ++u)
+                if (u == 0 || j + u < j1) acc += mm[u];
             // group g done: the partial sum is already a bound; stop once it proves every live
             // pair prunable
             if (gn != g && a.key && (g & 7) == 7 && more &&
@@ -331,10 +335,9 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
                 break;
             if (!more) break;
 #pragma unroll
-            for (int k = 0; k < NCH; ++k) {
-                c0[k] = p0[k];
-                c1[k] = p1[k];
-            }
+            for (int u = 0; u < PPS; ++u)
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) c[u][k] = p[u][k];
             j = jn;
             g = gn;
             j1 = j1n;
@@ -785,10 +788,18 @@ hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NCH, int PPS>
+static void launch_lb_pc_lanes_pps(const PcArgs& a, int nblocks, hipStream_t s) {
+    if (a.D == 4 * NCH) hipLaunchKernelGGL((k_lb_pc_lanes<NCH, true, PPS>), dim3(nblocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_lb_pc_lanes<NCH, false, PPS>), dim3(nblocks), dim3(64), 0, s, a);
+}
+
+// three points per step when the group length is a multiple of three and the points are narrow
+// (more loads in flight, no idle slot in a group), else two
 template <int NCH>
 static void launch_lb_pc_lanes_nch(const PcArgs& a, int nblocks, hipStream_t s) {
-    if (a.D == 4 * NCH) hipLaunchKernelGGL((k_lb_pc_lanes<NCH, true>), dim3(nblocks), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_lb_pc_lanes<NCH, false>), dim3(nblocks), dim3(64), 0, s, a);
+    if (NCH <= 2 && a.w % 3 == 0) launch_lb_pc_lanes_pps<NCH, NCH <= 2 ? 3 : 2>(a, nblocks, s);
+    else launch_lb_pc_lanes_pps<NCH, 2>(a, nblocks, s);
 }
 
 hipError_t launch_lb_pc_lanes(const PcArgs& a, int nblocks, hipStream_t s) {

@@ -76,12 +76,29 @@ typedef __attribute__((address_space(4))) const float const_as_float;   // loads
 // Chunk k (components 4k .. 4k+3, zero past D) of the point at pt; vec: one
 // 16-byte load (D a multiple of 4, pt 16-byte aligned).  Chunks at or past D
 // (the chunk count is padded up to an instantiated width) read nothing.
+// Dword-aligned multi-dword loads (global memory accepts them on gfx950).
+struct __attribute__((aligned(4))) f32x4_a4 { float x, y, z, w; };
+struct __attribute__((packed, aligned(4))) f32x3_a4 { float x, y, z; };
+struct __attribute__((packed, aligned(4))) f32x2_a4 { float x, y; };
+
 __device__ __forceinline__ float4 point_chunk(const float* __restrict__ pt, int k, int D, bool vec) {
     if (vec) return 4 * k < D ? *reinterpret_cast<const float4*>(pt + 4 * k) : make_float4(0.f, 0.f, 0.f, 0.f);
-    float v[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = 4 * k + c < D ? pt[4 * k + c] : 0.0f;
-    return make_float4(v[0], v[1], v[2], v[3]);
+    // the chunk's valid components in one load
+    const int left = D - 4 * k;
+    const float* c = pt + 4 * k;
+    if (left >= 4) {
+        const f32x4_a4 v = *reinterpret_cast<const f32x4_a4*>(c);
+        return make_float4(v.x, v.y, v.z, v.w);
+    }
+    if (left == 3) {
+        const f32x3_a4 v = *reinterpret_cast<const f32x3_a4*>(c);
+        return make_float4(v.x, v.y, v.z, 0.0f);
+    }
+    if (left == 2) {
+        const f32x2_a4 v = *reinterpret_cast<const f32x2_a4*>(c);
+        return make_float4(v.x, v.y, 0.0f, 0.0f);
+    }
+    return make_float4(left == 1 ? c[0] : 0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 }  // namespace tcdtw

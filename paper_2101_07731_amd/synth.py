@@ -15,7 +15,9 @@ generators stand in for them with the shapes named per workload below:
     prototype resampled through a monotone piecewise-linear time map
     (8 segments, slopes U[0.9, 1.1], rescaled to the series span, i.e. a
     local stretch of at most 10%), plus N(0, 0.1^2) noise, z-normalised,
-    so that every query has close neighbours.
+    so that every query has close neighbours;
+  * smooth curves: per dimension a sum of 4 harmonics with amplitudes
+    N(0,1)/k and uniform phases (trajectory prototypes).
 
 All generators use numpy's PCG64 (np.random.default_rng) and return
 float32 arrays laid out [series][t][d].
@@ -74,6 +76,17 @@ def prototype_set(rng, N, T, D, n_proto=8, noise=0.1, protos=None, rho=0.5):
     return znorm(out), labels
 
 
+def smooth_curves(rng, N, T, D, harmonics=4):
+    """[N, T, D] smooth closed curves: per dimension a sum of harmonics k = 1..h with amplitude
+    N(0,1)/k and a uniform phase, z-normalised (pen-trajectory-like paths)."""
+    t = np.arange(T, dtype=np.float64) / T
+    k = np.arange(1, harmonics + 1, dtype=np.float64)
+    amp = rng.standard_normal((N, D, harmonics)) / k
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=(N, D, harmonics))
+    out = np.einsum("ndh,ndht->ntd", amp, np.sin(2.0 * np.pi * k[None, None, :, None] * t + ph[..., None]))
+    return znorm(out)
+
+
 def _f32(x):
     return np.ascontiguousarray(x, dtype=np.float32)
 
@@ -100,6 +113,23 @@ def cascade_knn(nq=1000, nc=10000, T=256, D=8, seed=2, n_proto=8):
     rc = np.random.default_rng(1000 + seed)
     Q, _ = prototype_set(rq, nq, T, D, protos=protos)
     Cs, _ = prototype_set(rc, nc, T, D, protos=protos)
+    return _f32(Q), _f32(Cs)
+
+
+def trajectory_knn(nq=1000, nc=10000, T=182, D=3, seed=6, n_proto=20, noise=0.5):
+    """Trajectory 1-NN workload, the shape of a pen-trajectory archive (d = 3,
+    length 182): 20 prototype classes of smooth curves (smooth_curves, 4
+    harmonics), each series a prototype through a random monotone time map plus
+    N(0, 0.5^2) noise, z-normalised.  The points of such series lie near curves
+    that run across the dimensions, so the per-dimension envelopes of LB_MV are
+    loose where the point-clustering boxes of LB_PC are not.
+    Full size: 1000 queries x 10000 references, window 10%."""
+    rp = np.random.default_rng(3000 + seed)
+    protos = smooth_curves(rp, n_proto, T, D)
+    rq = np.random.default_rng(2000 + seed)
+    rc = np.random.default_rng(1000 + seed)
+    Q, _ = prototype_set(rq, nq, T, D, protos=protos, noise=noise)
+    Cs, _ = prototype_set(rc, nc, T, D, protos=protos, noise=noise)
     return _f32(Q), _f32(Cs)
 
 

@@ -356,6 +356,23 @@ def test_lb_ti_dense_matrix(dev, P, top, frac):
     np.testing.assert_array_less(lo - 1e-30, lb + 1e-30)
 
 
+@pytest.mark.parametrize("bounds", ["mv+pc", "mv+pc+ti"])
+def test_trajectory_workload_advanced_bounds(dev, bounds):
+    """The trajectory workload (smooth curves across d = 3, length 182): the
+    cascade with LB_PC behind LB_MV equals the oracle's exhaustive search, and
+    LB_PC prunes pairs there (the oracle's own sequential cascade prunes with
+    it on the same data)."""
+    from paper_2101_07731_amd import synth
+    Q, Cs = synth.trajectory_knn(nq=40, nc=1500)
+    idx, dist, st = run_knn(dev, Q, Cs, frac=(1, 10), bounds=bounds)
+    say("trajectory", bounds, st)
+    check_against_oracle(idx, dist, Q, Cs, 1, 10)
+    assert st["pruned_mv"] + st["pruned_pc"] + st["pruned_ti"] + st["dtw_started"] == st["pairs"], st
+    assert st["pruned_pc"] > 0
+    _, _, cs = O.knn_cascade(Q[:8], Cs, num=1, den=10, bounds=2)
+    assert cs["pruned_pc"].sum() > 0
+
+
 TI_SHAPES = [(40, 40, 0, 3), (40, 40, 1, 6), (50, 64, 7, 6), (64, 50, 3, 13), (12, 12, 5, 6), (8, 8, 7, 4),
              (96, 96, 31, 8), (96, 96, 32, 8), (150, 150, 63, 5)]
 
@@ -458,7 +475,8 @@ def test_tune_cascade_picks_a_runnable_choice(dev):
     check_against_oracle(idx.cpu().numpy(), dist.cpu().numpy(), Ql, Cl, 1, 2)
 
 
-def test_graphed_search_replays_match_eager(dev):
+@pytest.mark.parametrize("k", [1, 4])
+def test_graphed_search_replays_match_eager(dev, k):
     """The whole cascade captured in a HIP graph (search.GraphedSearch): three
     replays, with eager searches and synchronisations between them and new
     queries copied in before the last, each equal to the eager result."""
@@ -467,17 +485,22 @@ def test_graphed_search_replays_match_eager(dev):
     Q2, _ = synth.cascade_knn(nq=24, nc=1, T=80, D=6, seed=71)
     ix = search.Index(torch.from_numpy(Cs).to(dev))
     for bounds in ("mv", "mv+pc+ti"):
-        say("graphed search", bounds)
-        g = search.GraphedSearch(ix, torch.from_numpy(Q).to(dev), frac=(1, 10), bounds=bounds)
-        ei, ed = search.knn(ix, torch.from_numpy(Q).to(dev), frac=(1, 10), bounds=bounds)
+        say("graphed search", bounds, "k", k)
+        g = search.GraphedSearch(ix, torch.from_numpy(Q).to(dev), k=k, frac=(1, 10), bounds=bounds)
+        ei, ed = search.knn(ix, torch.from_numpy(Q).to(dev), k=k, frac=(1, 10), bounds=bounds)
         for rep in range(3):
             if rep == 2:
                 g.queries_flat.copy_(torch.from_numpy(Q2).to(dev).reshape(g.queries_flat.shape))
-                ei, ed = search.knn(ix, torch.from_numpy(Q2).to(dev), frac=(1, 10), bounds=bounds)
+                ei, ed = search.knn(ix, torch.from_numpy(Q2).to(dev), k=k, frac=(1, 10), bounds=bounds)
             gi, gd = g.replay()
             torch.cuda.synchronize()
             np.testing.assert_array_equal(gi.cpu().numpy(), ei.cpu().numpy())
             np.testing.assert_array_equal(gd.cpu().numpy(), ed.cpu().numpy())
             search.knn(ix, torch.from_numpy(Q[:5]).to(dev), frac=(1, 10))   # eager work between replays
             torch.cuda.synchronize()
-    check_against_oracle(gi.cpu().numpy(), gd.cpu().numpy(), Q2, Cs, 1, 10)
+    if k == 1:
+        check_against_oracle(gi.cpu().numpy(), gd.cpu().numpy(), Q2, Cs, 1, 10)
+    else:
+        ri, rd = O.knn_exhaustive_k(Q2, Cs, k, num=1, den=10)
+        np.testing.assert_array_equal(gi.cpu().numpy(), ri)
+        np.testing.assert_array_equal(gd.cpu().numpy(), rd.astype(np.float32))
