@@ -323,3 +323,32 @@ def test_fake_no_device_and_sync_status(monkeypatch):
     # the host checks still come first
     st = lib.tc_dtw_banded(C.byref(x), C.byref(x), L.Window(-1, 0, 0), 0, C.c_void_p(0x2000), None, None, 0, None)
     assert st == L.ERR_INVALID
+
+
+def test_reuse_query_meta_validated_on_the_host():
+    """tc_dtw_knn_params.reuse_query_meta is 0 (copy the per-query metadata) or
+    1 (reuse what an earlier call left in the workspace); anything else is
+    refused before any device call, by the workspace query and the search."""
+    lib = L.lib()
+    ix = L.Index()
+    ix.buf = C.c_void_p(0x4000)
+    ix.bytes = 1 << 20
+    ix.count = 10
+    ix.dim = 2
+    ix.uniform_len = 8
+    ix.max_len = 8
+    ix.ntiles = 1
+    Q = L.Batch(0x1000, None, None, 3, 2, 8, None)
+    p = L.KnnParams()
+    lib.tc_dtw_knn_params_default(C.byref(p))
+    assert p.reuse_query_meta == 0
+    assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q), C.byref(p)) > 0
+    p.reuse_query_meta = 1
+    assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q), C.byref(p)) > 0
+    for bad in (2, -1):
+        p.reuse_query_meta = bad
+        assert lib.tc_dtw_knn_workspace_bytes(C.byref(ix), C.byref(Q), C.byref(p)) == 0
+        st = lib.tc_dtw_knn(C.byref(ix), C.byref(Q), C.byref(p), C.c_void_p(0x100), C.c_void_p(0x200), None,
+                            C.c_void_p(0x300), 1 << 20, None)
+        assert st == L.ERR_INVALID
+        assert b"reuse_query_meta" in lib.tc_dtw_last_error()
