@@ -229,7 +229,9 @@ def extra_ragged_banks(dev, reps=2):
             "one_call_per_bank": {"queries_per_s": round(len(queries) / (ms * 1e-3), 2), "ms": round(ms, 3),
                                   "pct_dtw_pruned": round(100.0 * (1 - started / pairs), 3),
                                   "gcups_dtw": round(cells / (ms * 1e-3) / 1e9, 2),
-                                  "per_bank_ms": {str(D): round(st_all[D]["stage_ms"][7], 3) for D in st_all}}}
+                                  "per_bank_ms": {str(D): round(st_all[D]["stage_ms"][7], 3) for D in st_all},
+                                  "stage_ms_sum": {n: round(sum(st_all[D]["stage_ms"][i] for D in st_all), 4)
+                                                   for i, n in enumerate(STAGES)}}}
 
 
 def extra_lb_mv_streaming(dev, reps=5):

@@ -364,9 +364,14 @@ struct RaggedPlan {
     tc_dtw_window win{};
     std::vector<int64_t> q_off, t_off;
     std::vector<int32_t> q_len, q_dim, q_cb, q_ce;   // with banks: D and candidate range of each query
+    // grouped searches (banks): queries in bank order, q_out[k] the caller's index of query k, and
+    // each bank's query range, D and size
+    bool grouped = false;
+    std::vector<int32_t> q_out;
+    std::vector<int> g_q0, g_q1, g_D, g_size;
     int64_t tab_floats = 0;
     size_t o_lb, o_seeds, o_seed_dist, o_list, o_list_dist, o_cnt, o_gcnt, o_prefix, o_items, o_counters,
-        o_key, o_stats, o_qoff, o_qlen, o_toff, o_tab, o_qdim, o_qcb, o_qce, bytes;
+        o_key, o_stats, o_qoff, o_qlen, o_toff, o_tab, o_qdim, o_qcb, o_qce, o_qout, bytes;
 };
 
 static bool is_ragged_search(const tc_dtw_index* ix, const tc_dtw_batch* qb) {
@@ -375,8 +380,10 @@ static bool is_ragged_search(const tc_dtw_index* ix, const tc_dtw_batch* qb) {
            qb->dims != nullptr;
 }
 
+// group: with banks, order the queries by bank (searches: each bank's DTWs then run as one launch
+// sized for that bank); the bound matrix keeps the caller's order.
 static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch* qb, const tc_dtw_knn_params* p,
-                                      RaggedPlan& K, HostSet& Qs) {
+                                      RaggedPlan& K, HostSet& Qs, bool group = false) {
     tc_dtw_status st;
     if ((st = check_index(ix)) != TC_DTW_OK) return st;
     if ((st = read_set(qb, "queries", Qs)) != TC_DTW_OK) return st;
@@ -393,18 +400,41 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     K.nc = ix->count;
     K.D = std::max(Qs.dim, ix->dim);   // the largest D sizes the LDS and the kernels' chunk count
     K.banks = ix->nbanks > 0;
+    // order[k]: the caller's index of internal query k
+    std::vector<int32_t> order(K.nq);
+    for (int q = 0; q < K.nq; ++q) order[q] = q;
     if (K.banks) {
-        K.q_dim.resize(K.nq);
-        K.q_cb.resize(K.nq);
-        K.q_ce.resize(K.nq);
+        std::vector<int> bank_of(K.nq);
         for (int q = 0; q < K.nq; ++q) {
             const int D = Qs.dimension(q);
             int b = 0;
             while (b < ix->nbanks && ix->bank_dim[b] != D) ++b;
             if (b == ix->nbanks) return fail(TC_DTW_ERR_INVALID, "a query's dim has no bank in the index");
-            K.q_dim[q] = D;
-            K.q_cb[q] = ix->bank_first[b];
-            K.q_ce[q] = ix->bank_first[b] + ix->bank_count[b];
+            bank_of[q] = b;
+        }
+        if (group) {
+            K.grouped = true;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return bank_of[x] < bank_of[y]; });
+            K.q_out = order;
+            for (int k = 0; k < K.nq;) {
+                const int b = bank_of[order[k]];
+                int e = k;
+                while (e < K.nq && bank_of[order[e]] == b) ++e;
+                K.g_q0.push_back(k);
+                K.g_q1.push_back(e);
+                K.g_D.push_back(ix->bank_dim[b]);
+                K.g_size.push_back(ix->bank_count[b]);
+                k = e;
+            }
+        }
+        K.q_dim.resize(K.nq);
+        K.q_cb.resize(K.nq);
+        K.q_ce.resize(K.nq);
+        for (int k = 0; k < K.nq; ++k) {
+            const int b = bank_of[order[k]];
+            K.q_dim[k] = ix->bank_dim[b];
+            K.q_cb[k] = ix->bank_first[b];
+            K.q_ce[k] = ix->bank_first[b] + ix->bank_count[b];
             K.pairs += (uint64_t)ix->bank_count[b];
         }
     } else {
@@ -418,12 +448,13 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     K.q_off.resize(K.nq);
     K.q_len.resize(K.nq);
     K.t_off.resize(K.nq);
-    for (int q = 0; q < K.nq; ++q) {
+    for (int k = 0; k < K.nq; ++k) {
+        const int q = order[k];
         const int m = Qs.length(q);
-        K.q_off[q] = Qs.offset(q);
-        K.q_len[q] = m;
+        K.q_off[k] = Qs.offset(q);
+        K.q_len[k] = m;
         K.maxm = std::max(K.maxm, m);
-        K.t_off[q] = K.tab_floats;
+        K.t_off[k] = K.tab_floats;
         int L = 0;
         while ((1 << L) <= m) ++L;   // floor(log2 m) + 1
         K.tab_floats += 2LL * L * m * Qs.dimension(q);
@@ -453,6 +484,7 @@ static tc_dtw_status make_ragged_plan(const tc_dtw_index* ix, const tc_dtw_batch
     K.o_qdim = at(K.banks ? (size_t)K.nq * 4 : 0);
     K.o_qcb = at(K.banks ? (size_t)K.nq * 4 : 0);
     K.o_qce = at(K.banks ? (size_t)K.nq * 4 : 0);
+    K.o_qout = at(K.grouped ? (size_t)K.nq * 4 : 0);
     K.bytes = c.need();
     return TC_DTW_OK;
 }
@@ -483,6 +515,12 @@ static hipError_t ragged_upload(const RaggedPlan& K, char* w, RaggedKnnArgs& r, 
         r.bank_max = 0;
         for (int q = 0; q < K.nq; ++q) r.bank_max = std::max(r.bank_max, K.q_ce[q] - K.q_cb[q]);
     }
+    r.q_out = nullptr;
+    if (K.grouped) {
+        if (copy && (e = hipMemcpyAsync(w + K.o_qout, K.q_out.data(), K.nq * 4, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        r.q_out = reinterpret_cast<const int32_t*>(w + K.o_qout);
+    }
     return hipSuccess;
 }
 
@@ -491,7 +529,7 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
                                 hipStream_t s) {
     RaggedPlan K;
     HostSet Qs;
-    tc_dtw_status st = make_ragged_plan(ix, queries, p, K, Qs);
+    tc_dtw_status st = make_ragged_plan(ix, queries, p, K, Qs, true);
     if (st != TC_DTW_OK) return st;
     if (!nn_idx || !nn_dist) return fail(TC_DTW_ERR_INVALID, "null output pointer");
     if (!ws || ws_bytes < K.bytes) return fail(TC_DTW_ERR_WORKSPACE, "workspace smaller than tc_dtw_knn_workspace_bytes()");
@@ -549,9 +587,39 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
     if ((e = launch_knn_prep(d, s)) != hipSuccess) return hip_fail(e, "prep");
     if (!K.plain && (e = launch_rq_tables(r, s)) != hipSuccess) return hip_fail(e, "query tables");
     mark(1);
-    if (!K.plain && (e = launch_rlb_mv(r, s)) != hipSuccess) return hip_fail(e, "lb_mv");
+    // grouped queries: one launch per bank, with that bank's D, size and query range
+    auto group_args = [&](const RaggedKnnArgs& base, size_t g) {
+        RaggedKnnArgs a = base;
+        a.q0 = K.g_q0[g];
+        a.q1 = K.g_q1[g];
+        a.D = K.g_D[g];
+        a.bank_max = K.g_size[g];
+        return a;
+    };
+    if (!K.plain) {
+        if (K.grouped) {
+            for (size_t g = 0; g < K.g_q0.size(); ++g)
+                if ((e = launch_rlb_mv(group_args(r, g), s)) != hipSuccess) return hip_fail(e, "lb_mv");
+        } else if ((e = launch_rlb_mv(r, s)) != hipSuccess) {
+            return hip_fail(e, "lb_mv");
+        }
+    }
     mark(2);
     const size_t lds = rknn_dtw_lds_bytes(K.maxn, K.D);
+    // the DTW list launches of one stage: one per bank (its own work counter, cleared with the
+    // others when the call starts) or one over every query
+    auto dtw_launches = [&](const RaggedKnnArgs& a, int64_t per_query, int stage) -> hipError_t {
+        if (!K.grouped)
+            return launch_rknn_dtw(a, persistent_blocks(lds, (int64_t)K.nq * per_query), s);
+        for (size_t g = 0; g < K.g_q0.size(); ++g) {
+            RaggedKnnArgs b = group_args(a, g);
+            b.counter = d.counters + 1 + 8 * stage + (int)g;
+            const int64_t items = (int64_t)(b.q1 - b.q0) * std::min<int64_t>(per_query, b.bank_max);
+            hipError_t e2 = launch_rknn_dtw(b, persistent_blocks(rknn_dtw_lds_bytes(K.maxn, b.D), items), s);
+            if (e2 != hipSuccess) return e2;
+        }
+        return hipSuccess;
+    };
     KnnDtwArgs scan;
     std::memset(&scan, 0, sizeof scan);
     scan.nq = K.nq; scan.P = 1; scan.prefix = d.prefix; scan.item_query = d.item_query; scan.counter = r.counter;
@@ -564,8 +632,7 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
         a.list_dist = d.seed_dist;
         a.cap = K.R;
         a.abandon = 0;
-        if ((e = launch_rknn_dtw(a, persistent_blocks(lds, (int64_t)K.nq * K.R), s)) != hipSuccess)
-            return hip_fail(e, "seed dtw");
+        if ((e = dtw_launches(a, K.R, 1)) != hipSuccess) return hip_fail(e, "seed dtw");
     }
     mark(3);
     const double keep = 1.0 - (double)p->prune_margin;
@@ -580,8 +647,7 @@ static tc_dtw_status knn_ragged(const tc_dtw_index* ix, const tc_dtw_batch* quer
         a.list_dist = d.list_dist;
         a.cap = K.nc;
         a.abandon = K.abandon ? 1 : 0;
-        if ((e = launch_rknn_dtw(a, persistent_blocks(lds, (int64_t)K.nq * K.nc), s)) != hipSuccess)
-            return hip_fail(e, "dtw");
+        if ((e = dtw_launches(a, K.nc, 2)) != hipSuccess) return hip_fail(e, "dtw");
     }
     mark(6);
     {
@@ -743,7 +809,7 @@ size_t tc_dtw_knn_workspace_bytes(const tc_dtw_index* ix, const tc_dtw_batch* qu
     if (is_ragged_search(ix, queries)) {
         RaggedPlan R;
         HostSet Qr;
-        return make_ragged_plan(ix, queries, p, R, Qr) == TC_DTW_OK ? R.bytes : 0;
+        return make_ragged_plan(ix, queries, p, R, Qr, true) == TC_DTW_OK ? R.bytes : 0;
     }
     KnnPlan K;
     HostSet Q;

@@ -138,7 +138,7 @@ constexpr int kKeyStride = 16;   // u64 words
 constexpr int kQT = 8;           // queries per LB_MV tile
 constexpr int kMaxSeeds = 32;
 constexpr int kMaxK = 32;           // largest k of a k-nearest-neighbour search
-constexpr int kNumCounters = 8;
+constexpr int kNumCounters = 24;   // 1 + two stages x one persistent launch per bank (8 at most)
 constexpr int kNumStats = 16;
 enum {
     kStPrunedMv = 0, kStPrunedPc, kStPrunedTi, kStDtwStarted, kStDtwAbandoned, kStRescored,
@@ -232,7 +232,10 @@ struct RaggedKnnArgs {
     const int32_t* q_dim;      // [nq] D of each query (banks of several D), or null: D for all
     const int32_t* q_cb;       // [nq] first candidate of the query's bank (with q_dim)
     const int32_t* q_ce;       // [nq] one past its last candidate
-    int32_t bank_max;          // the largest bank (with q_dim)
+    int32_t bank_max;          // the largest bank (with q_dim; of this launch's bank with a query range)
+    const int32_t* q_out;      // [nq] the caller's index of each query (queries grouped by bank), or null
+    int32_t q0, q1;            // the queries of this launch: DTW items of queries q0 .. q1-1, LB_MV rows
+                               // q0 + blockIdx.y (q1 = 0: every query)
     const float* C;            // index series
     const int64_t* c_off;      // [nc] float offsets inside the index series
     const int32_t* c_len;      // [nc]

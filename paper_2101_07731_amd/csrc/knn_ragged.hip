@@ -117,7 +117,7 @@ __device__ __forceinline__ float mv_term(float v, float U, float Lw) {
 
 template <int NCH, bool VEC>
 __global__ __launch_bounds__(256) void k_rlb_mv(RaggedKnnArgs a) {
-    const int q = blockIdx.y;
+    const int q = a.q0 + blockIdx.y;
     const int lane = threadIdx.x & 63;
     // with banks of several dims the grid covers the largest bank and each query its own
     const int c = (a.q_dim ? a.q_cb[q] : 0) + blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -205,10 +205,12 @@ __device__ __forceinline__ void rknn_pair_if(int nch, float& v, const RaggedKnnA
 template <int NCH>
 __global__ __launch_bounds__(64) void k_rknn_dtw(RaggedKnnArgs a) {
     const int lane = threadIdx.x;
-    const int total = a.prefix[a.nq];
+    // the items of queries q0 .. q1-1 (every query when q1 is 0)
+    const int first = __builtin_amdgcn_readfirstlane(a.q1 > 0 ? a.prefix[a.q0] : 0);
+    const int total = __builtin_amdgcn_readfirstlane(a.prefix[a.q1 > 0 ? a.q1 : a.nq]);
     unsigned long long w_started = 0, w_aband = 0, w_cells = 0;
     for (;;) {
-        const int item = wave_next_item(a.counter);
+        const int item = first + wave_next_item(a.counter);
         if (item >= total) break;
         // every value that steers the loops below is read into a scalar register
         const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
@@ -339,8 +341,9 @@ __global__ __launch_bounds__(64) void k_rknn_finalize(RaggedKnnArgs a) {
         }
     }
     if (lane == 0) {
-        a.nn_idx[q] = bestidx == 0x7fffffff ? -1 : bestidx;
-        a.nn_dist[q] = (float)best;
+        const int qo = a.q_out ? a.q_out[q] : q;   // the caller's index of the query
+        a.nn_idx[qo] = bestidx == 0x7fffffff ? -1 : bestidx;
+        a.nn_dist[qo] = (float)best;
         atomicAdd(&a.stats[kStRescored], (unsigned long long)rescored);
         int nseeds = 0;
         for (int k = 0; k < ns; ++k) nseeds += a.seeds[(int64_t)q * ns + k] >= 0;
@@ -368,7 +371,7 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
 }
 
 hipError_t launch_rlb_mv(const RaggedKnnArgs& a, hipStream_t s) {
-    const dim3 grid(((a.q_dim ? a.bank_max : a.nc) + 3) / 4, a.nq);
+    const dim3 grid(((a.q_dim ? a.bank_max : a.nc) + 3) / 4, a.q1 > 0 ? a.q1 - a.q0 : a.nq);
     if (a.D % 4 != 0 && !a.q_dim) {
         hipLaunchKernelGGL((k_rlb_mv<1, false>), grid, dim3(256), 0, s, a);
     } else {
