@@ -227,11 +227,16 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
 // space are scalar loads), and
 // each lane walks its own candidate's points in order.  Per (point, box,
 // dimension): two subtractions with a scalar operand, a 3-way max with 0 and
-// an FMA; per box a minimum.  EXACT: D == 4 NCH (whole 16-byte chunks, no
-// per-dimension test).
+// an FMA; per box a minimum.  DC: the point width D when it is fixed at
+// compile time (no test per dimension, the box's bounds read by wide scalar
+// loads), 0 when it is read at run time.  MED: the distance of x to
+// [lo, hi] as x - med3(x, lo, hi) (one operation fewer per point once the
+// box's lo sits in a vector register: gfx950 reads one scalar operand per
+// instruction), else max(lo - x, x - hi, 0); the two are equal bit for bit
+// up to the sign, which the square removes.
 
 // Squared distance of a point (NCH chunks) to the box at bb ([D][2] lo, hi).
-template <int NCH, bool EXACT>
+template <int NCH, int DC, bool MED>
 __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const float4 (&c)[NCH]) {
     float s = 0.0f;
 #pragma unroll
@@ -240,8 +245,10 @@ __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int p = 4 * k + t;
-            if (EXACT || p < D) {
-                const float v = __builtin_fmaxf(__builtin_fmaxf(bb[2 * p] - cv[t], cv[t] - bb[2 * p + 1]), 0.0f);
+            if (DC > 0 ? p < DC : p < D) {
+                const float v = MED ? cv[t] - __builtin_amdgcn_fmed3f(cv[t], bb[2 * p], bb[2 * p + 1])
+                                    : __builtin_fmaxf(__builtin_fmaxf(bb[2 * p] - cv[t], cv[t] - bb[2 * p + 1]),
+                                                      0.0f);
                 s = __builtin_fmaf(v, v, s);
             }
         }
@@ -249,10 +256,11 @@ __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const
     return s;
 }
 
-template <int NCH, bool EXACT, int PPS>
+template <int NCH, int DC, int PPS, bool MED>
 __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
+    constexpr bool EXACT = DC == 4 * NCH;
     const int lane = threadIdx.x;
-    const int D = a.D, n = a.n, K = a.K, w = a.w, G = a.ngroups;
+    const int D = DC > 0 ? DC : a.D, n = a.n, K = a.K, w = a.w, G = a.ngroups;
     const double defl = 1.0 - (double)(n + D + 5) * (1.0 / 16777216.0) * 1.001;
     const bool vec = EXACT && (reinterpret_cast<uintptr_t>(a.C) & 15) == 0;
     unsigned long long evaluated = 0;   // pairs this wave evaluated
@@ -317,13 +325,13 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
                 const const_as_float* b1 = b0 + D * 2;
 #pragma unroll
                 for (int u = 0; u < PPS; ++u)
-                    mm[u] = __builtin_fminf(mm[u], __builtin_fminf(box_dist<NCH, EXACT>(b0, D, c[u]),
-                                                                   box_dist<NCH, EXACT>(b1, D, c[u])));
+                    mm[u] = __builtin_fminf(mm[u], __builtin_fminf(box_dist<NCH, DC, MED>(b0, D, c[u]),
+                                                                   box_dist<NCH, DC, MED>(b1, D, c[u])));
             }
             if (b < nb) {
                 const const_as_float* b0 = bc + b * D * 2;
 #pragma unroll
-                for (int u = 0; u < PPS; ++u) mm[u] = __builtin_fminf(mm[u], box_dist<NCH, EXACT>(b0, D, c[u]));
+                for (int u = 0; u < PPS; ++u) mm[u] = __builtin_fminf(mm[u], box_dist<NCH, DC, MED>(b0, D, c[u]));
             }
 #pragma unroll
             for (int u = 0; u < PPS; ++u)
@@ -788,18 +796,40 @@ hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NCH, int PPS>
-static void launch_lb_pc_lanes_pps(const PcArgs& a, int nblocks, hipStream_t s) {
-    if (a.D == 4 * NCH) hipLaunchKernelGGL((k_lb_pc_lanes<NCH, true, PPS>), dim3(nblocks), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_lb_pc_lanes<NCH, false, PPS>), dim3(nblocks), dim3(64), 0, s, a);
+// the median form for points of up to 8 dimensions (measured faster at d = 8, even at d = 3)
+template <int NCH>
+constexpr bool pc_lanes_median() { return NCH <= 2; }
+
+template <int NCH, int DC, int PPS>
+static void launch_pc_lanes(const PcArgs& a, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_lb_pc_lanes<NCH, DC, PPS, pc_lanes_median<NCH>()>), dim3(nblocks), dim3(64), 0, s, a);
 }
 
-// three points per step when the group length is a multiple of three and the points are narrow
-// (more loads in flight, no idle slot in a group), else two
+// Narrow points take a whole group per step when the group length is a multiple of six, else
+// three points when it is a multiple of three (more loads in flight, no idle slot in a group),
+// else two; wide points two.
+template <int NCH, int DC>
+static void launch_pc_lanes_dc(const PcArgs& a, int nblocks, hipStream_t s) {
+    if (NCH <= 2 && a.w % 6 == 0) launch_pc_lanes<NCH, DC, NCH <= 2 ? 6 : 2>(a, nblocks, s);
+    else if (NCH <= 2 && a.w % 3 == 0) launch_pc_lanes<NCH, DC, NCH <= 2 ? 3 : 2>(a, nblocks, s);
+    else launch_pc_lanes<NCH, DC, 2>(a, nblocks, s);
+}
+
+// D fixed at compile time for points of up to 8 dimensions; wider points whole chunks or D at
+// run time
 template <int NCH>
 static void launch_lb_pc_lanes_nch(const PcArgs& a, int nblocks, hipStream_t s) {
-    if (NCH <= 2 && a.w % 3 == 0) launch_lb_pc_lanes_pps<NCH, NCH <= 2 ? 3 : 2>(a, nblocks, s);
-    else launch_lb_pc_lanes_pps<NCH, 2>(a, nblocks, s);
+    if constexpr (NCH <= 2) {
+        switch (a.D - 4 * (NCH - 1)) {
+            case 1: launch_pc_lanes_dc<NCH, 4 * NCH - 3>(a, nblocks, s); break;
+            case 2: launch_pc_lanes_dc<NCH, 4 * NCH - 2>(a, nblocks, s); break;
+            case 3: launch_pc_lanes_dc<NCH, 4 * NCH - 1>(a, nblocks, s); break;
+            default: launch_pc_lanes_dc<NCH, 4 * NCH>(a, nblocks, s); break;
+        }
+    } else {
+        if (a.D == 4 * NCH) launch_pc_lanes_dc<NCH, 4 * NCH>(a, nblocks, s);
+        else launch_pc_lanes_dc<NCH, 0>(a, nblocks, s);
+    }
 }
 
 hipError_t launch_lb_pc_lanes(const PcArgs& a, int nblocks, hipStream_t s) {
