@@ -876,7 +876,7 @@ tc_dtw_status tc_dtw_knn(const tc_dtw_index* ix, const tc_dtw_batch* queries, co
     if (K.gate) {
         // Sec. 6: advanced bounds only for gated pairs; LB_PC first, then LB_TI
         if ((e = launch_copy_i32(d.cnt, x.cntmv, K.nq, s)) != hipSuccess) return hip_fail(e, "snapshot");
-        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * K.cap, 32);   // 8 waves per SIMD
+        const int pc_blocks = persistent_blocks(0, (int64_t)K.nq * K.cap, 32);   // up to 8 waves per SIMD (fewer where registers cap them)
         RouteArgs r;
         std::memset(&r, 0, sizeof r);
         r.nq = K.nq; r.nc = K.nc; r.cap = K.cap;

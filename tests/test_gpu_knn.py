@@ -270,7 +270,7 @@ def _pc_floor(Cs):
 
 
 @pytest.mark.parametrize("case", [(8, 3, (1, 10), 2, 6, 6), (16, 4, (1, 5), 3, 4, 6), (33, 2, (1, 10), 2, 16, 3)],
-                         ids=["d8_W8_L2_K6", "d4_W16_L3_K4", "d2_W3_L2_K16_w3"])
+                         ids=["d8_W8_L2_K6", "d16_W16_L3_K4", "d33_W8_L2_K16_w3"])
 def test_lb_pc_dense_matrix(dev, case):
     from paper_2101_07731_amd import search, synth
     D, seed, frac, Lv, K, w = case
@@ -288,9 +288,31 @@ def test_lb_pc_dense_matrix(dev, case):
     np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
 
 
+@pytest.mark.parametrize("D", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("w", [6, 3, 4])
+def test_lb_pc_narrow_points(dev, D, w):
+    """The query-side LB_PC kernel with every point width up to 7 fixed at
+    compile time and the group lengths that select six, three and two points
+    per step (a ragged last group: 77 = 12 * 6 + 5 positions), per element
+    against the oracle."""
+    from paper_2101_07731_amd import search, synth
+    T = 77
+    Q, Cs = synth.cascade_knn(nq=5, nc=70, T=T, D=D, seed=60 + D)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_pc narrow", D, w)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="pc", frac=(1, 10), pc_levels=2,
+                             pc_clusters=4, pc_group=w).cpu().numpy().astype(np.float64)
+    W = O.window_eff(T, T, 0, 1, 10)
+    fl = _pc_floor(Cs)
+    ref = np.array([[O.lb_pc(q, c, W, Lv=2, K=4, w=w, floor_len=fl) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12))
+    slack = 2 * (T + D + 5) * 2.0 ** -24 * 1.01 + 1e-7
+    np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
+
+
 @pytest.mark.parametrize("case", [(8, 3, (1, 10), 2, 6, 6, 80), (16, 4, (1, 5), 3, 4, 6, 80),
                                   (33, 2, (1, 10), 2, 16, 3, 33), (5, 5, (1, 10), 2, 6, 6, 71)],
-                         ids=["d8_W8_L2_K6", "d4_W16_L3_K4", "d2_W3_L2_K16_w3", "d5_m71_n80"])
+                         ids=["d8_W8_L2_K6", "d16_W16_L3_K4", "d33_W8_L2_K16_w3", "d5_m71_n80"])
 def test_lb_pc_candidate_boxes_dense_matrix(dev, case):
     """LB_PC with the roles swapped (boxes of the candidates, built once per
     index) against oracle.lb_pc(c, q): same rounding bar as the query-side
