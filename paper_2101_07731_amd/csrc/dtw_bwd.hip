@@ -9,8 +9,9 @@
 //      it (consecutive steps mostly stay among them; on the diagonal layout
 //      the next block back is read ahead), each step reading its word from
 //      the lane that holds it and appending its 2-bit step to a record in
-//      LDS (one word per 16 steps); meanwhile waves 1-3 copy both series to
-//      LDS when they fit;
+//      LDS (one word per 16 steps; on the diagonal layout a run of diagonal
+//      steps is read from one word at once, with no branch per step);
+//      meanwhile waves 1-3 copy both series to LDS when they fit;
 //   3. all threads decode the record: each takes a run of consecutive steps,
 //      a block scan of the row and column decrements gives its starting
 //      cell, and it writes the runs its steps close: a monotone path meets
@@ -92,51 +93,58 @@ struct CodeMap {
 // 64; on the diagonal layout (32-bit index arithmetic) the block before it
 // is read ahead, since a step never moves to a later block and moves back at
 // most one.  Returns the number of steps.
-// Diagonal layout: the walk keeps (sigma, slot, r) of the current cell
-// (sigma = j - i + off, slot = sigma & 1, r = (i + j - slot) / 2) and
-// updates them per step: a diagonal step leaves sigma and the slot and
-// lowers r; a step to (i-1, j) or (i, j-1) moves sigma by +1 or -1, flips
-// the slot and lowers r when the slot was 0.  The walk ends at (0, 0), the
-// only cell with r = 0 and slot 0.  The word of a cell is block r / 8,
-// lane sigma / 2; a step never moves to a later block and moves back at
-// most one, so the block before the current one is read ahead.
+// Diagonal layout: the walk keeps (sigma, r) of the current cell (sigma =
+// j - i + off, its slot sigma & 1, r = (i + j - slot) / 2): a diagonal step
+// lowers r; a step to (i-1, j) or (i, j-1) moves sigma by +1 or -1 (flipping
+// the slot) and lowers r when the slot was 0.  The walk ends at (0, 0), the
+// only cell with r = 0 and slot 0.  The word of a cell is block r / 8, lane
+// sigma / 2, and holds the codes of rounds 8 (r / 8) .. 8 (r / 8) + 7 of both
+// slots, so a run of diagonal steps is read from one word: the slot's codes
+// of rounds r mod 8 down to 0, the run ending at the first nonzero code (or
+// at round 0, after which the walk is in the block before).  A step never
+// moves to a later block and moves back at most one, so the block before the
+// current one is read ahead.  The loop is bounded by the longest path.
 __device__ __forceinline__ int walk_diag(const CodeMap& cm, const uint32_t* codes, int words, int m, int n,
                                          uint32_t* rec, int lane) {
     int sigma = (n - m) + cm.off;
-    int slot = sigma & 1;
-    int r = (m + n - 2 - slot) >> 1;
+    int r = (m + n - 2 - (sigma & 1)) >> 1;
     int blk = r >> 3;
     auto load = [&](int b) __attribute__((always_inline)) {
         const int w = b * cm.G + lane;
         return (b >= 0 && w < words) ? codes[w] : 0u;
     };
     uint32_t held = load(blk), ahead = load(blk - 1);
-    int L = 0;
-    while (r > 0 || slot != 0) {
-        // up to 16 steps into one record word (all values scalar)
-        uint32_t acc = 0;
-        int k = 0;
-        for (; k < 16 && (r > 0 || slot != 0); ++k) {
-            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)held, sigma >> 1);
-            uint32_t code = (word >> ((r & 7) * 4 + 2 * slot)) & 3u;
-            code = code == 3u ? 2u : code;
-            if (code == 0u) {
-                r -= 1;
-            } else {
-                r -= slot == 0;
-                slot ^= 1;
-                sigma += code == 1u ? 1 : -1;
-            }
-            acc |= code << (2 * k);
-            if ((r >> 3) != blk) {
-                blk = r >> 3;
-                held = ahead;
-                ahead = load(blk - 1);
-            }
+    const int maxL = m + n - 2;
+    int L = 0;          // steps recorded
+    uint32_t acc = 0;   // the record word of step L (code 0 = diagonal)
+    // Branch-free steps: each iteration takes one non-diagonal step or a run of diagonal ones,
+    // stores the record word it wrote into (every lane the same value) and starts a new word
+    // when the steps cross into the next.
+    while ((r > 0 || (sigma & 1)) && L < maxL) {
+        const int slot = sigma & 1, rr = r & 7;
+        const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)held, sigma >> 1);
+        // this slot's codes of rounds 0 .. rr, round t at bits 4t and 4t + 1
+        const uint32_t z = (word >> (2 * slot)) & 0x33333333u & (0xffffffffu >> (28 - 4 * rr));
+        const uint32_t c = z >> (4 * rr);
+        const bool diag = c == 0u;
+        // diagonal steps down to the first nonzero code below round rr (the highest set bit
+        // of z; none: through round 0); from r = 0 only slot 1 remains, which is never diagonal
+        const int run = diag ? max(min(rr - ((31 - (int)__clz(z)) >> 2), r), 1) : 1;
+        const uint32_t code = c == 3u ? 2u : c;
+        acc |= code << (2 * (L & 15));
+        rec[L >> 4] = acc;
+        const int Ln = min(L + run, maxL);   // (a valid path ends at exactly maxL steps or fewer)
+        acc = ((Ln ^ L) >> 4) != 0 ? 0u : acc;
+        L = Ln;
+        r -= diag ? run : (slot == 0 ? 1 : 0);
+        sigma += diag ? 0 : (code == 1u ? 1 : -1);
+        if ((r >> 3) != blk) {
+            blk = r >> 3;
+            held = ahead;
+            ahead = load(blk - 1);
         }
-        if (lane == 0) rec[L >> 4] = acc;
-        L += k;
     }
+    if ((L & 15) != 0) rec[L >> 4] = acc;
     return L;
 }
 
@@ -266,21 +274,27 @@ __device__ void bwd_item(const DtwBwdArgs& a, int item) {
     const float* yv_src = sstaged ? sser + m * D : ys;
     float* gx = a.grad_x + xoff;
     float* gy = a.grad_y + yoff;
-    for (int t = tid; t < m * D; t += kBwdThreads) {
-        const int i = t / D, p = t - i * D;
+    // element t = i D + p; (i, p) advanced by kBwdThreads elements per iteration without a division
+    const int si = kBwdThreads / D, sp = kBwdThreads - si * D;
+    for (int t = tid, i = tid / D, p = tid - (tid / D) * D; t < m * D; t += kBwdThreads) {
         const int j0 = rlo[i], j1 = rhi[i];
         const double xv = xv_src[t];
         double acc = 0.0;
         for (int j = j0; j <= j1; ++j) acc += xv - (double)yv_src[j * D + p];
         gx[t] = (float)((double)g2 * acc);
+        i += si;
+        p += sp;
+        if (p >= D) { p -= D; ++i; }
     }
-    for (int t = tid; t < n * D; t += kBwdThreads) {
-        const int j = t / D, p = t - j * D;
+    for (int t = tid, j = tid / D, p = tid - (tid / D) * D; t < n * D; t += kBwdThreads) {
         const int i0 = clo[j], i1 = chi[j];
         const double yv = yv_src[t];
         double acc = 0.0;
         for (int i = i0; i <= i1; ++i) acc += yv - (double)xv_src[i * D + p];
         gy[t] = (float)((double)g2 * acc);
+        j += si;
+        p += sp;
+        if (p >= D) { p -= D; ++j; }
     }
 }
 
