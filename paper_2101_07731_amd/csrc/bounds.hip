@@ -229,14 +229,14 @@ __global__ __launch_bounds__(64) void k_lb_pc(PcArgs a) {
 // dimension): two subtractions with a scalar operand, a 3-way max with 0 and
 // an FMA; per box a minimum.  DC: the point width D when it is fixed at
 // compile time (no test per dimension, the box's bounds read by wide scalar
-// loads), 0 when it is read at run time.  MED: the distance of x to
-// [lo, hi] as x - med3(x, lo, hi) (one operation fewer per point once the
-// box's lo sits in a vector register: gfx950 reads one scalar operand per
-// instruction), else max(lo - x, x - hi, 0); the two are equal bit for bit
-// up to the sign, which the square removes.
+// loads), 0 when it is read at run time.  The distance of x to [lo, hi] is
+// x - med3(x, lo, hi): one operation fewer per point than max(lo - x,
+// x - hi, 0) once the box's lo sits in a vector register (gfx950 reads one
+// scalar operand per instruction; the move serves the PPS points of a step),
+// and equal to it bit for bit up to the sign, which the square removes.
 
 // Squared distance of a point (NCH chunks) to the box at bb ([D][2] lo, hi).
-template <int NCH, int DC, bool MED>
+template <int NCH, int DC>
 __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const float4 (&c)[NCH]) {
     float s = 0.0f;
 #pragma unroll
@@ -246,9 +246,7 @@ __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const
         for (int t = 0; t < 4; ++t) {
             const int p = 4 * k + t;
             if (DC > 0 ? p < DC : p < D) {
-                const float v = MED ? cv[t] - __builtin_amdgcn_fmed3f(cv[t], bb[2 * p], bb[2 * p + 1])
-                                    : __builtin_fmaxf(__builtin_fmaxf(bb[2 * p] - cv[t], cv[t] - bb[2 * p + 1]),
-                                                      0.0f);
+                const float v = cv[t] - __builtin_amdgcn_fmed3f(cv[t], bb[2 * p], bb[2 * p + 1]);
                 s = __builtin_fmaf(v, v, s);
             }
         }
@@ -256,7 +254,7 @@ __device__ __forceinline__ float box_dist(const const_as_float* bb, int D, const
     return s;
 }
 
-template <int NCH, int DC, int PPS, bool MED>
+template <int NCH, int DC, int PPS>
 __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
     constexpr bool EXACT = DC == 4 * NCH;
     const int lane = threadIdx.x;
@@ -325,13 +323,13 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
                 const const_as_float* b1 = b0 + D * 2;
 #pragma unroll
                 for (int u = 0; u < PPS; ++u)
-                    mm[u] = __builtin_fminf(mm[u], __builtin_fminf(box_dist<NCH, DC, MED>(b0, D, c[u]),
-                                                                   box_dist<NCH, DC, MED>(b1, D, c[u])));
+                    mm[u] = __builtin_fminf(mm[u], __builtin_fminf(box_dist<NCH, DC>(b0, D, c[u]),
+                                                                   box_dist<NCH, DC>(b1, D, c[u])));
             }
             if (b < nb) {
                 const const_as_float* b0 = bc + b * D * 2;
 #pragma unroll
-                for (int u = 0; u < PPS; ++u) mm[u] = __builtin_fminf(mm[u], box_dist<NCH, DC, MED>(b0, D, c[u]));
+                for (int u = 0; u < PPS; ++u) mm[u] = __builtin_fminf(mm[u], box_dist<NCH, DC>(b0, D, c[u]));
             }
 #pragma unroll
             for (int u = 0; u < PPS; ++u)
@@ -796,13 +794,9 @@ hipError_t launch_pc_boxes(const PcArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// the median form for points of up to 8 dimensions (measured faster at d = 8, even at d = 3)
-template <int NCH>
-constexpr bool pc_lanes_median() { return NCH <= 2; }
-
 template <int NCH, int DC, int PPS>
 static void launch_pc_lanes(const PcArgs& a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_lb_pc_lanes<NCH, DC, PPS, pc_lanes_median<NCH>()>), dim3(nblocks), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_lb_pc_lanes<NCH, DC, PPS>), dim3(nblocks), dim3(64), 0, s, a);
 }
 
 // Narrow points take a whole group per step when the group length is a multiple of six, else
