@@ -142,6 +142,46 @@ def test_backward_matches_oracle_path_gradient(dev, case):
         np.testing.assert_allclose(gy[b], rc, rtol=1e-6, atol=1e-6 * scale)
 
 
+def _path_shape_pair(kind, rng, m, D):
+    x = walks(rng, 1, m, D)[0]
+    if kind == "diagonal":        # near copy: a diagonal path across every code block and record word
+        y = x + 1e-4 * rng.standard_normal(x.shape).astype(np.float32)
+    elif kind == "shifted":       # y lags x by 7 positions: runs of horizontal and vertical steps at the ends
+        y = np.concatenate([np.repeat(x[:1], 7, axis=0), x[:-7]]) + \
+            1e-4 * rng.standard_normal(x.shape).astype(np.float32)
+    elif kind == "stretched":     # every point of x twice: alternating diagonal and horizontal steps
+        y = np.repeat(x, 2, axis=0) + 1e-4 * rng.standard_normal((2 * m, D)).astype(np.float32)
+    else:                         # independent walks of unequal lengths
+        y = walks(rng, 1, m + 45, D)[0]
+    return np.ascontiguousarray(x, dtype=np.float32), np.ascontiguousarray(y, dtype=np.float32)
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "shifted", "stretched", "unequal"])
+@pytest.mark.parametrize("m", [97, 300])
+def test_backward_path_shapes(dev, kind, m):
+    """Paths of known shape through the walk of the recorded codes (long runs
+    of diagonal steps read several to a code word, runs of horizontal or
+    vertical steps, alternating steps, record words crossed inside a run):
+    float64 forward, so the path is the oracle's, and every gradient
+    element against the oracle's path gradient."""
+    from paper_2101_07731_amd import pairs
+    rng = np.random.default_rng(300 + m + len(kind))
+    D = 5
+    x, y = _path_shape_pair(kind, rng, m, D)
+    n = y.shape[0]
+    say("backward path shape", kind, m, n)
+    X, Y = torch.from_numpy(x[None]).to(dev), torch.from_numpy(y[None]).to(dev)
+    dist, saved = pairs.banded(X, Y, frac=(1, 10), f64=True, save=True)
+    g = torch.tensor([1.5], device=dev)
+    gx, gy = pairs.backward(X, Y, saved, g, frac=(1, 10))
+    weff = O.window_eff(m, n, 0, 1, 10)
+    v, rq, rc, _ = O.path_grad(x, y, weff, 1.5)
+    assert np.float32(v) == dist[0].item()
+    scale = max(1.0, np.abs(rq).max(), np.abs(rc).max())
+    np.testing.assert_allclose(gx.cpu().numpy()[0], rq, rtol=1e-6, atol=1e-6 * scale)
+    np.testing.assert_allclose(gy.cpu().numpy()[0], rc, rtol=1e-6, atol=1e-6 * scale)
+
+
 def test_backward_f32_forward_invariants(dev):
     """With a float32 forward the path may differ from the FP64 one at
     near-ties; any monotone path's gradient still satisfies translation
