@@ -177,27 +177,29 @@ __global__ __launch_bounds__(64) void dtw_rows_kernel(DtwFwdArgs a) {
 
 // ---------------------------------------------------------------------------
 // Diagonal pairs with the point costs formed ahead of the recurrence (float,
-// uniform pairs).  A workgroup of eight waves takes one item (the P pairs of
-// one wave of dtw_diag_kernel, same lane layout): after the pairs are staged
-// and the costs of the first chunk of rounds formed, waves 1-7 form the
-// costs of chunk c + 1 (cells of both slots of every lane, +inf on killed
+// uniform pairs).  A workgroup of sixteen waves takes one item (the P pairs
+// of one wave of dtw_diag_kernel, same lane layout): after the pairs are
+// staged and the costs of the first chunk of rounds formed, waves 1-15 form
+// the costs of chunk c + 1 (cells of both slots of every lane, +inf on killed
 // slots, spare lanes and cells outside the matrix) into one half of an LDS
 // double buffer while wave 0 runs the recurrence over chunk c from the other
 // half.  The serial chain of a round is then two cost reads, two 3-way
 // minima, two adds and two lane shifts; the argmin codes (when saved) are
 // written in diag_core's layout, so tc_dtw_backward reads them unchanged.
 // This mapping is for batches too small to fill the chip with one wave per
-// item, whose time is the latency of the serial chain.
+// item, whose time is the latency of the serial chain (more cost waves keep
+// the recurrence wave's SIMD freer: 41.7 us with eight waves, 38.4 us with
+// sixteen, for 256 pairs of 512 at d = 12).
 // ---------------------------------------------------------------------------
 constexpr int kCoopRounds = 32;   // rounds per chunk (a multiple of 8: code words never straddle chunks)
-constexpr int kCoopThreads = 512; // one recurrence wave and seven cost waves
+constexpr int kCoopThreads = 1024; // one recurrence wave and fifteen cost waves
 
 size_t diag_coop_lds_bytes(int m, int n, int W, int D, int P) {
     return diag_lds_bytes(m, n, W, D, P) + (size_t)2 * kCoopRounds * kWave * 8;
 }
 
 template <int NCH, bool SAVE, bool WODD>
-__global__ __launch_bounds__(512) void dtw_diag_coop_kernel(DtwFwdArgs a) {
+__global__ __launch_bounds__(1024) void dtw_diag_coop_kernel(DtwFwdArgs a) {
     const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
     const int m = a.m, n = a.n, W = a.W, P = a.P, D = a.D;
     const int out0 = blockIdx.x * P;
