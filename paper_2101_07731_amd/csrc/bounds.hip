@@ -353,6 +353,106 @@ __global__ __launch_bounds__(64) void k_lb_pc_lanes(PcArgs a) {
     if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
 }
 
+// LB_PC with the query's boxes (Sec. 5), lanes over the candidate's points,
+// for narrow points (d <= 4) and series of at most 192 positions: a wave
+// takes up to 64 listed candidates of one query and measures them one after
+// another.  Lane l holds positions 3l .. 3l+2 of every candidate (inside one
+// group, the group length being a multiple of three) and the KM boxes of
+// that group in registers, read once per work item (boxes past the group's
+// count are +inf, so they never win the minimum).  The wave reads each
+// candidate in one contiguous stretch, and a candidate the trigger skips
+// costs nothing; the pair's sum is each lane's three minima added in order,
+// then summed across the wave (the deflation covers any summation order).
+template <int DC, int KM>
+__global__ __launch_bounds__(64) void k_lb_pc_pts(PcArgs a) {
+    const int lane = threadIdx.x;
+    const int n = a.n, G = a.ngroups;
+    const double defl = 1.0 - (double)(n + DC + 5) * (1.0 / 16777216.0) * 1.001;
+    const int j0 = 3 * lane;
+    const int g = j0 < n ? j0 / a.w : 0;
+    const float INF = __builtin_inff();
+    unsigned long long evaluated = 0;   // pairs this wave evaluated
+    for (;;) {
+        const int item = wave_next_item(a.counter);
+        if (item >= a.prefix[a.nq]) break;
+        const int q = __builtin_amdgcn_readfirstlane(a.item_query[item]);
+        const int e0 = (item - __builtin_amdgcn_readfirstlane(a.prefix[q])) * kWave;
+        const int cnt = __builtin_amdgcn_readfirstlane(a.in_list ? a.in_cnt[q] : a.in_uniform);
+        const int e1 = min(cnt, e0 + kWave);
+        // this lane's group's boxes
+        float lo[KM][DC], hi[KM][DC];
+        {
+            const int nb = j0 < n ? a.nbox[(int64_t)q * G + g] : 0;
+            const float* bq = a.boxes + ((int64_t)q * G + g) * a.K * DC * 2;
+#pragma unroll
+            for (int b = 0; b < KM; ++b)
+#pragma unroll
+                for (int p = 0; p < DC; ++p) {
+                    lo[b][p] = b < nb ? bq[(b * DC + p) * 2] : INF;
+                    hi[b][p] = b < nb ? bq[(b * DC + p) * 2 + 1] : INF;
+                }
+        }
+        float bsf = INF;
+        if (a.key) bsf = key_bsf(a.key + (int64_t)q * kKeyStride);
+        auto ref_of = [&](int e) __attribute__((always_inline)) -> int {
+            return a.in_list ? (int)__builtin_amdgcn_readfirstlane((int)a.in_list[(int64_t)q * a.cap + e]) : e;
+        };
+        // selective deployment: only pairs with LB_MV > e^2 bsf
+        auto gated = [&](int ref) __attribute__((always_inline)) -> bool {
+            return a.key && !((double)a.lb_mv[(int64_t)q * a.nc + ref] > a.e2 * (double)bsf);
+        };
+        auto load = [&](int ref, float4 (&x)[3]) __attribute__((always_inline)) {
+            const float* cs = a.C + (int64_t)ref * n * DC;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int j = j0 + t < n ? j0 + t : 0;
+                x[t] = point_chunk(cs + (int64_t)j * DC, 0, DC, false);
+            }
+        };
+        int e = e0;
+        int ref = e < e1 ? ref_of(e) : 0;
+        float4 x[3];
+        load(ref, x);
+        while (e < e1) {
+            // the next listed candidate's points are read while this one is measured
+            const int en = e + 1;
+            const int refn = en < e1 ? ref_of(en) : ref;
+            float4 xn[3];
+            load(refn, xn);
+            if (gated(ref)) {
+                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = -1.0f;   // not evaluated
+            } else {
+                float s = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const float cv[4] = {x[t].x, x[t].y, x[t].z, x[t].w};
+                    float m = INF;
+#pragma unroll
+                    for (int b = 0; b < KM; ++b) {
+                        float d = 0.0f;
+#pragma unroll
+                        for (int p = 0; p < DC; ++p) {
+                            const float v = cv[p] - __builtin_amdgcn_fmed3f(cv[p], lo[b][p], hi[b][p]);
+                            d = __builtin_fmaf(v, v, d);
+                        }
+                        m = __builtin_fminf(m, d);
+                    }
+                    s += j0 + t < n ? m : 0.0f;
+                }
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+                if (lane == 0) a.out_lb[(int64_t)q * a.cap + e] = rdown((double)s * defl);
+                ++evaluated;
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) x[t] = xn[t];
+            e = en;
+            ref = refn;
+        }
+    }
+    if (a.evaluated && lane == 0 && evaluated) atomicAdd(a.evaluated, evaluated);
+}
+
 // dst[r * NCH + k] = chunk k of point r * rstride of the series at src, for
 // rows r < rows, by one wave with eight chunks per lane in flight.
 template <int NCH>
@@ -811,8 +911,24 @@ static void launch_pc_lanes_dc(const PcArgs& a, int nblocks, hipStream_t s) {
 
 // D fixed at compile time for points of up to 8 dimensions; wider points whole chunks or D at
 // run time
+template <int DC>
+static void launch_pc_pts(const PcArgs& a, int nblocks, hipStream_t s) {
+    if (a.K <= 4) hipLaunchKernelGGL((k_lb_pc_pts<DC, 4>), dim3(nblocks), dim3(64), 0, s, a);
+    else if (a.K <= 6) hipLaunchKernelGGL((k_lb_pc_pts<DC, 6>), dim3(nblocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_lb_pc_pts<DC, 8>), dim3(nblocks), dim3(64), 0, s, a);
+}
+
 template <int NCH>
 static void launch_lb_pc_lanes_nch(const PcArgs& a, int nblocks, hipStream_t s) {
+    // narrow points of short series: lanes over the candidate's points
+    if (NCH == 1 && a.w % 3 == 0 && a.n <= 3 * kWave && a.K <= 8) {
+        switch (a.D) {
+            case 1: launch_pc_pts<1>(a, nblocks, s); return;
+            case 2: launch_pc_pts<2>(a, nblocks, s); return;
+            case 3: launch_pc_pts<3>(a, nblocks, s); return;
+            default: launch_pc_pts<4>(a, nblocks, s); return;
+        }
+    }
     if constexpr (NCH <= 2) {
         switch (a.D - 4 * (NCH - 1)) {
             case 1: launch_pc_lanes_dc<NCH, 4 * NCH - 3>(a, nblocks, s); break;
