@@ -310,6 +310,28 @@ def test_lb_pc_narrow_points(dev, D, w):
     np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
 
 
+@pytest.mark.parametrize("K", [1, 5, 8])
+@pytest.mark.parametrize("T", [192, 193])
+def test_lb_pc_points_kernel_edges(dev, K, T):
+    """Narrow points (d = 3, w = 6) at the series length where the search
+    switches from lanes over the candidate's points (T <= 192) to lanes over
+    candidates, with box counts below, between and at the register sets
+    (K = 1, 5, 8): per element against the oracle."""
+    from paper_2101_07731_amd import search, synth
+    D = 3
+    Q, Cs = synth.cascade_knn(nq=3, nc=40, T=T, D=D, seed=80 + K)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    say("lb_pc points kernel edges", K, T)
+    lb = search.lower_bounds(ix, torch.from_numpy(Q).to(dev), kind="pc", frac=(1, 10), pc_levels=2,
+                             pc_clusters=K, pc_group=6).cpu().numpy().astype(np.float64)
+    W = O.window_eff(T, T, 0, 1, 10)
+    fl = _pc_floor(Cs)
+    ref = np.array([[O.lb_pc(q, c, W, Lv=2, K=K, w=6, floor_len=fl) for c in Cs] for q in Q])
+    assert np.all(lb <= ref * (1 + 1e-12))
+    slack = 2 * (T + D + 5) * 2.0 ** -24 * 1.01 + 1e-7
+    np.testing.assert_array_less(ref * (1 - slack) - 1e-30, lb + 1e-30)
+
+
 @pytest.mark.parametrize("case", [(8, 3, (1, 10), 2, 6, 6, 80), (16, 4, (1, 5), 3, 4, 6, 80),
                                   (33, 2, (1, 10), 2, 16, 3, 33), (5, 5, (1, 10), 2, 6, 6, 71)],
                          ids=["d8_W8_L2_K6", "d16_W16_L3_K4", "d33_W8_L2_K16_w3", "d5_m71_n80"])
