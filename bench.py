@@ -52,7 +52,7 @@ STAGES = ("prep", "lb_mv", "seed", "compact", "lb_pc_ti", "dtw", "finalize", "to
 
 EXTRAS = ("full_cascade", "cand_boxes", "cascade_setup", "knn_k10", "knn_independent", "single_query_latency",
           "batched_pairs", "dtw_loss", "long_knn", "ragged_banks", "lb_mv_streaming", "plain_gpu", "windows",
-          "trajectories")
+          "trajectories", "small_graph")
 # measured on every run: the batched and forward+backward pair rates of the metric, the plain
 # (no bounds) method on the same GPU, the other windows, and the trajectory workload on which the
 # advanced bounds prune
@@ -329,6 +329,52 @@ def extra_cascade_setup(dev, ix, Qd, T, reps=3):
     Ql = torch.from_numpy(Q).to(dev)
     for K in (4, 16):
         out["long_K%d" % K] = run_one(ixl, Ql, 40, frac=(1, 10), pc_clusters=K)
+    return out
+
+
+def extra_small_graph(dev, reps=50):
+    """The small workload (64 queries x 256 references, length 64, d = 3, W = 6), whose call is
+    bound by launches and host work: whole searches replayed from a HIP graph
+    (search.GraphedSearch) against eager calls, LB_MV and no bounds; the replays' neighbours must
+    equal the eager ones."""
+    import numpy as np
+    import torch
+    from paper_2101_07731_amd import search, synth
+    gen_kw, frac, _ = WORKLOADS["plain"]
+    Q, Cs = synth.plain_knn(**gen_kw)
+    ix = search.Index(torch.from_numpy(Cs).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    out = {"workload": WORKLOADS["plain"][2]}
+    for b in ("mv", "plain"):
+        kw = dict(frac=frac, bounds=b)
+        wsb = search.knn_workspace_bytes(ix, Qd, **kw)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        ei, ed = search.knn(ix, Qd, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            search.knn(ix, Qd, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t0) * 1e3 / reps
+        try:
+            g = search.GraphedSearch(ix, Qd, **kw)
+        except Exception as err:   # a search that cannot be captured is reported, not timed
+            out[b] = {"eager_ms": round(eager_ms, 4), "graph_error": str(err)}
+            continue
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / reps
+        gi, gd = g.replay()
+        torch.cuda.synchronize()
+        same = bool(np.array_equal(gi.cpu().numpy(), ei.cpu().numpy()) and
+                    np.array_equal(gd.cpu().numpy(), ed.cpu().numpy()))
+        out[b] = {"eager_ms": round(eager_ms, 4), "graph_ms": round(graph_ms, 4),
+                  "eager_queries_per_s": round(Qd.shape[0] / eager_ms * 1e3, 1),
+                  "graph_queries_per_s": round(Qd.shape[0] / graph_ms * 1e3, 1), "same_result": same}
     return out
 
 
@@ -611,7 +657,8 @@ def main():
         out["cascade_setup"] = extra_cascade_setup(dev, ix, Qd, T)
     for name, fn in (("batched_pairs", extra_batched_pairs), ("dtw_loss", extra_fwd_bwd),
                      ("long_knn", extra_long_knn), ("ragged_banks", extra_ragged_banks),
-                     ("lb_mv_streaming", extra_lb_mv_streaming), ("trajectories", extra_trajectories)):
+                     ("lb_mv_streaming", extra_lb_mv_streaming), ("trajectories", extra_trajectories),
+                     ("small_graph", extra_small_graph)):
         if name in extras:
             note(name)
             out[name] = fn(dev)
